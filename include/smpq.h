@@ -1,0 +1,207 @@
+/*
+ * smpq.h -- C ABI of libsmpq: the overlap topological charge density
+ *           q(x) = 1/2 tr(gamma5 D_ov)(x, x) by symmetric multi-probing, on AMD MI355X.
+ *
+ * The calls follow the paper's statement of the problem (Xiong, Zhang, Zou,
+ * arXiv:1901.02211): a gauge field on a lattice L(nx, ny, nz, nt) (section 2.1),
+ * the hopping parameter kappa of the Wilson kernel (section 1, Eq. 3), a
+ * Zolotarev rational approximation of the sign function with its spectral
+ * interval (Eq. 4), a probing scheme P(m_x, m_y, m_z, m_t, mode) (section 2.2,
+ * Eq. 15) and, as output, q(x) (Eq. 16) and Q = sum_x q(x).
+ *
+ * Conventions shared by every call
+ *  - Lattice: dims = {nx, ny, nz, nt}; site index s = x + nx*(y + ny*(z + nz*t));
+ *    periodic boundary conditions in all four directions.  V = nx*ny*nz*nt.
+ *  - Gamma basis (chiral, Euclidean, hermitian): gamma_k = [[0, -i sigma_k], [i sigma_k, 0]]
+ *    for k = x, y, z; gamma_t = [[0, 1], [1, 0]]; gamma5 = gamma_x gamma_y gamma_z gamma_t
+ *    = diag(1, 1, -1, -1).
+ *  - Wilson kernel (Eq. 3): D_W psi(x) = psi(x) - kappa sum_mu [(1 - gamma_mu) U_mu(x) psi(x + mu)
+ *    + (1 + gamma_mu) U_mu(x - mu)^dag psi(x - mu)];  H_W = gamma5 D_W;  D_ov = 1 + gamma5 eps(H_W).
+ *  - Host gauge field: complex128 U[site][mu][row][col], interleaved (re, im) doubles,
+ *    72*V doubles in all.
+ *  - Host spinors: complex128 psi[rhs][site][spin][colour], 24*V doubles per right-hand side.
+ *  - Ownership: every host buffer belongs to the caller; the library copies it in or out
+ *    inside the call and keeps no pointer to it.  Device memory belongs to the context.
+ *  - Errors: every call returns a smpq_status; negative values are errors, and
+ *    smpq_last_error() gives a message for the last failing call on that context.
+ *    Nothing throws across this boundary.  A failing call leaves the context usable.
+ *  - Threads: a context is used by one host thread at a time.  All device work of a
+ *    context runs on its stream, in order.
+ *  - device = -1 creates a host-only context: colouring, Zolotarev coefficients and
+ *    argument checks work, every call that needs the GPU returns SMPQ_EDEVICE.
+ */
+#ifndef SMPQ_H
+#define SMPQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SMPQ_MAX_POLES 32
+
+typedef struct smpq_ctx smpq_ctx;
+
+typedef enum {
+    SMPQ_OK = 0,
+    SMPQ_EINVAL = -1,    /* bad argument (null pointer, out-of-range value)        */
+    SMPQ_EDIM = -2,      /* sizes that do not fit the lattice or the scheme         */
+    SMPQ_ENOMEM = -3,    /* device or host allocation failed                        */
+    SMPQ_EDEVICE = -4,   /* HIP error, or a GPU call on a host-only context         */
+    SMPQ_ENOCONV = -5,   /* a CG solve reached max_iter                              */
+    SMPQ_ESTATE = -6,    /* call out of order (e.g. q(x) before a gauge field)      */
+    SMPQ_ENUMERIC = -7   /* NaN/Inf, non-unitary links, or a CG breakdown           */
+} smpq_status;
+
+typedef enum {
+    SMPQ_FP64 = 0,       /* every vector, link and scalar in FP64                    */
+    SMPQ_MIXED_FP32 = 1  /* D_W and the CG body in FP32; FP64 CG scalars, FP64 reliable
+                            updates of the residual, FP64 solution accumulators and
+                            FP64 contraction                                          */
+} smpq_precision;
+
+typedef struct {
+    double lam_min, lam_max;     /* Zolotarev interval used for |H_W|                  */
+    double zolo_delta;           /* max |sign(x) - eps_Z(x)| on that interval           */
+    double t_bounds_s;           /* Lanczos + Zolotarev set-up (0 if the interval was given) */
+    double t_solve_s;            /* multi-shift CG over all sources                      */
+    double t_contract_s;         /* rational assembly, contraction and copy-out          */
+    double sum_imag_q;           /* sum_x Im q(x): zero up to rounding                   */
+    double max_abs_imag_q;       /* diagnostic of the probing off-diagonal terms         */
+    int64_t n_sources;           /* right-hand sides solved                             */
+    int64_t n_batches;           /* device batches they were grouped in                 */
+    int64_t total_iters;         /* sum over sources of CG iterations                   */
+    int64_t max_iters;           /* largest CG iteration count of one source            */
+    int64_t n_reliable_updates;  /* FP64 residual replacements (mixed precision)         */
+    int64_t shift_updates;       /* sum over sources and iterations of updated shifts    */
+    /* live kernel timing (HIP events on the context stream); filled when enabled
+       with smpq_set_timing().  Bytes are the algorithmic bytes each kernel must move. */
+    double dslash_ms;            /* total duration of the Wilson stencil launches        */
+    double dslash_bytes;         /* algorithmic bytes of those launches                  */
+    int64_t dslash_launches;
+    double update_ms;            /* total duration of the fused multi-shift update       */
+    double update_bytes;
+    int64_t update_launches;
+} smpq_stats;
+
+/* Create a context for a lattice dims[4] = {nx, ny, nz, nt} on HIP device `device`
+ * (-1: host only).  kappa starts at 0.21 (section 1), the solver at FP64 with
+ * tol 1e-12, max_iter 10000 and a reliable update every 50 iterations.
+ * Errors: EINVAL (null), EDIM (an extent < 1, or V >= 2^31), EDEVICE, ENOMEM. */
+smpq_status smpq_create(const int dims[4], int device, smpq_ctx **out);
+
+/* Release the context and all its device memory.  NULL is accepted. */
+void smpq_destroy(smpq_ctx *ctx);
+
+const char *smpq_strerror(smpq_status status);
+const char *smpq_last_error(const smpq_ctx *ctx);
+
+/* Copy a gauge field (host layout above, n_doubles = 72*V) to the device, keeping an
+ * FP64 and an FP32 copy.  Rejects non-finite entries and links with
+ * max |U^dag U - 1| > 1e-10 or |det U - 1| > 1e-10 (ENUMERIC).  (section 2.1) */
+smpq_status smpq_load_gauge(smpq_ctx *ctx, const double *U, size_t n_doubles);
+
+/* Hopping parameter of the Wilson kernel, 0 < kappa < 0.25 (section 1). */
+smpq_status smpq_set_kappa(smpq_ctx *ctx, double kappa);
+
+/* Lanczos on H_W^2 = D_W^dag D_W (FP64, on the device) for `steps` steps from the
+ * SplitMix64 start vector of stream `seed` (counter i gives mix(seed + (i+1)*0x9e3779b97f4a7c15);
+ * real parts from even counters, imaginary parts from odd ones, order (site, spin, colour)).
+ * Returns the extreme Ritz values of H_W^2.  The interval of Eq. 4 is implied, not
+ * printed, by the paper.  Errors: EINVAL (steps < 2), ESTATE (no gauge field). */
+smpq_status smpq_lanczos(smpq_ctx *ctx, int steps, uint64_t seed, double *theta_min, double *theta_max);
+
+/* Zolotarev interval for |H_W|: [0.9 sqrt(theta_min), 1.02 sqrt(theta_max)] from
+ * smpq_lanczos(ctx, steps, 0, ...). */
+smpq_status smpq_estimate_bounds(smpq_ctx *ctx, int steps, double *lam_min, double *lam_max);
+
+/* Zolotarev coefficients of eps(H) ~ H (c_0 + sum_i c_i / (H^2 + q_i)) (Eq. 4) with
+ * n_poles poles (the paper uses 14) on |H| in [lam_min, lam_max], computed on the host
+ * in FP64.  Errors: EINVAL (n_poles outside 1..SMPQ_MAX_POLES, lam_min <= 0,
+ * lam_min >= lam_max). */
+smpq_status smpq_set_zolotarev(smpq_ctx *ctx, int n_poles, double lam_min, double lam_max);
+
+/* Copy out the coefficients: c[n_poles], q[n_poles] (q ascending), delta = max error of
+ * the approximation on the interval.  Any output pointer may be NULL.  ESTATE if unset. */
+smpq_status smpq_get_zolotarev(const smpq_ctx *ctx, int *n_poles, double *c0, double *c,
+                               double *q, double *delta);
+
+/* Solver settings: precision, relative residual tol per shift (a shift stops once
+ * zeta_i |r| <= tol |b|), iteration limit (ENOCONV when reached) and the interval, in
+ * iterations, of FP64 residual replacement in SMPQ_MIXED_FP32.  (section 2.1, Eqs. 6-8) */
+smpq_status smpq_set_solver(smpq_ctx *ctx, smpq_precision prec, double tol, int max_iter,
+                            int reliable_interval);
+
+/* Upper bound on the right-hand sides resident on the device at once (0: automatic,
+ * from free device memory).  Rounded down to a multiple of 12 when >= 12. */
+smpq_status smpq_set_batch(smpq_ctx *ctx, int max_rhs);
+
+/* Probing scheme with gaps r[mu] = n_mu / m_mu (section 2.2, Eqs. 15-19):
+ *   mode 0 normal:  colour = x mod r                                 (prod r classes)
+ *   mode 1 split:   colour = (x mod r, sum_mu floor(x_mu / r_mu) mod 2) (2 prod r classes;
+ *                   every n_mu / r_mu must be even)
+ *   mode 2 combine: classes x mod r and x mod r + r/2 merged            (prod r / 2 classes;
+ *                   every r_mu must be even)
+ * Labels: mode 0 = lexicographic index of (x mod r), x fastest; mode 1 = 2*that + parity;
+ * mode 2 = index of the representative whose t-offset is < r_t/2.
+ * Outputs (nullable): n_classes, n_sources = 12 * n_classes.  EDIM when r does not divide
+ * the lattice or the mode's condition fails. */
+smpq_status smpq_set_scheme(smpq_ctx *ctx, const int r[4], int mode, int *n_classes,
+                            int *n_sources);
+
+/* Point sources (section 2.1, Eq. 5): every site is its own class (V classes). */
+smpq_status smpq_set_point_scheme(smpq_ctx *ctx, int *n_classes, int *n_sources);
+
+/* Copy out the colour of every site (int32[V]).  ESTATE if no scheme is set. */
+smpq_status smpq_get_coloring(const smpq_ctx *ctx, int32_t *colour);
+
+/* out = D_W in (dagger = 0) or D_W^dag in (dagger = 1) for n_rhs spinors (host layout),
+ * in the given precision (FP32 rounds the input, links and result through float). */
+smpq_status smpq_apply_dw(smpq_ctx *ctx, const double *in, double *out, int n_rhs, int dagger,
+                          smpq_precision prec);
+
+/* out = D_ov in = in + gamma5 eps_Z(H_W) in (Eq. 3) for n_rhs spinors, through the
+ * multi-shift CG of the solver settings.  Needs a gauge field and Zolotarev coefficients. */
+smpq_status smpq_apply_dov(smpq_ctx *ctx, const double *in, double *out, int n_rhs);
+
+/* q(x) on every site from all classes of the scheme (Eq. 16): for each class S and
+ * each (alpha, a), phi = sum_{y in S} e_{y,alpha,a}, and for x in S
+ * q(x) += 1/2 [gamma5 D_ov phi](x, alpha, a).  qx[V] gets Re q, qx_imag[V] (nullable) the
+ * imaginary part (a diagnostic), Q (nullable) = sum_x qx[x].  If no Zolotarev
+ * coefficients are set, 14 poles on smpq_estimate_bounds(ctx, 300) are used.
+ * st (nullable) receives statistics. */
+smpq_status smpq_compute_qx(smpq_ctx *ctx, double *qx, double *qx_imag, double *Q,
+                            smpq_stats *st);
+
+/* As smpq_compute_qx for the listed classes only (each 0 <= class < n_classes, no
+ * duplicates); sites of other classes are set to 0 in qx and qx_imag. */
+smpq_status smpq_compute_qx_classes(smpq_ctx *ctx, const int32_t *classes, int n_classes,
+                                    double *qx, double *qx_imag, smpq_stats *st);
+
+/* Exact point-source density (Eq. 5) on n listed sites: qx[i] = q(sites[i]).  Does not
+ * change the scheme set with smpq_set_scheme. */
+smpq_status smpq_compute_qx_points(smpq_ctx *ctx, const int64_t *sites, int n, double *qx,
+                                   smpq_stats *st);
+
+/* Use `stream` (a hipStream_t) for all device work of the context; NULL restores the
+ * context's own stream.  The caller keeps ownership of the stream. */
+smpq_status smpq_set_stream(smpq_ctx *ctx, void *stream);
+
+/* Enable (1) or disable (0) per-kernel HIP-event timing of the stencil and update
+ * kernels inside the solver; results appear in smpq_stats. */
+smpq_status smpq_set_timing(smpq_ctx *ctx, int enable);
+
+/* Standalone timing of the Wilson stencil: `launches` applications of D_W in the
+ * given precision to n_rhs right-hand sides, rotating through n_sets disjoint
+ * input/output/link sets so that consecutive launches do not reuse cached data.
+ * Returns the mean duration per launch (HIP events) and the algorithmic bytes per
+ * launch (links once, every input and output spinor once). */
+smpq_status smpq_bench_dslash(smpq_ctx *ctx, smpq_precision prec, int n_rhs, int n_sets,
+                              int launches, double *ms_per_launch, double *bytes_per_launch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SMPQ_H */

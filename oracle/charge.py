@@ -36,23 +36,30 @@ def dov_apply(U, lat, kappa, zolo, b, tol, max_iter):
     return b + apply_gamma5(eb)
 
 
+def source_contribution(U, lat, kappa, zolo, colour, c, alpha, a, tol, max_iter):
+    """One probing source phi = sum_{y in S_c} e_{y,alpha,a} (Eq. 15): returns the sites S_c,
+    the values 1/2 [gamma5 D_ov phi](x, alpha, a) for x in S_c (Eq. 16) and the CG iterations."""
+    V = lat.volume
+    S = np.nonzero(colour == c)[0]
+    b = np.zeros((V, 4, 3), dtype=np.complex128)
+    b[S, alpha, a] = 1.0
+    eb, iters = eps_apply(U, lat, kappa, zolo, b, tol, max_iter)
+    out = apply_gamma5(b) + eb                           # gamma5 D_ov phi
+    return S, 0.5 * out[S, alpha, a], iters
+
+
 def qx_probing(U, lat, kappa, zolo, colour, classes, tol, max_iter, stats=None):
     """q(x) on the sites of the given classes, one source per (class, alpha, a) (Eq. 16).
 
     With the point colouring this is the exact point-source trace of Eq. 5.
     Sites outside the given classes are left at zero.
     """
-    V = lat.volume
-    q = np.zeros(V, dtype=np.complex128)
+    q = np.zeros(lat.volume, dtype=np.complex128)
     for c in classes:
-        S = np.nonzero(colour == c)[0]
         for alpha in range(4):
             for a in range(3):
-                b = np.zeros((V, 4, 3), dtype=np.complex128)
-                b[S, alpha, a] = 1.0
-                eb, iters = eps_apply(U, lat, kappa, zolo, b, tol, max_iter)
-                out = apply_gamma5(b) + eb               # gamma5 D_ov b
-                q[S] += 0.5 * out[S, alpha, a]
+                S, val, iters = source_contribution(U, lat, kappa, zolo, colour, c, alpha, a, tol, max_iter)
+                q[S] += val
                 if stats is not None:
                     stats.append(iters)
     return q

@@ -1,0 +1,270 @@
+"""ctypes marshalling for libsmpq.so: numpy arrays in, numpy arrays out.
+
+Host layouts (see include/smpq.h): gauge field complex128 [V, 4, 3, 3]
+(site, mu, row, col); spinors complex128 [n, V, 4, 3] (rhs, site, spin, colour).
+Errors raise SmpqError carrying the status and the library's message.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsmpq.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1901_02211_amd.build`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+__all__ = [
+    "SMPQ_FP64", "SMPQ_MIXED_FP32", "SmpqError", "SmpqStats", "LIB_PATH", "EXPORTS",
+    "smpq_create", "smpq_destroy", "smpq_strerror", "smpq_last_error", "smpq_load_gauge",
+    "smpq_set_kappa", "smpq_lanczos", "smpq_estimate_bounds", "smpq_set_zolotarev",
+    "smpq_get_zolotarev", "smpq_set_solver", "smpq_set_batch", "smpq_set_scheme",
+    "smpq_set_point_scheme", "smpq_get_coloring", "smpq_apply_dw", "smpq_apply_dov",
+    "smpq_compute_qx", "smpq_compute_qx_classes", "smpq_compute_qx_points", "smpq_set_stream",
+    "smpq_set_timing", "smpq_bench_dslash",
+]
+
+SMPQ_FP64 = 0
+SMPQ_MIXED_FP32 = 1
+_c_int_p = ctypes.POINTER(ctypes.c_int)
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+class SmpqStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("lam_min", "lam_max", "zolo_delta", "t_bounds_s", "t_solve_s",
+                                               "t_contract_s", "sum_imag_q", "max_abs_imag_q")] + \
+               [(n, ctypes.c_int64) for n in ("n_sources", "n_batches", "total_iters", "max_iters",
+                                              "n_reliable_updates", "shift_updates")] + \
+               [("dslash_ms", ctypes.c_double), ("dslash_bytes", ctypes.c_double), ("dslash_launches", ctypes.c_int64),
+                ("update_ms", ctypes.c_double), ("update_bytes", ctypes.c_double), ("update_launches", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_SIG = {
+    "smpq_create": (ctypes.c_int, [_c_int_p, ctypes.c_int, ctypes.POINTER(_vp)]),
+    "smpq_destroy": (None, [_vp]),
+    "smpq_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "smpq_last_error": (ctypes.c_char_p, [_vp]),
+    "smpq_load_gauge": (ctypes.c_int, [_vp, _c_double_p, ctypes.c_size_t]),
+    "smpq_set_kappa": (ctypes.c_int, [_vp, ctypes.c_double]),
+    "smpq_lanczos": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_uint64, _c_double_p, _c_double_p]),
+    "smpq_estimate_bounds": (ctypes.c_int, [_vp, ctypes.c_int, _c_double_p, _c_double_p]),
+    "smpq_set_zolotarev": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double]),
+    "smpq_get_zolotarev": (ctypes.c_int, [_vp, _c_int_p, _c_double_p, _c_double_p, _c_double_p, _c_double_p]),
+    "smpq_set_solver": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int]),
+    "smpq_set_batch": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "smpq_set_scheme": (ctypes.c_int, [_vp, _c_int_p, ctypes.c_int, _c_int_p, _c_int_p]),
+    "smpq_set_point_scheme": (ctypes.c_int, [_vp, _c_int_p, _c_int_p]),
+    "smpq_get_coloring": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32)]),
+    "smpq_apply_dw": (ctypes.c_int, [_vp, _c_double_p, _c_double_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "smpq_apply_dov": (ctypes.c_int, [_vp, _c_double_p, _c_double_p, ctypes.c_int]),
+    "smpq_compute_qx": (ctypes.c_int, [_vp, _c_double_p, _c_double_p, _c_double_p, ctypes.POINTER(SmpqStats)]),
+    "smpq_compute_qx_classes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int, _c_double_p,
+                                               _c_double_p, ctypes.POINTER(SmpqStats)]),
+    "smpq_compute_qx_points": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, _c_double_p,
+                                              ctypes.POINTER(SmpqStats)]),
+    "smpq_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "smpq_set_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "smpq_bench_dslash": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_double_p,
+                                         _c_double_p]),
+}
+EXPORTS = tuple(_SIG)
+for _name, (_res, _args) in _SIG.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class SmpqError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{_lib.smpq_strerror(status).decode()} ({status}): {message}")
+        self.status = status
+
+
+class _Ctx:
+    """Owning handle of a smpq_ctx; destroyed with the object."""
+
+    def __init__(self, ptr, dims):
+        self.ptr = ptr
+        self.dims = tuple(dims)
+        self.volume = int(np.prod(dims))
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            _lib.smpq_destroy(self.ptr)
+            self.ptr = None
+
+
+def _check(ctx, status):
+    if status != 0:
+        msg = _lib.smpq_last_error(ctx.ptr).decode() if ctx is not None else ""
+        raise SmpqError(status, msg)
+
+
+def _dp(a):
+    return a.ctypes.data_as(_c_double_p)
+
+
+def _real_view(a, shape_tail, n_expected=None):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    if a.shape[-len(shape_tail):] != tuple(shape_tail):
+        raise ValueError(f"expected trailing shape {shape_tail}, got {a.shape}")
+    return a, a.view(np.float64)
+
+
+def smpq_strerror(status):
+    return _lib.smpq_strerror(status).decode()
+
+
+def smpq_last_error(ctx):
+    return _lib.smpq_last_error(ctx.ptr).decode()
+
+
+def smpq_create(dims, device=0):
+    d = (ctypes.c_int * 4)(*[int(v) for v in dims])
+    out = _vp()
+    st = _lib.smpq_create(d, int(device), ctypes.byref(out))
+    if st != 0:
+        raise SmpqError(st, "smpq_create failed")
+    return _Ctx(out, dims)
+
+
+def smpq_destroy(ctx):
+    if ctx.ptr:
+        _lib.smpq_destroy(ctx.ptr)
+        ctx.ptr = None
+
+
+def smpq_load_gauge(ctx, U):
+    U, r = _real_view(U, (4, 3, 3))
+    _check(ctx, _lib.smpq_load_gauge(ctx.ptr, _dp(r), r.size))
+
+
+def smpq_set_kappa(ctx, kappa):
+    _check(ctx, _lib.smpq_set_kappa(ctx.ptr, float(kappa)))
+
+
+def smpq_lanczos(ctx, steps, seed=0):
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _check(ctx, _lib.smpq_lanczos(ctx.ptr, int(steps), int(seed), ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def smpq_estimate_bounds(ctx, steps=300):
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _check(ctx, _lib.smpq_estimate_bounds(ctx.ptr, int(steps), ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def smpq_set_zolotarev(ctx, n_poles, lam_min, lam_max):
+    _check(ctx, _lib.smpq_set_zolotarev(ctx.ptr, int(n_poles), float(lam_min), float(lam_max)))
+
+
+def smpq_get_zolotarev(ctx):
+    n = ctypes.c_int()
+    c0, delta = ctypes.c_double(), ctypes.c_double()
+    c = np.zeros(32)
+    q = np.zeros(32)
+    _check(ctx, _lib.smpq_get_zolotarev(ctx.ptr, ctypes.byref(n), ctypes.byref(c0), _dp(c), _dp(q),
+                                        ctypes.byref(delta)))
+    return c0.value, c[:n.value].copy(), q[:n.value].copy(), delta.value
+
+
+def smpq_set_solver(ctx, precision=SMPQ_FP64, tol=1e-12, max_iter=10000, reliable_interval=50):
+    _check(ctx, _lib.smpq_set_solver(ctx.ptr, int(precision), float(tol), int(max_iter), int(reliable_interval)))
+
+
+def smpq_set_batch(ctx, max_rhs):
+    _check(ctx, _lib.smpq_set_batch(ctx.ptr, int(max_rhs)))
+
+
+def smpq_set_scheme(ctx, r, mode=0):
+    rr = (ctypes.c_int * 4)(*[int(v) for v in r])
+    nc, ns = ctypes.c_int(), ctypes.c_int()
+    _check(ctx, _lib.smpq_set_scheme(ctx.ptr, rr, int(mode), ctypes.byref(nc), ctypes.byref(ns)))
+    return nc.value, ns.value
+
+
+def smpq_set_point_scheme(ctx):
+    nc, ns = ctypes.c_int(), ctypes.c_int()
+    _check(ctx, _lib.smpq_set_point_scheme(ctx.ptr, ctypes.byref(nc), ctypes.byref(ns)))
+    return nc.value, ns.value
+
+
+def smpq_get_coloring(ctx):
+    out = np.zeros(ctx.volume, dtype=np.int32)
+    _check(ctx, _lib.smpq_get_coloring(ctx.ptr, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return out
+
+
+def _spinors(ctx, psi):
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    if psi.ndim == 3:
+        psi = psi[None]
+    if psi.shape[1:] != (ctx.volume, 4, 3):
+        raise ValueError(f"spinors must have shape (n, {ctx.volume}, 4, 3)")
+    return psi
+
+
+def smpq_apply_dw(ctx, psi, dagger=False, precision=SMPQ_FP64):
+    psi = _spinors(ctx, psi)
+    out = np.empty_like(psi)
+    _check(ctx, _lib.smpq_apply_dw(ctx.ptr, _dp(psi.view(np.float64)), _dp(out.view(np.float64)), psi.shape[0],
+                                   int(bool(dagger)), int(precision)))
+    return out
+
+
+def smpq_apply_dov(ctx, psi):
+    psi = _spinors(ctx, psi)
+    out = np.empty_like(psi)
+    _check(ctx, _lib.smpq_apply_dov(ctx.ptr, _dp(psi.view(np.float64)), _dp(out.view(np.float64)), psi.shape[0]))
+    return out
+
+
+def smpq_compute_qx(ctx):
+    """Returns (qx, qx_imag, Q, stats dict)."""
+    qx = np.zeros(ctx.volume)
+    qi = np.zeros(ctx.volume)
+    Q = ctypes.c_double()
+    st = SmpqStats()
+    _check(ctx, _lib.smpq_compute_qx(ctx.ptr, _dp(qx), _dp(qi), ctypes.byref(Q), ctypes.byref(st)))
+    return qx, qi, Q.value, st.as_dict()
+
+
+def smpq_compute_qx_classes(ctx, classes):
+    """Returns (qx, qx_imag, stats dict) with zeros outside the listed classes."""
+    cl = np.ascontiguousarray(classes, dtype=np.int32)
+    qx = np.zeros(ctx.volume)
+    qi = np.zeros(ctx.volume)
+    st = SmpqStats()
+    _check(ctx, _lib.smpq_compute_qx_classes(ctx.ptr, cl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(cl),
+                                             _dp(qx), _dp(qi), ctypes.byref(st)))
+    return qx, qi, st.as_dict()
+
+
+def smpq_compute_qx_points(ctx, sites):
+    s = np.ascontiguousarray(sites, dtype=np.int64)
+    qx = np.zeros(len(s))
+    st = SmpqStats()
+    _check(ctx, _lib.smpq_compute_qx_points(ctx.ptr, s.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(s),
+                                            _dp(qx), ctypes.byref(st)))
+    return qx, st.as_dict()
+
+
+def smpq_set_stream(ctx, stream_handle):
+    """stream_handle: integer hipStream_t (e.g. torch.cuda.current_stream().cuda_stream) or None."""
+    _check(ctx, _lib.smpq_set_stream(ctx.ptr, _vp(stream_handle) if stream_handle else None))
+
+
+def smpq_set_timing(ctx, enable=True):
+    _check(ctx, _lib.smpq_set_timing(ctx.ptr, int(bool(enable))))
+
+
+def smpq_bench_dslash(ctx, precision, n_rhs, n_sets, launches):
+    ms, by = ctypes.c_double(), ctypes.c_double()
+    _check(ctx, _lib.smpq_bench_dslash(ctx.ptr, int(precision), int(n_rhs), int(n_sets), int(launches),
+                                       ctypes.byref(ms), ctypes.byref(by)))
+    return ms.value, by.value

@@ -1,0 +1,1009 @@
+// C ABI of libsmpq (include/smpq.h): context, gauge residency, Lanczos bounds,
+// Zolotarev set-up, probing schemes, and the batched multi-shift CG driver that turns
+// probing sources into q(x) (Xiong, Zhang, Zou, arXiv:1901.02211, sections 1-2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/smpq.h"
+#include "host_math.h"
+#include "kernels.h"
+
+using namespace smpq;
+
+namespace {
+
+struct Fail {
+    smpq_status st;
+    std::string msg;
+};
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            throw Fail{e_ == hipErrorOutOfMemory ? SMPQ_ENOMEM : SMPQ_EDEVICE,                    \
+                       std::string(#expr) + ": " + hipGetErrorString(e_)};                        \
+    } while (0)
+
+void *dev_alloc(size_t bytes) {
+    void *p = nullptr;
+    if (bytes == 0) return nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Fail{SMPQ_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+    }
+    return p;
+}
+
+struct DevMem {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(const DevMem &) = delete;
+    DevMem &operator=(const DevMem &) = delete;
+    ~DevMem() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void ensure(size_t b) {
+        if (b <= bytes) return;
+        release();
+        p = dev_alloc(b);
+        bytes = b;
+    }
+    template <class T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+// Device workspace of one batch of right-hand sides.
+struct Workspace {
+    int prec = -1, NS = 0, B = 0;
+    DevMem r, tmp, ap, p, y, x0, tmp64, ap64;
+    DevMem st_d;   // doubles of the MSState
+    DevMem st_i;   // ints of the MSState
+    DevMem st_l;   // long longs of the MSState
+    DevMem partial, list, count, slot_class, slot_comp, batch_classes, bexp;
+    MSState S{};
+};
+
+struct EventTimer {
+    std::vector<hipEvent_t> ev;
+    size_t used = 0;
+    ~EventTimer() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+    hipEvent_t next() {
+        if (used == ev.size()) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            ev.push_back(e);
+        }
+        return ev[used++];
+    }
+    // sum of elapsed times of consecutive (start, stop) pairs; requires the stream synced
+    double collect() {
+        double ms = 0.0;
+        for (size_t i = 0; i + 1 < used; i += 2) {
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+            ms += t;
+        }
+        used = 0;
+        return ms;
+    }
+};
+
+}  // namespace
+
+struct smpq_ctx {
+    int dims[4];
+    int V = 0;
+    size_t vs = 0;
+    int device = -1;
+    hipStream_t own = nullptr, stream = nullptr;
+    std::string err;
+    double kappa = 0.21;
+    bool have_gauge = false;
+    DevMem U64, U32;
+    bool have_zolo = false;
+    Zolo zolo;
+    DevMem zc, zdelta;   // device copies of c_i and q_i - q_min
+    smpq_precision prec = SMPQ_FP64;
+    double tol = 1e-12;
+    int max_iter = 10000;
+    int reliable = 50;
+    int max_rhs = 0;
+    bool have_scheme = false;
+    std::vector<int32_t> colour;
+    int n_classes = 0;
+    std::vector<int32_t> cptr, csites;
+    DevMem d_colour, d_cptr, d_csites;
+    DevMem d_pcolour, d_pptr;   // point scheme (identity) on demand
+    Workspace ws;
+    DevMem qx, qxi, lz;
+    bool timing = false;
+    EventTimer t_dslash, t_update;
+    int *h_count = nullptr;     // pinned
+    Geom geom() const { return Geom{dims[0], dims[1], dims[2], dims[3], V, vs}; }
+};
+
+namespace {
+
+void need_device(smpq_ctx *c) {
+    if (c->device < 0) throw Fail{SMPQ_EDEVICE, "host-only context (device = -1)"};
+    HIPCHK(hipSetDevice(c->device));
+}
+
+template <class F>
+smpq_status guarded(smpq_ctx *c, F &&f) {
+    if (!c) return SMPQ_EINVAL;
+    try {
+        f();
+        c->err.clear();
+        return SMPQ_OK;
+    } catch (const Fail &e) {
+        c->err = e.msg;
+        return e.st;
+    } catch (const std::exception &e) {
+        c->err = e.what();
+        return SMPQ_EINVAL;
+    }
+}
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// host spinor [rhs][site][spin][colour] complex128 <-> device [rhs][comp][site] double2
+void spinor_to_device(const smpq_ctx *c, const double *h, int n, std::vector<double> &stage) {
+    stage.assign((size_t)n * 24 * c->vs, 0.0);
+    for (int r = 0; r < n; ++r)
+        for (int s = 0; s < c->V; ++s)
+            for (int k = 0; k < 12; ++k) {
+                const double *src = h + ((size_t)r * c->V + s) * 24 + 2 * k;
+                double *dst = stage.data() + 2 * (((size_t)r * 12 + k) * c->vs + s);
+                dst[0] = src[0];
+                dst[1] = src[1];
+            }
+}
+
+void spinor_from_device(const smpq_ctx *c, const std::vector<double> &stage, int n, double *h) {
+    for (int r = 0; r < n; ++r)
+        for (int s = 0; s < c->V; ++s)
+            for (int k = 0; k < 12; ++k) {
+                const double *src = stage.data() + 2 * (((size_t)r * 12 + k) * c->vs + s);
+                double *dst = h + ((size_t)r * c->V + s) * 24 + 2 * k;
+                dst[0] = src[0];
+                dst[1] = src[1];
+            }
+}
+
+// right-hand sides per stencil block (log2): links are shared by the lanes of one site
+int lgr_for(int prec) { return prec == 0 ? 1 : 2; }
+
+size_t bytes_per_slot(const smpq_ctx *c, int prec, int NS) {
+    const size_t v64 = 12 * 16 * c->vs, v32 = 6 * 16 * c->vs;
+    if (prec == 0) return (3 + NS) * v64 + v64;
+    return (3 + NS) * v32 + 4 * v64;
+}
+
+void ensure_workspace(smpq_ctx *c, int prec, int NS, int B) {
+    Workspace &w = c->ws;
+    const Geom g = c->geom();
+    const size_t v64 = 12 * 16 * c->vs, v32 = 6 * 16 * c->vs;
+    const size_t vt = prec == 0 ? v64 : v32;
+    if (w.prec != prec || w.NS != NS || w.B < B) {
+        w.r.release(); w.tmp.release(); w.ap.release(); w.p.release(); w.y.release();
+        w.x0.release(); w.tmp64.release(); w.ap64.release();
+        w.prec = prec;
+        w.NS = NS;
+        w.B = B;
+        w.r.ensure(vt * B);
+        w.tmp.ensure(vt * B);
+        w.ap.ensure(vt * B);
+        w.p.ensure(vt * B * NS);
+        w.y.ensure(v64 * B);
+        if (prec == 1) {
+            w.x0.ensure(v64 * B);
+            w.tmp64.ensure(v64 * B);
+            w.ap64.ensure(v64 * B);
+        }
+    }
+    const size_t pstride = partial_stride(g);
+    w.st_d.ensure(sizeof(double) * ((size_t)B * (5 + 3 * NS + 3 * NS)));
+    w.st_i.ensure(sizeof(int) * ((size_t)B * (2 * NS + 4 + 2 * NS) + 16));
+    w.st_l.ensure(sizeof(long long) * (size_t)B * 3);
+    w.partial.ensure(sizeof(double) * (size_t)B * pstride);
+    w.list.ensure(sizeof(int) * B);
+    w.count.ensure(sizeof(int) * 4);
+    w.slot_class.ensure(sizeof(int) * B);
+    w.slot_comp.ensure(sizeof(int) * B);
+    w.batch_classes.ensure(sizeof(int) * (B / 12 + 1));
+    MSState &S = w.S;
+    double *d = w.st_d.as<double>();
+    S.rr = d; d += B;
+    S.bnorm = d; d += B;
+    S.alpha = d; d += B;
+    S.alpha_prev = d; d += B;
+    S.beta_prev = d; d += B;
+    S.zeta = d; d += (size_t)B * NS;
+    S.zeta_prev = d; d += (size_t)B * NS;
+    S.zeta_new = d; d += (size_t)B * NS;
+    S.upd_cy = d; d += (size_t)B * NS;
+    S.upd_zeta = d; d += (size_t)B * NS;
+    S.upd_beta = d; d += (size_t)B * NS;
+    int *ip = w.st_i.as<int>();
+    S.sh_active = ip; ip += (size_t)B * NS;
+    S.sh_iters = ip; ip += (size_t)B * NS;
+    S.done = ip; ip += B;
+    S.iters = ip; ip += B;
+    S.status = ip; ip += B;
+    S.upd_n = ip; ip += B;
+    S.upd_idx = ip; ip += (size_t)B * NS;
+    S.upd_pupd = ip; ip += (size_t)B * NS;
+    long long *lp = w.st_l.as<long long>();
+    S.cnt_entries = lp; lp += B;
+    S.cnt_pupd = lp; lp += B;
+    S.cnt_active = lp; lp += B;
+    S.partial = w.partial.as<double>();
+    S.pstride = pstride;
+    S.list = w.list.as<int>();
+    S.count = w.count.as<int>();
+    S.NS = NS;
+}
+
+int choose_batch(smpq_ctx *c, int prec, int NS, int total_slots, bool multiple_of_12) {
+    size_t freeb = 0, totalb = 0;
+    HIPCHK(hipMemGetInfo(&freeb, &totalb));
+    // memory already held by a workspace of the same shape is reusable
+    size_t held = 0;
+    if (c->ws.prec == prec && c->ws.NS == NS) held = bytes_per_slot(c, prec, NS) * c->ws.B;
+    const double budget = 0.80 * (double)(freeb + held);
+    long long B = (long long)(budget / (double)bytes_per_slot(c, prec, NS));
+    if (c->max_rhs > 0) B = std::min<long long>(B, c->max_rhs);
+    B = std::min<long long>(B, total_slots);
+    if (multiple_of_12) B = (B / 12) * 12;
+    if (B < (multiple_of_12 ? 12 : 1))
+        throw Fail{SMPQ_ENOMEM, "not enough device memory for one batch of right-hand sides"};
+    return (int)B;
+}
+
+void require_gauge_zolo(smpq_ctx *c) {
+    if (!c->have_gauge) throw Fail{SMPQ_ESTATE, "no gauge field loaded"};
+    if (!c->have_zolo) throw Fail{SMPQ_ESTATE, "no Zolotarev coefficients set"};
+}
+
+void upload_zolo(smpq_ctx *c) {
+    const int n = c->zolo.n;
+    std::vector<double> dl(n);
+    for (int i = 0; i < n; ++i) dl[i] = c->zolo.q[i] - c->zolo.q[0];
+    c->zc.ensure(sizeof(double) * n);
+    c->zdelta.ensure(sizeof(double) * n);
+    HIPCHK(hipMemcpy(c->zc.p, c->zolo.c.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->zdelta.p, dl.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+}
+
+struct BatchResult {
+    long long iters_sum = 0, iters_max = 0, n_reliable = 0, entries = 0, pupd = 0, active = 0;
+};
+
+// Multi-shift CG for the first nslots slots of the workspace, sources from src.
+// On return y[slot] = c_0 b + sum_i c_i x_i (Eq. 4 without the leading H).
+BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq_stats *st) {
+    Workspace &w = c->ws;
+    MSState S = w.S;
+    S.B = nslots;
+    S.i0 = 0;            // q ascending: the smallest shift is the base system
+    S.tol = c->tol;
+    S.c = c->zc.as<double>();
+    S.delta = c->zdelta.as<double>();
+    const int NS = S.NS;
+    const Geom g = c->geom();
+    hipStream_t s = c->stream;
+    const double s0 = c->zolo.q[0];
+    const size_t units = prec == 0 ? 12 : 6;
+    const size_t rs = units * c->vs;     // per-slot stride in storage units
+    const size_t rs64 = 12 * c->vs;
+    const void *U = prec == 0 ? c->U64.p : c->U32.p;
+    const int lgr = lgr_for(prec);
+    const int np_unit = unit_parts(prec, g), np_ds = dslash_parts(g, lgr), np_ds64 = dslash_parts(g, lgr_for(0));
+    (void)np_ds64;
+    Slots act{S.list, S.count, 0};
+
+    launch_cg_init(prec, g, src, nslots, NS, c->zolo.c0, w.r.p, w.p.p, w.y.as<double2>(),
+                   prec == 1 ? w.x0.as<double2>() : nullptr, S.partial, s);
+    launch_scalars_init(S, np_unit, s);
+    launch_compact(S, s);
+    HIPCHK(hipGetLastError());
+
+    BatchResult res;
+    const int G = 8;
+    int iter = 0;
+    for (;;) {
+        for (int gi = 0; gi < G; ++gi) {
+            if (c->timing) HIPCHK(hipEventRecord(c->t_dslash.next(), s));
+            launch_dslash(prec, false, lgr, 0, U, w.p.p, NS * rs, S.i0 * rs, w.tmp.p, rs, nullptr, 0, 0, g,
+                          c->kappa, 0.0, act, nslots, nullptr, s);
+            if (c->timing) {
+                HIPCHK(hipEventRecord(c->t_dslash.next(), s));
+                HIPCHK(hipEventRecord(c->t_dslash.next(), s));
+            }
+            launch_dslash(prec, true, lgr, 1, U, w.tmp.p, rs, 0, w.ap.p, rs, w.p.p, NS * rs, S.i0 * rs, g, c->kappa,
+                          s0, act, nslots, S.partial, s);
+            if (c->timing) HIPCHK(hipEventRecord(c->t_dslash.next(), s));
+            launch_scalars_alpha(S, np_ds, s);
+            launch_r_update(prec, g, S, w.r.p, w.ap.p, s);
+            launch_scalars_beta(S, np_unit, s);
+            if (c->timing) HIPCHK(hipEventRecord(c->t_update.next(), s));
+            launch_shift_update(prec, g, S, w.r.p, w.p.p, w.y.as<double2>(),
+                                prec == 1 ? w.x0.as<double2>() : nullptr, s);
+            if (c->timing) HIPCHK(hipEventRecord(c->t_update.next(), s));
+            launch_compact(S, s);
+            ++iter;
+            if (prec == 1 && c->reliable > 0 && iter % c->reliable == 0) {
+                launch_dslash(0, false, lgr_for(0), 0, c->U64.p, w.x0.p, rs64, 0, w.tmp64.p, rs64, nullptr, 0, 0, g, c->kappa,
+                              0.0, act, nslots, nullptr, s);
+                launch_dslash(0, true, lgr_for(0), 1, c->U64.p, w.tmp64.p, rs64, 0, w.ap64.p, rs64, w.x0.p, rs64, 0, g,
+                              c->kappa, s0, act, nslots, S.partial, s);
+                launch_reliable(prec, g, S, src, w.ap64.as<double2>(), w.r.p, s);
+                launch_scalars_rr(S, np_unit, s);
+                res.n_reliable++;
+            }
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(c->h_count, S.count, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (c->timing && st) {
+            st->dslash_ms += c->t_dslash.collect();
+            st->update_ms += c->t_update.collect();
+        }
+        if (*c->h_count == 0) break;
+        if (iter >= c->max_iter)
+            throw Fail{SMPQ_ENOCONV, "multi-shift CG did not converge within max_iter = " + std::to_string(c->max_iter)};
+    }
+    std::vector<int> status(nslots), iters(nslots);
+    std::vector<long long> ent(nslots), pup(nslots), actv(nslots);
+    HIPCHK(hipMemcpy(status.data(), S.status, sizeof(int) * nslots, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(iters.data(), S.iters, sizeof(int) * nslots, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(ent.data(), S.cnt_entries, sizeof(long long) * nslots, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(pup.data(), S.cnt_pupd, sizeof(long long) * nslots, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(actv.data(), S.cnt_active, sizeof(long long) * nslots, hipMemcpyDeviceToHost));
+    for (int k = 0; k < nslots; ++k) {
+        if (status[k] != kStatusOK) throw Fail{SMPQ_ENUMERIC, "CG breakdown: <p, A p> <= 0 or not finite"};
+        res.iters_sum += iters[k];
+        res.iters_max = std::max<long long>(res.iters_max, iters[k]);
+        res.entries += ent[k];
+        res.pupd += pup[k];
+        res.active += actv[k];
+    }
+    if (st) {
+        const double s_t = prec == 0 ? 16.0 : 8.0;     // bytes per complex spinor entry
+        const double u_t = prec == 0 ? 16.0 : 8.0;     // bytes per complex link entry
+        const double V = c->V;
+        // algorithmic bytes: D_W reads links once and each input/output spinor once; the
+        // second stencil also reads p for the "+ s0 p" term.  Per active slot-iteration.
+        st->dslash_bytes += (double)iter * 2.0 * 36.0 * u_t * V + (double)res.active * V * 12.0 * s_t * 5.0;
+        st->dslash_launches += 2LL * iter;
+        // update kernel: r read, y (FP64) read+write, x0 (FP64) read+write in mixed
+        // precision, every listed p_i read, every updated p_i written.
+        const double per_active = 12.0 * s_t + 2.0 * 192.0 + (prec == 1 ? 2.0 * 192.0 : 0.0);
+        st->update_bytes += V * ((double)res.active * per_active + (double)(res.entries + res.pupd) * 12.0 * s_t);
+        st->update_launches += iter;
+        st->n_reliable_updates += res.n_reliable;
+        st->shift_updates += res.entries;
+    }
+    return res;
+}
+
+void ensure_scheme_device(smpq_ctx *c) {
+    if (c->d_colour.p) return;
+    c->d_colour.ensure(sizeof(int) * c->V);
+    c->d_cptr.ensure(sizeof(int) * (c->n_classes + 1));
+    c->d_csites.ensure(sizeof(int) * c->V);
+    HIPCHK(hipMemcpy(c->d_colour.p, c->colour.data(), sizeof(int) * c->V, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_cptr.p, c->cptr.data(), sizeof(int) * (c->n_classes + 1), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_csites.p, c->csites.data(), sizeof(int) * c->V, hipMemcpyHostToDevice));
+}
+
+void ensure_point_device(smpq_ctx *c) {
+    if (c->d_pcolour.p) return;
+    std::vector<int> id(c->V + 1);
+    for (int i = 0; i <= c->V; ++i) id[i] = i;
+    c->d_pcolour.ensure(sizeof(int) * c->V);
+    c->d_pptr.ensure(sizeof(int) * (c->V + 1));
+    HIPCHK(hipMemcpy(c->d_pcolour.p, id.data(), sizeof(int) * c->V, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_pptr.p, id.data(), sizeof(int) * (c->V + 1), hipMemcpyHostToDevice));
+}
+
+void lanczos(smpq_ctx *c, int steps, uint64_t seed, double *tmin, double *tmax) {
+    const Geom g = c->geom();
+    const size_t v64 = 12 * 16 * c->vs;
+    c->lz.ensure(4 * v64);
+    double2 *v = c->lz.as<double2>(), *vp = v + 12 * c->vs, *w = vp + 12 * c->vs, *t = w + 12 * c->vs;
+    const int np_ds = dslash_parts(g, 0), np_unit = unit_parts(0, g);
+    DevMem part;
+    part.ensure(sizeof(double) * partial_stride(g));
+    std::vector<double> h((size_t)24 * c->V), stage;
+    for (size_t i = 0; i < h.size(); ++i) h[i] = 2.0 * splitmix64_uniform(seed, i) - 1.0;
+    double nrm = 0.0;
+    for (double x : h) nrm += x * x;
+    nrm = std::sqrt(nrm);
+    for (double &x : h) x /= nrm;
+    spinor_to_device(c, h.data(), 1, stage);
+    HIPCHK(hipMemsetAsync(c->lz.p, 0, 4 * v64, c->stream));
+    HIPCHK(hipMemcpyAsync(v, stage.data(), v64, hipMemcpyHostToDevice, c->stream));
+    std::vector<double> alpha, beta, hp(partial_stride(g));
+    Slots one{nullptr, nullptr, 1};
+    double bprev = 0.0;
+    for (int j = 0; j < steps; ++j) {
+        launch_dslash(0, false, 0, 0, c->U64.p, v, 0, 0, t, 0, nullptr, 0, 0, g, c->kappa, 0.0, one, 1, nullptr,
+                      c->stream);
+        launch_dslash(0, true, 0, 1, c->U64.p, t, 0, 0, w, 0, v, 0, 0, g, c->kappa, 0.0, one, 1, part.as<double>(),
+                      c->stream);
+        HIPCHK(hipMemcpyAsync(hp.data(), part.p, sizeof(double) * np_ds, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        double a = 0.0;
+        for (int i = 0; i < np_ds; ++i) a += hp[i];
+        alpha.push_back(a);
+        if (j == steps - 1) break;
+        launch_lanczos_update(g, w, v, vp, a, bprev, part.as<double>(), c->stream);
+        HIPCHK(hipMemcpyAsync(hp.data(), part.p, sizeof(double) * np_unit, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        double b2 = 0.0;
+        for (int i = 0; i < np_unit; ++i) b2 += hp[i];
+        const double b = std::sqrt(b2);
+        if (!(b > 0.0) || !std::isfinite(b)) break;
+        beta.push_back(b);
+        launch_scale(g, vp, w, 1.0 / b, c->stream);
+        std::swap(v, vp);
+        bprev = b;
+    }
+    HIPCHK(hipGetLastError());
+    beta.resize(alpha.size() - 1);
+    tridiag_extremes(alpha, beta, tmin, tmax);
+}
+
+void set_zolo(smpq_ctx *c, int n, double lo, double hi) {
+    if (n < 1 || n > SMPQ_MAX_POLES) throw Fail{SMPQ_EINVAL, "n_poles must be in 1..SMPQ_MAX_POLES"};
+    if (!(lo > 0.0) || !(hi > lo) || !std::isfinite(hi))
+        throw Fail{SMPQ_EINVAL, "need 0 < lam_min < lam_max"};
+    try {
+        c->zolo = zolotarev(n, lo, hi);
+    } catch (const std::exception &e) {
+        throw Fail{SMPQ_ENUMERIC, e.what()};
+    }
+    c->have_zolo = true;
+    if (c->device >= 0) upload_zolo(c);
+}
+
+void auto_zolo(smpq_ctx *c, smpq_stats *st) {
+    if (c->have_zolo) return;
+    const double t0 = now_s();
+    double tmin, tmax;
+    lanczos(c, 300, 0, &tmin, &tmax);
+    set_zolo(c, 14, 0.9 * std::sqrt(tmin), 1.02 * std::sqrt(tmax));
+    if (st) st->t_bounds_s += now_s() - t0;
+}
+
+// q(x) for the listed classes of a colouring (scheme or point), written into the
+// device arrays qx/qxi (which the caller zeroes).
+void qx_classes(smpq_ctx *c, const std::vector<int> &classes, bool point, smpq_stats *st) {
+    const int prec = c->prec == SMPQ_FP64 ? 0 : 1;
+    const int NS = c->zolo.n;
+    const int total = (int)classes.size() * 12;
+    if (total == 0) return;
+    const int B = choose_batch(c, prec, NS, total, true);
+    ensure_workspace(c, prec, NS, B);
+    Workspace &w = c->ws;
+    const int *colour = point ? c->d_pcolour.as<int>() : c->d_colour.as<int>();
+    const int *cptr = point ? c->d_pptr.as<int>() : c->d_cptr.as<int>();
+    const int *csites = point ? c->d_pcolour.as<int>() : c->d_csites.as<int>();
+    const int per = B / 12;
+    std::vector<int> sc(B), sp(B);
+    for (size_t k0 = 0; k0 < classes.size(); k0 += per) {
+        const int nc = (int)std::min<size_t>(per, classes.size() - k0);
+        int maxsize = 1;
+        for (int i = 0; i < nc; ++i) {
+            const int cl = classes[k0 + i];
+            for (int j = 0; j < 12; ++j) {
+                sc[12 * i + j] = cl;
+                sp[12 * i + j] = j;
+            }
+            maxsize = std::max(maxsize, point ? 1 : c->cptr[cl + 1] - c->cptr[cl]);
+        }
+        HIPCHK(hipMemcpyAsync(w.slot_class.p, sc.data(), sizeof(int) * 12 * nc, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(w.slot_comp.p, sp.data(), sizeof(int) * 12 * nc, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(w.batch_classes.p, classes.data() + k0, sizeof(int) * nc, hipMemcpyHostToDevice,
+                              c->stream));
+        Source src{colour, w.slot_class.as<int>(), w.slot_comp.as<int>(), nullptr};
+        const double t0 = now_s();
+        BatchResult r = run_batch(c, prec, 12 * nc, src, st);
+        const double t1 = now_s();
+        launch_contract(c->geom(), c->U64.as<double2>(), w.y.as<double2>(), c->kappa, w.batch_classes.as<int>(), nc,
+                        maxsize, cptr, csites, c->qx.as<double>(), c->qxi.as<double>(), c->stream);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (st) {
+            st->t_solve_s += t1 - t0;
+            st->t_contract_s += now_s() - t1;
+            st->n_sources += 12 * nc;
+            st->n_batches += 1;
+            st->total_iters += r.iters_sum;
+            st->max_iters = std::max<int64_t>(st->max_iters, r.iters_max);
+        }
+    }
+}
+
+void prepare_q(smpq_ctx *c, smpq_stats *st) {
+    need_device(c);
+    if (!c->have_gauge) throw Fail{SMPQ_ESTATE, "no gauge field loaded"};
+    auto_zolo(c, st);
+    c->qx.ensure(sizeof(double) * c->V);
+    c->qxi.ensure(sizeof(double) * c->V);
+    HIPCHK(hipMemsetAsync(c->qx.p, 0, sizeof(double) * c->V, c->stream));
+    HIPCHK(hipMemsetAsync(c->qxi.p, 0, sizeof(double) * c->V, c->stream));
+    if (st) {
+        st->lam_min = c->zolo.lam_min;
+        st->lam_max = c->zolo.lam_max;
+        st->zolo_delta = c->zolo.delta;
+    }
+}
+
+void finish_q(smpq_ctx *c, double *qx, double *qxi, smpq_stats *st) {
+    const double t0 = now_s();
+    std::vector<double> hi(c->V);
+    HIPCHK(hipMemcpy(qx, c->qx.p, sizeof(double) * c->V, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(hi.data(), c->qxi.p, sizeof(double) * c->V, hipMemcpyDeviceToHost));
+    if (qxi) std::memcpy(qxi, hi.data(), sizeof(double) * c->V);
+    if (st) {
+        double sum = 0.0, mx = 0.0;
+        for (double v : hi) {
+            sum += v;
+            mx = std::max(mx, std::fabs(v));
+        }
+        st->sum_imag_q = sum;
+        st->max_abs_imag_q = mx;
+        st->t_contract_s += now_s() - t0;
+    }
+}
+
+}  // namespace
+
+// =============================================================================== C ABI
+extern "C" {
+
+const char *smpq_strerror(smpq_status s) {
+    switch (s) {
+        case SMPQ_OK: return "ok";
+        case SMPQ_EINVAL: return "invalid argument";
+        case SMPQ_EDIM: return "dimension mismatch";
+        case SMPQ_ENOMEM: return "out of memory";
+        case SMPQ_EDEVICE: return "device error";
+        case SMPQ_ENOCONV: return "solver did not converge";
+        case SMPQ_ESTATE: return "call out of order";
+        case SMPQ_ENUMERIC: return "numerical error";
+    }
+    return "unknown status";
+}
+
+const char *smpq_last_error(const smpq_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+smpq_status smpq_create(const int dims[4], int device, smpq_ctx **out) {
+    if (!dims || !out) return SMPQ_EINVAL;
+    *out = nullptr;
+    long long V = 1;
+    for (int i = 0; i < 4; ++i) {
+        if (dims[i] < 1) return SMPQ_EDIM;
+        V *= dims[i];
+    }
+    if (V >= (1LL << 31) / 16) return SMPQ_EDIM;
+    smpq_ctx *c = new smpq_ctx();
+    std::memcpy(c->dims, dims, sizeof(int) * 4);
+    c->V = (int)V;
+    c->vs = (size_t)((V + 255) / 256) * 256;
+    c->device = device;
+    if (device >= 0) {
+        int n = 0;
+        if (hipGetDeviceCount(&n) != hipSuccess || device >= n) {
+            (void)hipGetLastError();
+            delete c;
+            return SMPQ_EDEVICE;
+        }
+        if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess ||
+            hipHostMalloc((void **)&c->h_count, sizeof(int) * 4) != hipSuccess) {
+            (void)hipGetLastError();
+            delete c;
+            return SMPQ_EDEVICE;
+        }
+        c->stream = c->own;
+    }
+    *out = c;
+    return SMPQ_OK;
+}
+
+void smpq_destroy(smpq_ctx *c) {
+    if (!c) return;
+    if (c->device >= 0) {
+        (void)hipSetDevice(c->device);
+        if (c->stream) (void)hipStreamSynchronize(c->stream);
+    }
+    hipStream_t own = c->own;
+    int *hc = c->h_count;
+    int dev = c->device;
+    delete c;
+    if (dev >= 0) {
+        if (hc) (void)hipHostFree(hc);
+        if (own) (void)hipStreamDestroy(own);
+    }
+}
+
+smpq_status smpq_load_gauge(smpq_ctx *c, const double *U, size_t n) {
+    return guarded(c, [&] {
+        if (!U) throw Fail{SMPQ_EINVAL, "null gauge pointer"};
+        if (n != (size_t)72 * c->V) throw Fail{SMPQ_EDIM, "gauge field must hold 72*V doubles"};
+        for (size_t i = 0; i < n; ++i)
+            if (!std::isfinite(U[i])) throw Fail{SMPQ_ENUMERIC, "non-finite gauge link entry"};
+        for (size_t l = 0; l < (size_t)4 * c->V; ++l) {
+            const double *u = U + 18 * l;
+            double err = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    double re = 0.0, im = 0.0;   // (U^dag U)_ab = sum_k conj(U_ka) U_kb
+                    for (int k = 0; k < 3; ++k) {
+                        const double ar = u[2 * (3 * k + a)], ai = u[2 * (3 * k + a) + 1];
+                        const double br = u[2 * (3 * k + b)], bi = u[2 * (3 * k + b) + 1];
+                        re += ar * br + ai * bi;
+                        im += ar * bi - ai * br;
+                    }
+                    err = std::max(err, std::hypot(re - (a == b), im));
+                }
+            // det by cofactor expansion along the first row
+            auto C = [&](int r, int k) { return std::pair<double, double>(u[2 * (3 * r + k)], u[2 * (3 * r + k) + 1]); };
+            auto mul = [](std::pair<double, double> x, std::pair<double, double> y) {
+                return std::pair<double, double>(x.first * y.first - x.second * y.second,
+                                                 x.first * y.second + x.second * y.first);
+            };
+            auto sub = [](std::pair<double, double> x, std::pair<double, double> y) {
+                return std::pair<double, double>(x.first - y.first, x.second - y.second);
+            };
+            auto m0 = sub(mul(C(1, 1), C(2, 2)), mul(C(1, 2), C(2, 1)));
+            auto m1 = sub(mul(C(1, 0), C(2, 2)), mul(C(1, 2), C(2, 0)));
+            auto m2 = sub(mul(C(1, 0), C(2, 1)), mul(C(1, 1), C(2, 0)));
+            auto det = mul(C(0, 0), m0);
+            auto t1 = mul(C(0, 1), m1), t2 = mul(C(0, 2), m2);
+            det.first += -t1.first + t2.first;
+            det.second += -t1.second + t2.second;
+            if (err > 1e-10 || std::hypot(det.first - 1.0, det.second) > 1e-10)
+                throw Fail{SMPQ_ENUMERIC, "gauge link is not in SU(3) (|U^dag U - 1| or |det U - 1| > 1e-10)"};
+        }
+        need_device(c);
+        const size_t V = c->V;
+        std::vector<double> u64(V * 72);
+        std::vector<float> u32(V * 72);
+        for (size_t s = 0; s < V; ++s)
+            for (int mu = 0; mu < 4; ++mu)
+                for (int k = 0; k < 9; ++k) {
+                    const double *src = U + ((s * 4 + mu) * 9 + k) * 2;
+                    const size_t d = ((size_t)(mu * 9 + k) * V + s) * 2;
+                    u64[d] = src[0];
+                    u64[d + 1] = src[1];
+                    u32[d] = (float)src[0];
+                    u32[d + 1] = (float)src[1];
+                }
+        c->U64.ensure(sizeof(double) * V * 72);
+        c->U32.ensure(sizeof(float) * V * 72);
+        HIPCHK(hipMemcpy(c->U64.p, u64.data(), sizeof(double) * V * 72, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(c->U32.p, u32.data(), sizeof(float) * V * 72, hipMemcpyHostToDevice));
+        c->have_gauge = true;
+    });
+}
+
+smpq_status smpq_set_kappa(smpq_ctx *c, double kappa) {
+    return guarded(c, [&] {
+        if (!(kappa > 0.0 && kappa < 0.25)) throw Fail{SMPQ_EINVAL, "kappa must be in (0, 0.25)"};
+        c->kappa = kappa;
+    });
+}
+
+smpq_status smpq_lanczos(smpq_ctx *c, int steps, uint64_t seed, double *tmin, double *tmax) {
+    return guarded(c, [&] {
+        if (steps < 2 || !tmin || !tmax) throw Fail{SMPQ_EINVAL, "need steps >= 2 and output pointers"};
+        need_device(c);
+        if (!c->have_gauge) throw Fail{SMPQ_ESTATE, "no gauge field loaded"};
+        lanczos(c, steps, seed, tmin, tmax);
+    });
+}
+
+smpq_status smpq_estimate_bounds(smpq_ctx *c, int steps, double *lo, double *hi) {
+    return guarded(c, [&] {
+        if (steps < 2 || !lo || !hi) throw Fail{SMPQ_EINVAL, "need steps >= 2 and output pointers"};
+        need_device(c);
+        if (!c->have_gauge) throw Fail{SMPQ_ESTATE, "no gauge field loaded"};
+        double tmin, tmax;
+        lanczos(c, steps, 0, &tmin, &tmax);
+        *lo = 0.9 * std::sqrt(tmin);
+        *hi = 1.02 * std::sqrt(tmax);
+    });
+}
+
+smpq_status smpq_set_zolotarev(smpq_ctx *c, int n, double lo, double hi) {
+    return guarded(c, [&] {
+        if (c->device >= 0) HIPCHK(hipSetDevice(c->device));
+        set_zolo(c, n, lo, hi);
+    });
+}
+
+smpq_status smpq_get_zolotarev(const smpq_ctx *cc, int *n, double *c0, double *cv, double *q, double *delta) {
+    smpq_ctx *c = const_cast<smpq_ctx *>(cc);
+    return guarded(c, [&] {
+        if (!c->have_zolo) throw Fail{SMPQ_ESTATE, "no Zolotarev coefficients set"};
+        if (n) *n = c->zolo.n;
+        if (c0) *c0 = c->zolo.c0;
+        if (cv) std::memcpy(cv, c->zolo.c.data(), sizeof(double) * c->zolo.n);
+        if (q) std::memcpy(q, c->zolo.q.data(), sizeof(double) * c->zolo.n);
+        if (delta) *delta = c->zolo.delta;
+    });
+}
+
+smpq_status smpq_set_solver(smpq_ctx *c, smpq_precision prec, double tol, int max_iter, int reliable) {
+    return guarded(c, [&] {
+        if (prec != SMPQ_FP64 && prec != SMPQ_MIXED_FP32) throw Fail{SMPQ_EINVAL, "unknown precision"};
+        if (!(tol > 0.0 && tol < 1.0)) throw Fail{SMPQ_EINVAL, "tol must be in (0, 1)"};
+        if (max_iter < 1) throw Fail{SMPQ_EINVAL, "max_iter must be >= 1"};
+        if (reliable < 0) throw Fail{SMPQ_EINVAL, "reliable_interval must be >= 0"};
+        c->prec = prec;
+        c->tol = tol;
+        c->max_iter = max_iter;
+        c->reliable = reliable;
+    });
+}
+
+smpq_status smpq_set_batch(smpq_ctx *c, int max_rhs) {
+    return guarded(c, [&] {
+        if (max_rhs < 0) throw Fail{SMPQ_EINVAL, "max_rhs must be >= 0"};
+        c->max_rhs = max_rhs >= 12 ? (max_rhs / 12) * 12 : max_rhs;
+    });
+}
+
+static void install_scheme(smpq_ctx *c, std::vector<int32_t> &&col, int ncls) {
+    c->colour = std::move(col);
+    c->n_classes = ncls;
+    c->cptr.assign(ncls + 1, 0);
+    for (int v : c->colour) c->cptr[v + 1]++;
+    for (int i = 0; i < ncls; ++i) c->cptr[i + 1] += c->cptr[i];
+    c->csites.assign(c->V, 0);
+    std::vector<int> fill(c->cptr.begin(), c->cptr.end() - 1);
+    for (int s = 0; s < c->V; ++s) c->csites[fill[c->colour[s]]++] = s;
+    c->have_scheme = true;
+    c->d_colour.release();
+    c->d_cptr.release();
+    c->d_csites.release();
+}
+
+smpq_status smpq_set_scheme(smpq_ctx *c, const int r[4], int mode, int *ncls, int *nsrc) {
+    return guarded(c, [&] {
+        if (!r) throw Fail{SMPQ_EINVAL, "null gap array"};
+        std::vector<int32_t> col;
+        std::string err;
+        const int n = make_colouring(c->dims, r, mode, col, err);
+        if (n < 0) throw Fail{mode < 0 || mode > 2 ? SMPQ_EINVAL : SMPQ_EDIM, err};
+        install_scheme(c, std::move(col), n);
+        if (ncls) *ncls = n;
+        if (nsrc) *nsrc = 12 * n;
+    });
+}
+
+smpq_status smpq_set_point_scheme(smpq_ctx *c, int *ncls, int *nsrc) {
+    return guarded(c, [&] {
+        std::vector<int32_t> col(c->V);
+        for (int s = 0; s < c->V; ++s) col[s] = s;
+        install_scheme(c, std::move(col), c->V);
+        if (ncls) *ncls = c->V;
+        if (nsrc) *nsrc = 12 * c->V;
+    });
+}
+
+smpq_status smpq_get_coloring(const smpq_ctx *cc, int32_t *colour) {
+    smpq_ctx *c = const_cast<smpq_ctx *>(cc);
+    return guarded(c, [&] {
+        if (!colour) throw Fail{SMPQ_EINVAL, "null output"};
+        if (!c->have_scheme) throw Fail{SMPQ_ESTATE, "no scheme set"};
+        std::memcpy(colour, c->colour.data(), sizeof(int32_t) * c->V);
+    });
+}
+
+smpq_status smpq_apply_dw(smpq_ctx *c, const double *in, double *out, int n, int dagger, smpq_precision prec) {
+    return guarded(c, [&] {
+        if (!in || !out || n < 1) throw Fail{SMPQ_EINVAL, "need input, output and n_rhs >= 1"};
+        if (prec != SMPQ_FP64 && prec != SMPQ_MIXED_FP32) throw Fail{SMPQ_EINVAL, "unknown precision"};
+        need_device(c);
+        if (!c->have_gauge) throw Fail{SMPQ_ESTATE, "no gauge field loaded"};
+        const Geom g = c->geom();
+        const size_t v64 = 12 * 16 * c->vs, v32 = 6 * 16 * c->vs;
+        std::vector<double> stage;
+        spinor_to_device(c, in, n, stage);
+        DevMem a, b, a32, b32;
+        a.ensure(v64 * n);
+        b.ensure(v64 * n);
+        HIPCHK(hipMemcpyAsync(a.p, stage.data(), v64 * n, hipMemcpyHostToDevice, c->stream));
+        Slots sl{nullptr, nullptr, n};
+        if (prec == SMPQ_FP64) {
+            launch_dslash(0, dagger != 0, lgr_for(0), 0, c->U64.p, a.p, 12 * c->vs, 0, b.p, 12 * c->vs, nullptr, 0, 0, g,
+                          c->kappa, 0.0, sl, n, nullptr, c->stream);
+        } else {
+            a32.ensure(v32 * n);
+            b32.ensure(v32 * n);
+            launch_convert(1, g, a.p, a32.p, n, c->stream);
+            launch_dslash(1, dagger != 0, lgr_for(1), 0, c->U32.p, a32.p, 6 * c->vs, 0, b32.p, 6 * c->vs, nullptr, 0, 0, g,
+                          c->kappa, 0.0, sl, n, nullptr, c->stream);
+            launch_convert(0, g, b32.p, b.p, n, c->stream);
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(stage.data(), b.p, v64 * n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        spinor_from_device(c, stage, n, out);
+    });
+}
+
+smpq_status smpq_apply_dov(smpq_ctx *c, const double *in, double *out, int n) {
+    return guarded(c, [&] {
+        if (!in || !out || n < 1) throw Fail{SMPQ_EINVAL, "need input, output and n_rhs >= 1"};
+        need_device(c);
+        require_gauge_zolo(c);
+        const int prec = c->prec == SMPQ_FP64 ? 0 : 1;
+        const int NS = c->zolo.n;
+        const Geom g = c->geom();
+        const size_t v64 = 12 * 16 * c->vs;
+        std::vector<double> stage;
+        spinor_to_device(c, in, n, stage);
+        DevMem bin, bout;
+        bin.ensure(v64 * n);
+        bout.ensure(v64 * n);
+        HIPCHK(hipMemcpyAsync(bin.p, stage.data(), v64 * n, hipMemcpyHostToDevice, c->stream));
+        const int B = choose_batch(c, prec, NS, n, false);
+        ensure_workspace(c, prec, NS, B);
+        for (int k0 = 0; k0 < n; k0 += B) {
+            const int nb = std::min(B, n - k0);
+            const double2 *bptr = bin.as<double2>() + (size_t)k0 * 12 * c->vs;
+            Source src{nullptr, nullptr, nullptr, bptr};
+            run_batch(c, prec, nb, src, nullptr);
+            // D_ov b = b + gamma5 eps b = b + D_W y   (eps b = gamma5 D_W y)
+            Slots sl{nullptr, nullptr, nb};
+            launch_dslash(0, false, lgr_for(0), 1, c->U64.p, c->ws.y.p, 12 * c->vs, 0,
+                          bout.as<double2>() + (size_t)k0 * 12 * c->vs, 12 * c->vs, bptr, 12 * c->vs, 0, g, c->kappa,
+                          1.0, sl, nb, c->ws.partial.as<double>(), c->stream);
+            HIPCHK(hipGetLastError());
+        }
+        HIPCHK(hipMemcpyAsync(stage.data(), bout.p, v64 * n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        spinor_from_device(c, stage, n, out);
+    });
+}
+
+smpq_status smpq_compute_qx(smpq_ctx *c, double *qx, double *qxi, double *Q, smpq_stats *st) {
+    return guarded(c, [&] {
+        if (!qx) throw Fail{SMPQ_EINVAL, "null output"};
+        if (!c->have_scheme) throw Fail{SMPQ_ESTATE, "no scheme set"};
+        if (st) std::memset(st, 0, sizeof(*st));
+        prepare_q(c, st);
+        ensure_scheme_device(c);
+        std::vector<int> cls(c->n_classes);
+        for (int i = 0; i < c->n_classes; ++i) cls[i] = i;
+        qx_classes(c, cls, false, st);
+        finish_q(c, qx, qxi, st);
+        if (Q) {
+            double s = 0.0;
+            for (int i = 0; i < c->V; ++i) s += qx[i];
+            *Q = s;
+        }
+    });
+}
+
+smpq_status smpq_compute_qx_classes(smpq_ctx *c, const int32_t *classes, int n, double *qx, double *qxi,
+                                    smpq_stats *st) {
+    return guarded(c, [&] {
+        if (!qx || (!classes && n > 0) || n < 0) throw Fail{SMPQ_EINVAL, "bad class list or output"};
+        if (!c->have_scheme) throw Fail{SMPQ_ESTATE, "no scheme set"};
+        std::vector<int> cls(classes, classes + n);
+        std::vector<char> seen(c->n_classes, 0);
+        for (int v : cls) {
+            if (v < 0 || v >= c->n_classes) throw Fail{SMPQ_EINVAL, "class index out of range"};
+            if (seen[v]++) throw Fail{SMPQ_EINVAL, "duplicate class index"};
+        }
+        if (st) std::memset(st, 0, sizeof(*st));
+        prepare_q(c, st);
+        ensure_scheme_device(c);
+        qx_classes(c, cls, false, st);
+        finish_q(c, qx, qxi, st);
+    });
+}
+
+smpq_status smpq_compute_qx_points(smpq_ctx *c, const int64_t *sites, int n, double *qx, smpq_stats *st) {
+    return guarded(c, [&] {
+        if ((!sites && n > 0) || !qx || n < 0) throw Fail{SMPQ_EINVAL, "bad site list or output"};
+        std::vector<int> cls(n);
+        std::vector<char> seen(c->V, 0);
+        for (int i = 0; i < n; ++i) {
+            if (sites[i] < 0 || sites[i] >= c->V) throw Fail{SMPQ_EINVAL, "site index out of range"};
+            if (seen[sites[i]]++) throw Fail{SMPQ_EINVAL, "duplicate site"};
+            cls[i] = (int)sites[i];
+        }
+        if (st) std::memset(st, 0, sizeof(*st));
+        prepare_q(c, st);
+        ensure_point_device(c);
+        qx_classes(c, cls, true, st);
+        std::vector<double> all(c->V);
+        finish_q(c, all.data(), nullptr, st);
+        for (int i = 0; i < n; ++i) qx[i] = all[sites[i]];
+    });
+}
+
+smpq_status smpq_set_stream(smpq_ctx *c, void *stream) {
+    return guarded(c, [&] {
+        need_device(c);
+        HIPCHK(hipStreamSynchronize(c->stream));
+        c->stream = stream ? static_cast<hipStream_t>(stream) : c->own;
+    });
+}
+
+smpq_status smpq_set_timing(smpq_ctx *c, int enable) {
+    return guarded(c, [&] { c->timing = enable != 0; });
+}
+
+smpq_status smpq_bench_dslash(smpq_ctx *c, smpq_precision prec, int n_rhs, int n_sets, int launches, double *ms,
+                              double *bytes) {
+    return guarded(c, [&] {
+        if (n_rhs < 1 || n_sets < 1 || launches < 1 || !ms || !bytes) throw Fail{SMPQ_EINVAL, "bad arguments"};
+        if (prec != SMPQ_FP64 && prec != SMPQ_MIXED_FP32) throw Fail{SMPQ_EINVAL, "unknown precision"};
+        need_device(c);
+        if (!c->have_gauge) throw Fail{SMPQ_ESTATE, "no gauge field loaded"};
+        const int p = prec == SMPQ_FP64 ? 0 : 1;
+        const Geom g = c->geom();
+        const size_t units = p == 0 ? 12 : 6;
+        const size_t vbytes = units * 16 * c->vs;
+        const size_t lbytes = (size_t)c->V * 72 * (p == 0 ? 8 : 4);
+        std::vector<DevMem> ins(n_sets), outs(n_sets), links(n_sets);
+        for (int k = 0; k < n_sets; ++k) {
+            ins[k].ensure(vbytes * n_rhs);
+            outs[k].ensure(vbytes * n_rhs);
+            links[k].ensure(lbytes);
+            HIPCHK(hipMemcpyAsync(links[k].p, p == 0 ? c->U64.p : c->U32.p, lbytes, hipMemcpyDeviceToDevice,
+                                  c->stream));
+            HIPCHK(hipMemsetAsync(ins[k].p, 0, vbytes * n_rhs, c->stream));
+        }
+        Slots sl{nullptr, nullptr, n_rhs};
+        auto one = [&](int i) {
+            const int k = i % n_sets;
+            launch_dslash(p, false, lgr_for(p), 0, links[k].p, ins[k].p, units * c->vs, 0, outs[k].p, units * c->vs,
+                          nullptr, 0, 0, g, c->kappa, 0.0, sl, n_rhs, nullptr, c->stream);
+        };
+        for (int i = 0; i < n_sets; ++i) one(i);   // warm-up
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, c->stream));
+        for (int i = 0; i < launches; ++i) one(i);
+        HIPCHK(hipEventRecord(e1, c->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        HIPCHK(hipGetLastError());
+        *ms = t / launches;
+        const double u = p == 0 ? 16.0 : 8.0;
+        *bytes = (double)c->V * (36.0 * u + (double)n_rhs * 24.0 * u);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+// Launch interface of the device kernels (kernels.hip) used by the C ABI (api.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace smpq {
+
+constexpr int kBlock = 256;
+
+// Geometry + storage strides.  A spinor of one right-hand side is stored as
+// components [unit][site] with unit stride `vs` (the padded volume): FP64 uses 12
+// double2 units (one complex each), FP32 uses 6 float4 units (two complexes each).
+// Links are [mu][row*3 + col][site] complex (double2 or float2).
+struct Geom {
+    int nx, ny, nz, nt, V;
+    size_t vs;
+};
+
+// Right-hand-side addressing: slot k of a launch uses offset (slot * slot_stride + extra)
+// units from the base pointer, where slot = list[k] (or k when list is null) and the
+// number of slots is *count (or n when count is null).
+struct Slots {
+    const int *list;
+    const int *count;
+    int n;
+};
+
+// Per-batch multi-shift CG state (all device pointers; one entry per slot or slot*NS).
+struct MSState {
+    int B, NS, i0;
+    double tol;
+    double *rr, *bnorm, *alpha, *alpha_prev, *beta_prev;
+    double *zeta, *zeta_prev, *zeta_new;
+    int *sh_active, *sh_iters;
+    int *done, *iters, *status;
+    int *upd_n, *upd_idx, *upd_pupd;
+    double *upd_cy, *upd_zeta, *upd_beta;
+    long long *cnt_entries, *cnt_pupd, *cnt_active;
+    const double *c, *delta;
+    double *partial;     // per-block partial sums, slot stride pstride
+    size_t pstride;
+    int *list, *count;
+};
+
+// Source of the right-hand sides: probing (class, spin-colour component) or explicit FP64 vectors.
+struct Source {
+    const int *colour;      // probing: colour of each site
+    const int *slot_class;  // probing: class of each slot
+    const int *slot_comp;   // probing: component (spin*3 + colour) of each slot
+    const double2 *b;       // explicit: FP64 vectors, slot stride 12*vs (null for probing)
+};
+
+enum { kStatusOK = 0, kStatusBreakdown = 1 };
+
+// out = in - kappa * hop(in)  [epi = 0]
+// out = in - kappa * hop(in) + sigma * aux, partial[slot][block] = Re <aux, out>  [epi = 1]
+// prec: 0 = FP64, 1 = FP32.  dag selects D_W^dag.  2^lgR right-hand sides share a block
+// (lgR <= 3); the epilogue writes dslash_parts(g, lgR) partials per slot.
+void launch_dslash(int prec, bool dag, int lgR, int epi, const void *U, const void *in, size_t in_stride,
+                   size_t in_extra, void *out, size_t out_stride, const void *aux, size_t aux_stride,
+                   size_t aux_extra, const Geom &g, double kappa, double sigma, Slots sl, int max_slots,
+                   double *partial, hipStream_t st);
+__host__ __device__ int site_blocks(const Geom &g);               // blocks of 256 sites
+int dslash_parts(const Geom &g, int lgR);       // partials per slot written by the stencil epilogue
+int unit_parts(int prec, const Geom &g);        // partials per slot written by element-wise kernels
+size_t partial_stride(const Geom &g);           // slot stride of the partial buffer (>= both)
+
+void launch_cg_init(int prec, const Geom &g, const Source &src, int nslots, int NS, double c0, void *r,
+                    void *p, double2 *y, double2 *x0, double *partial, hipStream_t st);
+void launch_scalars_init(const MSState &s, int npart, hipStream_t st);
+void launch_scalars_alpha(const MSState &s, int npart, hipStream_t st);
+void launch_r_update(int prec, const Geom &g, const MSState &s, void *r, const void *ap, hipStream_t st);
+void launch_scalars_beta(const MSState &s, int npart, hipStream_t st);
+void launch_shift_update(int prec, const Geom &g, const MSState &s, const void *r, void *p, double2 *y,
+                         double2 *x0, hipStream_t st);
+void launch_compact(const MSState &s, hipStream_t st);
+void launch_reliable(int prec, const Geom &g, const MSState &s, const Source &src, const double2 *ap64,
+                     void *r, hipStream_t st);
+void launch_scalars_rr(const MSState &s, int npart, hipStream_t st);
+
+// q(x) contraction (Eq. 16) for the classes of one batch; slot = 12*class_pos + comp.
+void launch_contract(const Geom &g, const double2 *U64, const double2 *y, double kappa, const int *batch_classes,
+                     int n_classes, int max_class_size, const int *class_ptr, const int *class_sites, double *qx,
+                     double *qxi, hipStream_t st);
+
+// Lanczos helpers (single FP64 vector); the update writes unit_parts(0, g) partials
+void launch_lanczos_update(const Geom &g, double2 *w, const double2 *v, const double2 *vprev, double alpha,
+                           double beta, double *partial, hipStream_t st);
+void launch_scale(const Geom &g, double2 *dst, const double2 *src, double f, hipStream_t st);
+// layout conversion between FP64 (double2 x 12) and FP32 (float4 x 6) spinors, n slots
+void launch_convert(int to_prec, const Geom &g, const void *src, void *dst, int nslots, hipStream_t st);
+
+}  // namespace smpq

@@ -1,0 +1,718 @@
+// Device kernels of the overlap charge-density path on gfx950 (CDNA4, wave64).
+//
+//  k_dslash        Wilson stencil D_W / D_W^dag (section 1, Eq. 3); R right-hand sides
+//                  interleaved over the lanes of a block share each link fetch; optional
+//                  epilogue "+ sigma aux" with a fused <aux, out> partial for H^2 + sigma (Eq. 4).
+//  k_cg_init ...   multi-shift CG for (D_W^dag D_W + q_i) x_i = b (Eqs. 6-8): residual
+//                  update, fused update of every active shift's search direction plus the
+//                  running rational sum y = c_0 b + sum_i c_i x_i, scalar recurrences on the
+//                  device (one wave per right-hand side), FP64 residual replacement.
+//  k_contract      q(x) += 1/2 [gamma5 D_ov phi](x, alpha, a) on the probed sites (Eq. 16).
+//
+// Reductions are two-pass and fixed-order (per-block partials, then one wave per
+// right-hand side), so every FP64 result is bitwise reproducible from run to run.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "wilson_site.h"
+
+namespace smpq {
+
+// ------------------------------------------------------------------ storage traits
+template <class T>
+struct Store;
+
+template <>
+struct Store<double> {
+    using vec = double2;
+    using link = double2;
+    static constexpr int units = 12;
+    __device__ static __forceinline__ void load(const double2 *p, size_t vs, int s, cpx<double> v[12]) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const double2 t = p[c * vs + s];
+            v[c] = {t.x, t.y};
+        }
+    }
+    __device__ static __forceinline__ void store(double2 *p, size_t vs, int s, const cpx<double> v[12]) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) p[c * vs + s] = make_double2(v[c].re, v[c].im);
+    }
+};
+
+template <>
+struct Store<float> {
+    using vec = float4;
+    using link = float2;
+    static constexpr int units = 6;
+    __device__ static __forceinline__ void load(const float4 *p, size_t vs, int s, cpx<float> v[12]) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const float4 t = p[k * vs + s];
+            v[2 * k] = {t.x, t.y};
+            v[2 * k + 1] = {t.z, t.w};
+        }
+    }
+    __device__ static __forceinline__ void store(float4 *p, size_t vs, int s, const cpx<float> v[12]) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            p[k * vs + s] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+    }
+};
+
+template <class T>
+__device__ __forceinline__ void load_link(const typename Store<T>::link *U, int V, int mu, int s, cpx<T> u[9]) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const auto t = U[(size_t)(mu * 9 + k) * V + s];
+        u[k] = {t.x, t.y};
+    }
+}
+
+// Hardware dispatches consecutive workgroups round-robin over the 8 XCDs; give each XCD
+// a contiguous range of sites so that stencil neighbours share that XCD's L2.
+__device__ __forceinline__ int xcd_swizzle(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7, xcd = b & 7, k = b >> 3;
+    return xcd * q + (xcd < r ? xcd : r) + k;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Sum of n partials in a fixed order by one wave (lane l takes l, l+64, ...).
+__device__ __forceinline__ double wave_sum_partials(const double *p, int n) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += 64) v += p[i];
+    return wave_sum(v);
+}
+
+__device__ __forceinline__ int slot_of(const Slots &sl, int k) { return sl.list ? sl.list[k] : k; }
+__device__ __forceinline__ int slot_count(const Slots &sl) { return sl.count ? *sl.count : sl.n; }
+
+// ------------------------------------------------------------------ Wilson stencil
+// One right-hand side per thread.  A block of 256 threads covers 256/R consecutive sites
+// times R right-hand sides, with the right-hand side in the low bits of the thread index:
+// the R threads of one site load the same link addresses in the same wave, so a link is
+// fetched once for R right-hand sides without holding R accumulators in registers.
+template <int MU, int SF, class T>
+__device__ __forceinline__ void hop_dir(const typename Store<T>::link *U, int V, size_t vs,
+                                        const typename Store<T>::vec *in, int s, const Nbr &nb, cpx<T> acc[12]) {
+    cpx<T> u[9], p[12], h[6], g[6];
+    load_link<T>(U, V, MU, s, u);
+    Store<T>::load(in, vs, nb.fwd[MU], p);
+    project<MU, SF>(p, h);
+    su3_mul(u, h, g);
+    accumulate<MU, SF>(acc, g);
+    load_link<T>(U, V, MU, nb.bwd[MU], u);
+    Store<T>::load(in, vs, nb.bwd[MU], p);
+    project<MU, -SF>(p, h);
+    su3_dag_mul(u, h, g);
+    accumulate<MU, -SF>(acc, g);
+}
+
+template <class T, int SF>
+__device__ __forceinline__ void hop_site(const typename Store<T>::link *U, const Geom &g,
+                                         const typename Store<T>::vec *in, int s, cpx<T> acc[12]) {
+    const Nbr nb = neighbours(s, g.nx, g.ny, g.nz, g.nt);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = {T(0), T(0)};
+    hop_dir<0, SF, T>(U, g.V, g.vs, in, s, nb, acc);
+    hop_dir<1, SF, T>(U, g.V, g.vs, in, s, nb, acc);
+    hop_dir<2, SF, T>(U, g.V, g.vs, in, s, nb, acc);
+    hop_dir<3, SF, T>(U, g.V, g.vs, in, s, nb, acc);
+}
+
+template <class T, bool DAG, int EPI>
+__global__ __launch_bounds__(kBlock) void k_dslash(const typename Store<T>::link *__restrict__ U,
+                                                   const typename Store<T>::vec *__restrict__ in, size_t in_stride,
+                                                   size_t in_extra, typename Store<T>::vec *__restrict__ out,
+                                                   size_t out_stride, const typename Store<T>::vec *__restrict__ aux,
+                                                   size_t aux_stride, size_t aux_extra, Geom g, T kappa, T sigma,
+                                                   Slots sl, int lgR, int nsb, double *__restrict__ partial,
+                                                   size_t pstride) {
+    const int R = 1 << lgR;
+    const int L = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int sb = L % nsb, rg = L / nsb;
+    const int cnt = slot_count(sl);
+    if (rg * R >= cnt) return;  // uniform over the block
+    const int rl = threadIdx.x & (R - 1);
+    const int s = sb * (kBlock >> lgR) + (threadIdx.x >> lgR);
+    const int k = rg * R + rl;
+    const int slot = k < cnt ? slot_of(sl, k) : 0;
+    double dot = 0.0;
+    if (k < cnt && s < g.V) {
+        const auto *src = in + slot * in_stride + in_extra;
+        cpx<T> acc[12];
+        hop_site<T, DAG ? -1 : 1>(U, g, src, s, acc);
+        cpx<T> v[12];
+        Store<T>::load(src, g.vs, s, v);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) v[c] = v[c] - kappa * acc[c];
+        if constexpr (EPI == 1) {
+            cpx<T> a[12];
+            Store<T>::load(aux + slot * aux_stride + aux_extra, g.vs, s, a);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                v[c] = v[c] + sigma * a[c];
+                dot += (double)a[c].re * (double)v[c].re + (double)a[c].im * (double)v[c].im;
+            }
+        }
+        Store<T>::store(out + slot * out_stride, g.vs, s, v);
+    }
+    if constexpr (EPI == 1) {
+        // lanes with equal (lane mod R) hold the same right-hand side
+        for (int off = 32; off >= R; off >>= 1) dot += __shfl_xor(dot, off);
+        __shared__ double lds[kBlock / 64][8];
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        if (lane < R) lds[w][lane] = dot;
+        __syncthreads();
+        if ((int)threadIdx.x < R) {
+            const int kk = rg * R + threadIdx.x;
+            if (kk < cnt) {
+                double t = 0.0;
+#pragma unroll
+                for (int i = 0; i < kBlock / 64; ++i) t += lds[i][threadIdx.x];
+                partial[(size_t)slot_of(sl, kk) * pstride + sb] = t;
+            }
+        }
+    }
+}
+
+__host__ __device__ int site_blocks(const Geom &g) { return (g.V + kBlock - 1) / kBlock; }
+int dslash_parts(const Geom &g, int lgR) { return (g.V + (kBlock >> lgR) - 1) / (kBlock >> lgR); }
+size_t partial_stride(const Geom &g) { return (size_t)12 * site_blocks(g); }
+
+template <class T, bool DAG, int EPI>
+static void launch_dslash_t(const void *U, const void *in, size_t in_stride, size_t in_extra, void *out,
+                            size_t out_stride, const void *aux, size_t aux_stride, size_t aux_extra, const Geom &g,
+                            double kappa, double sigma, Slots sl, int max_slots, int lgR, double *partial,
+                            hipStream_t st) {
+    using vec = typename Store<T>::vec;
+    using link = typename Store<T>::link;
+    const int R = 1 << lgR;
+    const int nsb = dslash_parts(g, lgR);
+    const int ngr = (max_slots + R - 1) / R;
+    hipLaunchKernelGGL((k_dslash<T, DAG, EPI>), dim3(nsb * ngr), dim3(kBlock), 0, st, (const link *)U,
+                       (const vec *)in, in_stride, in_extra, (vec *)out, out_stride, (const vec *)aux, aux_stride,
+                       aux_extra, g, (T)kappa, (T)sigma, sl, lgR, nsb, partial, partial_stride(g));
+}
+
+void launch_dslash(int prec, bool dag, int lgR, int epi, const void *U, const void *in, size_t in_stride,
+                   size_t in_extra, void *out, size_t out_stride, const void *aux, size_t aux_stride, size_t aux_extra,
+                   const Geom &g, double kappa, double sigma, Slots sl, int max_slots, double *partial,
+                   hipStream_t st) {
+#define SMPQ_DS(T, D, E)                                                                                          \
+    launch_dslash_t<T, D, E>(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra, g, kappa,   \
+                             sigma, sl, max_slots, lgR, partial, st)
+    if (prec == 0) {
+        if (!dag && epi == 0) SMPQ_DS(double, false, 0);
+        else if (!dag) SMPQ_DS(double, false, 1);
+        else if (epi == 0) SMPQ_DS(double, true, 0);
+        else SMPQ_DS(double, true, 1);
+    } else {
+        if (!dag && epi == 0) SMPQ_DS(float, false, 0);
+        else if (!dag) SMPQ_DS(float, false, 1);
+        else if (epi == 0) SMPQ_DS(float, true, 0);
+        else SMPQ_DS(float, true, 1);
+    }
+#undef SMPQ_DS
+}
+
+// ------------------------------------------------------------------ element-wise kernels
+// Element-wise kernels work on one storage unit per thread: a float4 (two complex
+// entries) in FP32 or a double2 (one complex entry) in FP64.  Block b of a slot covers
+// unit u = b / nsb and sites (b % nsb)*256 + [0, 256), so a wave reads 64 consecutive
+// units of one component plane.
+template <class T>
+struct Unit;
+
+template <>
+struct Unit<float> {
+    static constexpr int C = 2;
+    __device__ static __forceinline__ void load(const float4 *p, size_t vs, int u, int s, cpx<float> v[2]) {
+        const float4 t = p[u * vs + s];
+        v[0] = {t.x, t.y};
+        v[1] = {t.z, t.w};
+    }
+    __device__ static __forceinline__ void store(float4 *p, size_t vs, int u, int s, const cpx<float> v[2]) {
+        p[u * vs + s] = make_float4(v[0].re, v[0].im, v[1].re, v[1].im);
+    }
+};
+
+template <>
+struct Unit<double> {
+    static constexpr int C = 1;
+    __device__ static __forceinline__ void load(const double2 *p, size_t vs, int u, int s, cpx<double> v[1]) {
+        const double2 t = p[u * vs + s];
+        v[0] = {t.x, t.y};
+    }
+    __device__ static __forceinline__ void store(double2 *p, size_t vs, int u, int s, const cpx<double> v[1]) {
+        p[u * vs + s] = make_double2(v[0].re, v[0].im);
+    }
+};
+
+// FP64 complex entry c of an FP64 spinor (double2 planes)
+__device__ __forceinline__ cpx<double> ld64(const double2 *p, size_t vs, int c, int s) {
+    const double2 t = p[c * vs + s];
+    return {t.x, t.y};
+}
+__device__ __forceinline__ void st64(double2 *p, size_t vs, int c, int s, cpx<double> v) {
+    p[c * vs + s] = make_double2(v.re, v.im);
+}
+
+__device__ __forceinline__ void block_partial(double v, double *partial, size_t idx) {
+    __shared__ double lds[kBlock / 64];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int i = 0; i < kBlock / 64; ++i) t += lds[i];
+        partial[idx] = t;
+    }
+}
+
+// Entry c of the source of a slot at site s.
+__device__ __forceinline__ cpx<double> source_entry(const Source &src, int slot, int c, int s, size_t vs) {
+    if (src.b) return ld64(src.b + (size_t)slot * 12 * vs, vs, c, s);
+    const bool on = (src.colour[s] == src.slot_class[slot]) && (c == src.slot_comp[slot]);
+    return {on ? 1.0 : 0.0, 0.0};
+}
+
+int unit_parts(int prec, const Geom &g) { return (prec == 0 ? 12 : 6) * site_blocks(g); }
+
+// r = b, p_i = b for every shift, y = c0 b, x0 = 0; partial = |b|^2 per block.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_cg_init(Geom g, Source src, int NS, double c0,
+                                                    typename Store<T>::vec *r, typename Store<T>::vec *p, double2 *y,
+                                                    double2 *x0, double *partial, size_t pstride) {
+    constexpr int C = Unit<T>::C;
+    const int slot = blockIdx.y;
+    const int nsb = site_blocks(g);
+    const int u = blockIdx.x / nsb;
+    const int s = (blockIdx.x % nsb) * kBlock + threadIdx.x;
+    const size_t rs = Store<T>::units * g.vs;
+    double nrm = 0.0;
+    if (s < g.V) {
+        cpx<T> bt[C];
+        double2 *ys = y + (size_t)slot * 12 * g.vs;
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const int c = u * C + i;
+            const cpx<double> b = source_entry(src, slot, c, s, g.vs);
+            bt[i] = {(T)b.re, (T)b.im};
+            nrm += (double)bt[i].re * bt[i].re + (double)bt[i].im * bt[i].im;
+            st64(ys, g.vs, c, s, c0 * b);
+            if (x0) st64(x0 + (size_t)slot * 12 * g.vs, g.vs, c, s, {0.0, 0.0});
+        }
+        Unit<T>::store(r + slot * rs, g.vs, u, s, bt);
+        for (int i = 0; i < NS; ++i) Unit<T>::store(p + ((size_t)slot * NS + i) * rs, g.vs, u, s, bt);
+    }
+    block_partial(nrm, partial, (size_t)slot * pstride + blockIdx.x);
+}
+
+void launch_cg_init(int prec, const Geom &g, const Source &src, int nslots, int NS, double c0, void *r, void *p,
+                    double2 *y, double2 *x0, double *partial, hipStream_t st) {
+    dim3 grid(unit_parts(prec, g), nslots);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_cg_init<double>, grid, dim3(kBlock), 0, st, g, src, NS, c0, (double2 *)r, (double2 *)p, y,
+                           x0, partial, partial_stride(g));
+    else
+        hipLaunchKernelGGL(k_cg_init<float>, grid, dim3(kBlock), 0, st, g, src, NS, c0, (float4 *)r, (float4 *)p, y,
+                           x0, partial, partial_stride(g));
+}
+
+// ------------------------------------------------------------------ CG scalars (one wave per slot)
+__global__ void k_scalars_init(MSState S, int npart) {
+    const int slot = blockIdx.x;
+    const double rr = wave_sum_partials(S.partial + (size_t)slot * S.pstride, npart);
+    if (threadIdx.x != 0) return;
+    S.rr[slot] = rr;
+    S.bnorm[slot] = sqrt(rr);
+    S.alpha_prev[slot] = 1.0;
+    S.beta_prev[slot] = 0.0;
+    S.alpha[slot] = 0.0;
+    for (int i = 0; i < S.NS; ++i) {
+        const int k = slot * S.NS + i;
+        S.zeta[k] = 1.0;
+        S.zeta_prev[k] = 1.0;
+        S.zeta_new[k] = 1.0;
+        S.sh_active[k] = rr > 0.0;
+        S.sh_iters[k] = 0;
+    }
+    S.done[slot] = !(rr > 0.0);
+    S.iters[slot] = 0;
+    S.status[slot] = kStatusOK;
+    S.upd_n[slot] = 0;
+    S.cnt_entries[slot] = 0;
+    S.cnt_pupd[slot] = 0;
+    S.cnt_active[slot] = 0;
+}
+
+void launch_scalars_init(const MSState &s, int npart, hipStream_t st) {
+    hipLaunchKernelGGL(k_scalars_init, dim3(s.B), dim3(64), 0, st, s, npart);
+}
+
+// alpha_k = |r_k|^2 / <p_k, A p_k>; for each active shift the new zeta.
+__global__ void k_scalars_alpha(MSState S, int npart) {
+    if ((int)blockIdx.x >= *S.count) return;
+    const int slot = S.list[blockIdx.x];
+    const double pap = wave_sum_partials(S.partial + (size_t)slot * S.pstride, npart);
+    if (threadIdx.x != 0) return;
+    if (!(pap > 0.0) || !isfinite(pap)) {
+        S.status[slot] = kStatusBreakdown;
+        S.alpha[slot] = 0.0;
+        return;
+    }
+    const double a = S.rr[slot] / pap;
+    const double ap = S.alpha_prev[slot], bp = S.beta_prev[slot];
+    S.alpha[slot] = a;
+    for (int i = 0; i < S.NS; ++i) {
+        const int k = slot * S.NS + i;
+        if (!S.sh_active[k]) continue;
+        const double z = S.zeta[k], zp = S.zeta_prev[k];
+        S.zeta_new[k] = z * zp * ap / (a * bp * (zp - z) + zp * ap * (1.0 + S.delta[i] * a));
+    }
+}
+
+void launch_scalars_alpha(const MSState &s, int npart, hipStream_t st) {
+    hipLaunchKernelGGL(k_scalars_alpha, dim3(s.B), dim3(64), 0, st, s, npart);
+}
+
+// r -= alpha A p ; partial |r|^2
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_r_update(Geom g, MSState S, typename Store<T>::vec *r,
+                                                     const typename Store<T>::vec *ap) {
+    constexpr int C = Unit<T>::C;
+    if ((int)blockIdx.y >= *S.count) return;
+    const int slot = S.list[blockIdx.y];
+    const int nsb = site_blocks(g);
+    const int u = blockIdx.x / nsb;
+    const int s = (blockIdx.x % nsb) * kBlock + threadIdx.x;
+    const size_t rs = Store<T>::units * g.vs;
+    double nrm = 0.0;
+    if (s < g.V && S.status[slot] == kStatusOK) {
+        const T a = (T)S.alpha[slot];
+        cpx<T> rv[C], av[C];
+        Unit<T>::load(r + slot * rs, g.vs, u, s, rv);
+        Unit<T>::load(ap + slot * rs, g.vs, u, s, av);
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            rv[i] = rv[i] - a * av[i];
+            nrm += (double)rv[i].re * rv[i].re + (double)rv[i].im * rv[i].im;
+        }
+        Unit<T>::store(r + slot * rs, g.vs, u, s, rv);
+    }
+    block_partial(nrm, S.partial, (size_t)slot * S.pstride + blockIdx.x);
+}
+
+void launch_r_update(int prec, const Geom &g, const MSState &s, void *r, const void *ap, hipStream_t st) {
+    dim3 grid(unit_parts(prec, g), s.B);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_r_update<double>, grid, dim3(kBlock), 0, st, g, s, (double2 *)r, (const double2 *)ap);
+    else
+        hipLaunchKernelGGL(k_r_update<float>, grid, dim3(kBlock), 0, st, g, s, (float4 *)r, (const float4 *)ap);
+}
+
+// beta_k = |r_{k+1}|^2/|r_k|^2; per active shift: alpha^i, beta^i, convergence
+// (zeta^i_{k+1} |r_{k+1}| <= tol |b|); build this iteration's update list.  The base
+// shift's direction keeps being updated while any shift of the slot is active.
+__global__ void k_scalars_beta(MSState S, int npart) {
+    if ((int)blockIdx.x >= *S.count) return;
+    const int slot = S.list[blockIdx.x];
+    const double rrn = wave_sum_partials(S.partial + (size_t)slot * S.pstride, npart);
+    if (threadIdx.x != 0) return;
+    if (S.status[slot] != kStatusOK) {
+        S.done[slot] = 1;
+        S.upd_n[slot] = 0;
+        return;
+    }
+    const double a = S.alpha[slot];
+    const double b = rrn / S.rr[slot];
+    const double rn = sqrt(rrn);
+    const double lim = S.tol * S.bnorm[slot];
+    const int it = S.iters[slot];
+    int n = 0, still = 0, npupd = 0;
+    for (int i = 0; i < S.NS; ++i) {
+        const int k = slot * S.NS + i;
+        const int u = slot * S.NS + n;
+        if (S.sh_active[k]) {
+            const double z = S.zeta[k], zn = S.zeta_new[k];
+            const double ratio = zn / z;
+            const bool conv = zn * rn <= lim;
+            S.upd_idx[u] = i;
+            S.upd_cy[u] = S.c[i] * a * ratio;
+            S.upd_zeta[u] = zn;
+            S.upd_beta[u] = b * ratio * ratio;
+            S.upd_pupd[u] = (!conv || i == S.i0) ? 1 : 0;
+            ++n;
+            if (conv) {
+                S.sh_active[k] = 0;
+                S.sh_iters[k] = it + 1;
+            } else {
+                ++still;
+            }
+            S.zeta_prev[k] = z;
+            S.zeta[k] = zn;
+        } else if (i == S.i0) {
+            S.upd_idx[u] = i;
+            S.upd_cy[u] = 0.0;
+            S.upd_zeta[u] = 1.0;
+            S.upd_beta[u] = b;
+            S.upd_pupd[u] = 1;
+            ++n;
+        }
+    }
+    if (still == 0) {  // slot finished: no direction needs updating any more
+        for (int e = 0; e < n; ++e) S.upd_pupd[slot * S.NS + e] = 0;
+        S.done[slot] = 1;
+    }
+    for (int e = 0; e < n; ++e) npupd += S.upd_pupd[slot * S.NS + e];
+    S.upd_n[slot] = n;
+    S.cnt_entries[slot] += n;
+    S.cnt_pupd[slot] += npupd;
+    S.cnt_active[slot] += 1;
+    S.alpha_prev[slot] = a;
+    S.beta_prev[slot] = b;
+    S.rr[slot] = rrn;
+    S.iters[slot] = it + 1;
+}
+
+void launch_scalars_beta(const MSState &s, int npart, hipStream_t st) {
+    hipLaunchKernelGGL(k_scalars_beta, dim3(s.B), dim3(64), 0, st, s, npart);
+}
+
+// For every entry of the slot's update list: y += c_i alpha^i p_i (old p_i), then
+// p_i = zeta^i r + beta^i p_i.  x0 += alpha p_base (mixed precision only).
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_shift_update(Geom g, MSState S, const typename Store<T>::vec *r,
+                                                         typename Store<T>::vec *p, double2 *y, double2 *x0) {
+    constexpr int C = Unit<T>::C;
+    if ((int)blockIdx.y >= *S.count) return;
+    const int slot = S.list[blockIdx.y];
+    const int nsb = site_blocks(g);
+    const int u = blockIdx.x / nsb;
+    const int s = (blockIdx.x % nsb) * kBlock + threadIdx.x;
+    if (s >= g.V) return;
+    const int n = S.upd_n[slot];
+    if (n == 0) return;
+    const size_t rs = Store<T>::units * g.vs;
+    double2 *ys = y + (size_t)slot * 12 * g.vs;
+    cpx<T> rv[C];
+    Unit<T>::load(r + slot * rs, g.vs, u, s, rv);
+    cpx<double> yv[C];
+#pragma unroll
+    for (int i = 0; i < C; ++i) yv[i] = ld64(ys, g.vs, u * C + i, s);
+#pragma unroll 1
+    for (int e = 0; e < n; ++e) {
+        const int k = slot * S.NS + e;
+        const int i = S.upd_idx[k];
+        const double cy = S.upd_cy[k];
+        typename Store<T>::vec *pp = p + ((size_t)slot * S.NS + i) * rs;
+        cpx<T> pv[C];
+        Unit<T>::load(pp, g.vs, u, s, pv);
+        if (cy != 0.0) {
+#pragma unroll
+            for (int j = 0; j < C; ++j) yv[j] = yv[j] + cy * cpx<double>{(double)pv[j].re, (double)pv[j].im};
+            if (x0 && i == S.i0) {
+                const double a = S.alpha[slot];
+                double2 *xs = x0 + (size_t)slot * 12 * g.vs;
+#pragma unroll
+                for (int j = 0; j < C; ++j)
+                    st64(xs, g.vs, u * C + j, s,
+                         ld64(xs, g.vs, u * C + j, s) + a * cpx<double>{(double)pv[j].re, (double)pv[j].im});
+            }
+        }
+        if (S.upd_pupd[k]) {
+            const T zn = (T)S.upd_zeta[k], bi = (T)S.upd_beta[k];
+#pragma unroll
+            for (int j = 0; j < C; ++j) pv[j] = zn * rv[j] + bi * pv[j];
+            Unit<T>::store(pp, g.vs, u, s, pv);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < C; ++i) st64(ys, g.vs, u * C + i, s, yv[i]);
+}
+
+void launch_shift_update(int prec, const Geom &g, const MSState &s, const void *r, void *p, double2 *y, double2 *x0,
+                         hipStream_t st) {
+    dim3 grid(unit_parts(prec, g), s.B);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_shift_update<double>, grid, dim3(kBlock), 0, st, g, s, (const double2 *)r, (double2 *)p,
+                           y, x0);
+    else
+        hipLaunchKernelGGL(k_shift_update<float>, grid, dim3(kBlock), 0, st, g, s, (const float4 *)r, (float4 *)p, y,
+                           x0);
+}
+
+// Ordered list of the slots still iterating.
+__global__ void k_compact(MSState S) {
+    if (threadIdx.x != 0) return;
+    int n = 0;
+    for (int slot = 0; slot < S.B; ++slot)
+        if (!S.done[slot]) S.list[n++] = slot;
+    *S.count = n;
+}
+
+void launch_compact(const MSState &s, hipStream_t st) { hipLaunchKernelGGL(k_compact, dim3(1), dim3(64), 0, st, s); }
+
+// Residual replacement: r = b - (H^2 + s) x0 evaluated in FP64 (ap64 holds (H^2 + s) x0),
+// stored in the iteration precision; partial |r|^2 of the stored values.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_reliable(Geom g, MSState S, Source src, const double2 *ap64,
+                                                     typename Store<T>::vec *r) {
+    constexpr int C = Unit<T>::C;
+    if ((int)blockIdx.y >= *S.count) return;
+    const int slot = S.list[blockIdx.y];
+    const int nsb = site_blocks(g);
+    const int u = blockIdx.x / nsb;
+    const int s = (blockIdx.x % nsb) * kBlock + threadIdx.x;
+    const size_t rs = Store<T>::units * g.vs;
+    double nrm = 0.0;
+    if (s < g.V) {
+        cpx<T> rv[C];
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const int c = u * C + i;
+            const cpx<double> d = source_entry(src, slot, c, s, g.vs) - ld64(ap64 + (size_t)slot * 12 * g.vs, g.vs, c, s);
+            rv[i] = {(T)d.re, (T)d.im};
+            nrm += (double)rv[i].re * rv[i].re + (double)rv[i].im * rv[i].im;
+        }
+        Unit<T>::store(r + slot * rs, g.vs, u, s, rv);
+    }
+    block_partial(nrm, S.partial, (size_t)slot * S.pstride + blockIdx.x);
+}
+
+void launch_reliable(int prec, const Geom &g, const MSState &s, const Source &src, const double2 *ap64, void *r,
+                     hipStream_t st) {
+    dim3 grid(unit_parts(prec, g), s.B);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_reliable<double>, grid, dim3(kBlock), 0, st, g, s, src, ap64, (double2 *)r);
+    else
+        hipLaunchKernelGGL(k_reliable<float>, grid, dim3(kBlock), 0, st, g, s, src, ap64, (float4 *)r);
+}
+
+__global__ void k_scalars_rr(MSState S, int npart) {
+    if ((int)blockIdx.x >= *S.count) return;
+    const int slot = S.list[blockIdx.x];
+    const double rr = wave_sum_partials(S.partial + (size_t)slot * S.pstride, npart);
+    if (threadIdx.x == 0) S.rr[slot] = rr;
+}
+
+void launch_scalars_rr(const MSState &s, int npart, hipStream_t st) {
+    hipLaunchKernelGGL(k_scalars_rr, dim3(s.B), dim3(64), 0, st, s, npart);
+}
+
+// ------------------------------------------------------------------ contraction (Eq. 16)
+// For each probed site x of class position ci and each component j (slot 12 ci + j):
+//   q(x)  += 1/2 gamma5_jj (1 + Re[D_W y_slot](x, j)),   qi(x) += 1/2 gamma5_jj Im[D_W y_slot](x, j),
+// since gamma5 D_ov phi = gamma5 (phi + D_W y) with eps phi = gamma5 D_W y.
+__global__ __launch_bounds__(kBlock) void k_contract(Geom g, const double2 *U64, const double2 *y, double kappa,
+                                                     const int *batch_classes, const int *class_ptr,
+                                                     const int *class_sites, double *qx, double *qxi) {
+    const int ci = blockIdx.y;
+    const int cls = batch_classes[ci];
+    const int beg = class_ptr[cls], end = class_ptr[cls + 1];
+    const int k = beg + blockIdx.x * kBlock + threadIdx.x;
+    if (k >= end) return;
+    const int x = class_sites[k];
+    double q = 0.0, qi = 0.0;
+#pragma unroll 1
+    for (int j = 0; j < 12; ++j) {
+        const double2 *yv = y + (size_t)(12 * ci + j) * 12 * g.vs;
+        cpx<double> acc[12];
+        hop_site<double, 1>(U64, g, yv, x, acc);
+        const cpx<double> self = ld64(yv, g.vs, j, x);
+        const double dre = self.re - kappa * acc[j].re;
+        const double dim = self.im - kappa * acc[j].im;
+        const double g5 = (j < 6) ? 0.5 : -0.5;
+        q += g5 * (1.0 + dre);
+        qi += g5 * dim;
+    }
+    qx[x] = q;
+    qxi[x] = qi;
+}
+
+void launch_contract(const Geom &g, const double2 *U64, const double2 *y, double kappa, const int *batch_classes,
+                     int n_classes, int max_class_size, const int *class_ptr, const int *class_sites, double *qx,
+                     double *qxi, hipStream_t st) {
+    dim3 grid((max_class_size + kBlock - 1) / kBlock, n_classes);
+    hipLaunchKernelGGL(k_contract, grid, dim3(kBlock), 0, st, g, U64, y, kappa, batch_classes, class_ptr,
+                       class_sites, qx, qxi);
+}
+
+// ------------------------------------------------------------------ Lanczos helpers (FP64, one vector)
+__global__ __launch_bounds__(kBlock) void k_lanczos_update(Geom g, double2 *w, const double2 *v, const double2 *vprev,
+                                                           double alpha, double beta, double *partial) {
+    const int nsb = site_blocks(g);
+    const int c = blockIdx.x / nsb;
+    const int s = (blockIdx.x % nsb) * kBlock + threadIdx.x;
+    double nrm = 0.0;
+    if (s < g.V) {
+        const size_t i = c * g.vs + s;
+        double2 t = w[i];
+        const double2 a = v[i], b = vprev[i];
+        t.x -= alpha * a.x + beta * b.x;
+        t.y -= alpha * a.y + beta * b.y;
+        w[i] = t;
+        nrm = t.x * t.x + t.y * t.y;
+    }
+    block_partial(nrm, partial, blockIdx.x);
+}
+
+void launch_lanczos_update(const Geom &g, double2 *w, const double2 *v, const double2 *vprev, double alpha,
+                           double beta, double *partial, hipStream_t st) {
+    hipLaunchKernelGGL(k_lanczos_update, dim3(unit_parts(0, g)), dim3(kBlock), 0, st, g, w, v, vprev, alpha, beta,
+                       partial);
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale(Geom g, double2 *dst, const double2 *src, double f) {
+    const int nsb = site_blocks(g);
+    const int c = blockIdx.x / nsb;
+    const int s = (blockIdx.x % nsb) * kBlock + threadIdx.x;
+    if (s >= g.V) return;
+    const double2 t = src[c * g.vs + s];
+    dst[c * g.vs + s] = make_double2(f * t.x, f * t.y);
+}
+
+void launch_scale(const Geom &g, double2 *dst, const double2 *src, double f, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale, dim3(unit_parts(0, g)), dim3(kBlock), 0, st, g, dst, src, f);
+}
+
+// ------------------------------------------------------------------ precision conversion
+__global__ __launch_bounds__(kBlock) void k_to_f32(Geom g, const double2 *src, float4 *dst) {
+    const int slot = blockIdx.y;
+    const int nsb = site_blocks(g);
+    const int u = blockIdx.x / nsb;
+    const int s = (blockIdx.x % nsb) * kBlock + threadIdx.x;
+    if (s >= g.V) return;
+    const double2 *sp = src + (size_t)slot * 12 * g.vs;
+    const double2 a = sp[(2 * u) * g.vs + s], b = sp[(2 * u + 1) * g.vs + s];
+    dst[(size_t)slot * 6 * g.vs + u * g.vs + s] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+}
+
+__global__ __launch_bounds__(kBlock) void k_to_f64(Geom g, const float4 *src, double2 *dst) {
+    const int slot = blockIdx.y;
+    const int nsb = site_blocks(g);
+    const int u = blockIdx.x / nsb;
+    const int s = (blockIdx.x % nsb) * kBlock + threadIdx.x;
+    if (s >= g.V) return;
+    const float4 t = src[(size_t)slot * 6 * g.vs + u * g.vs + s];
+    double2 *dp = dst + (size_t)slot * 12 * g.vs;
+    dp[(2 * u) * g.vs + s] = make_double2(t.x, t.y);
+    dp[(2 * u + 1) * g.vs + s] = make_double2(t.z, t.w);
+}
+
+void launch_convert(int to_prec, const Geom &g, const void *src, void *dst, int nslots, hipStream_t st) {
+    dim3 grid(unit_parts(1, g), nslots);
+    if (to_prec == 1)
+        hipLaunchKernelGGL(k_to_f32, grid, dim3(kBlock), 0, st, g, (const double2 *)src, (float4 *)dst);
+    else
+        hipLaunchKernelGGL(k_to_f64, grid, dim3(kBlock), 0, st, g, (const float4 *)src, (double2 *)dst);
+}
+
+}  // namespace smpq

@@ -1,0 +1,109 @@
+"""Host-side checks of libsmpq (no GPU): exported symbols, host-only context, colourings,
+Zolotarev coefficients and argument errors, against the oracle and the paper's tables."""
+import re
+
+import numpy as np
+import pytest
+
+import paper_1901_02211_amd as smpq
+from conftest import ROOT, load_table
+from oracle.lattice import Lattice
+from oracle.probing import colouring, gaps_from_m
+from oracle.zolotarev import zolotarev
+
+
+def _declared():
+    src = open(f"{ROOT}/include/smpq.h").read()
+    return sorted(set(re.findall(r"\b(smpq_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    import ctypes
+    lib = ctypes.CDLL(smpq.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(smpq.EXPORTS)
+
+
+def test_host_only_context_colourings_match_oracle():
+    for dims, r, mode in [((4, 4, 4, 8), 2, 0), ((4, 4, 4, 8), 2, 1), ((4, 4, 4, 8), 2, 2),
+                          ((6, 4, 4, 6), 2, 0), ((12, 12, 12, 12), 3, 0), ((8, 8, 8, 8), 4, 2)]:
+        c = smpq.smpq_create(dims, -1)
+        nc, ns = smpq.smpq_set_scheme(c, (r,) * 4, mode)
+        col, ncls = colouring(Lattice(dims), (r,) * 4, mode)
+        assert nc == ncls and ns == 12 * ncls
+        assert np.array_equal(smpq.smpq_get_coloring(c), col)
+
+
+@pytest.mark.parametrize("row", [r for r in load_table("table2_source_counts.txt") if r[0] <= 16])
+def test_table2_counts_from_library(row):
+    n, m, mode, nsmp, _ = row
+    c = smpq.smpq_create((n,) * 4, -1)
+    r = gaps_from_m((n,) * 4, (m,) * 4)
+    assert smpq.smpq_set_scheme(c, r, mode)[1] == nsmp
+
+
+ZOLO_CASES = [(14, 0.13, 2.62), (14, 0.05, 2.7), (14, 0.15, 2.7), (6, 0.3, 1.0), (20, 0.02, 3.0)] + \
+    [(n, lo, 2.7) for n in (4, 14, 24) for lo in np.linspace(0.01, 1.5, 23)]
+
+
+@pytest.mark.parametrize("n,lo,hi", ZOLO_CASES)
+def test_zolotarev_coefficients_match_oracle(n, lo, hi):
+    c = smpq.smpq_create((2, 2, 2, 2), -1)
+    smpq.smpq_set_zolotarev(c, n, lo, hi)
+    c0, cc, q, d = smpq.smpq_get_zolotarev(c)
+    o = zolotarev(n, lo, hi)
+    assert abs(c0 / o[0] - 1) < 1e-12
+    assert np.abs(cc / o[1] - 1).max() < 1e-12
+    assert np.abs(q / o[2] - 1).max() < 1e-12
+    assert abs(d - o[3]) < 2e-14 + 1e-6 * o[3]
+
+
+def test_argument_errors():
+    with pytest.raises(smpq.SmpqError) as e:
+        smpq.smpq_create((4, 0, 4, 4), -1)
+    assert e.value.status == -2
+    c = smpq.smpq_create((4, 4, 4, 6), -1)
+    for r, mode, status in [((4, 4, 4, 4), 0, -2), ((2, 2, 2, 2), 1, -2), ((2, 2, 2, 3), 2, -2),
+                            ((2, 2, 2, 2), 7, -1)]:
+        with pytest.raises(smpq.SmpqError) as e:
+            smpq.smpq_set_scheme(c, r, mode)
+        assert e.value.status == status
+    with pytest.raises(smpq.SmpqError) as e:
+        smpq.smpq_get_coloring(c)
+    assert e.value.status == -6
+    with pytest.raises(smpq.SmpqError) as e:
+        smpq.smpq_get_zolotarev(c)
+    assert e.value.status == -6
+    for k in (0.0, 0.25, -0.1):
+        with pytest.raises(smpq.SmpqError):
+            smpq.smpq_set_kappa(c, k)
+    for lo, hi in ((0.0, 1.0), (1.0, 0.5)):
+        with pytest.raises(smpq.SmpqError) as e:
+            smpq.smpq_set_zolotarev(c, 14, lo, hi)
+        assert e.value.status == -1
+    with pytest.raises(smpq.SmpqError):
+        smpq.smpq_set_zolotarev(c, 0, 0.1, 1.0)
+    with pytest.raises(smpq.SmpqError):
+        smpq.smpq_set_solver(c, smpq.SMPQ_FP64, 0.0, 10, 0)
+    with pytest.raises(smpq.SmpqError):
+        smpq.smpq_set_solver(c, 5, 1e-12, 10, 0)
+    V = 4 * 4 * 4 * 6
+    U = np.zeros((V, 4, 3, 3), dtype=complex)
+    U[:] = np.eye(3)
+    with pytest.raises(smpq.SmpqError) as e:     # GPU call on a host-only context
+        smpq.smpq_load_gauge(c, U)
+    assert e.value.status == -4
+    with pytest.raises(smpq.SmpqError) as e:     # wrong size
+        smpq.smpq_load_gauge(c, U[:-1])
+    assert e.value.status == -2
+    U[3, 1, 0, 0] = np.nan
+    with pytest.raises(smpq.SmpqError) as e:
+        smpq.smpq_load_gauge(c, U)
+    assert e.value.status == -7
+    with pytest.raises(smpq.SmpqError) as e:
+        smpq.smpq_compute_qx_points(c, [0])
+    assert e.value.status == -4
+    assert smpq.smpq_strerror(-5) == "solver did not converge"

@@ -1,0 +1,194 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the same seeded inputs.
+
+Sizes span several 256-site tiles with a ragged tail (V = 420, 576) plus odd extents.
+Tolerances: FP64 stencil 1e-13 and FP32 stencil 2e-6, relative to the largest output
+entry; FP64 q(x) within 1e-10 (absolute, |q(x)| <= 6 a priori); mixed precision within 1e-5.
+"""
+import numpy as np
+import pytest
+
+import smpq_inputs as si
+from oracle.charge import dov_apply, qx_probing
+from oracle.dirac import apply_dw, apply_gamma5, h_dense
+from oracle.lanczos import bounds, ritz_extremes
+from oracle.lattice import Lattice
+from oracle.probing import colouring, point_colouring
+from oracle.zolotarev import zolotarev
+
+pytestmark = pytest.mark.gpu
+
+import paper_1901_02211_amd as smpq  # noqa: E402
+
+KAPPA = 0.21
+TOL = 1e-12
+
+
+def _ctx(dims, U):
+    c = smpq.smpq_create(dims, 0)
+    smpq.smpq_load_gauge(c, U)
+    return c
+
+
+def _zolo_interval(U, lat):
+    return bounds(U, lat, KAPPA, 300, seed=0)
+
+
+@pytest.mark.parametrize("dims", [(6, 4, 4, 6), (5, 3, 4, 7), (4, 4, 4, 4)])
+@pytest.mark.parametrize("nrhs", [1, 3, 5])
+def test_dslash_parity(dims, nrhs):
+    print(f"dslash parity dims={dims} nrhs={nrhs}", flush=True)
+    lat = Lattice(dims)
+    U = si.near_identity_su3(dims, 0.5, 1)
+    psi = si.random_spinors(dims, nrhs, 2)
+    c = _ctx(dims, U)
+    for dag in (False, True):
+        ref = np.stack([apply_dw(U, lat, KAPPA, p, dagger=dag) for p in psi])
+        scale = np.abs(ref).max()
+        out64 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_FP64)
+        assert np.abs(out64 - ref).max() <= 1e-13 * scale
+        out32 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_MIXED_FP32)
+        assert np.abs(out32 - ref).max() <= 2e-6 * scale
+
+
+def test_dslash_gamma5_hermiticity_and_adjoint():
+    dims = (6, 4, 4, 6)
+    U = si.near_identity_su3(dims, 0.5, 3)
+    chi, psi = si.random_spinors(dims, 2, 4)
+    c = _ctx(dims, U)
+    d = smpq.smpq_apply_dw(c, psi)[0]
+    dd = smpq.smpq_apply_dw(c, chi, dagger=True)[0]
+    assert abs(np.vdot(chi, d) - np.vdot(dd, psi)) < 1e-12 * abs(np.vdot(chi, d))
+    g5 = apply_gamma5(smpq.smpq_apply_dw(c, apply_gamma5(psi))[0])
+    assert np.abs(g5 - smpq.smpq_apply_dw(c, psi, dagger=True)[0]).max() < 1e-13
+
+
+def test_lanczos_matches_dense_and_oracle():
+    dims = (4, 4, 2, 2)
+    lat = Lattice(dims)
+    U = si.near_identity_su3(dims, 0.3, 5)
+    w = np.linalg.eigvalsh(h_dense(U, lat, KAPPA))
+    c = _ctx(dims, U)
+    tmin, tmax = smpq.smpq_lanczos(c, 300, 0)
+    assert abs(tmin - (w ** 2).min()) < 1e-5 * (w ** 2).min()   # no reorthogonalisation on the GPU
+    assert abs(tmax - (w ** 2).max()) < 1e-10 * (w ** 2).max()
+    omin, omax = ritz_extremes(U, lat, KAPPA, 40, seed=0)
+    gmin, gmax = smpq.smpq_lanczos(c, 40, 0)
+    assert abs(gmax - omax) < 1e-8 * omax          # same start vector, same steps
+    assert abs(gmin - omin) < 1e-3 * omin
+    lo, hi = smpq.smpq_estimate_bounds(c, 300)
+    assert lo < np.abs(w).min() and hi > np.abs(w).max()
+
+
+def test_apply_dov_parity():
+    dims = (4, 4, 4, 4)
+    lat = Lattice(dims)
+    U = si.workload("noise4")
+    lo, hi = 0.13, 2.62
+    zo = zolotarev(14, lo, hi)
+    b = si.random_spinors(dims, 2, 6)
+    c = _ctx(dims, U)
+    smpq.smpq_set_zolotarev(c, 14, lo, hi)
+    smpq.smpq_set_solver(c, smpq.SMPQ_FP64, TOL, 5000, 0)
+    out = smpq.smpq_apply_dov(c, b)
+    for k in range(2):
+        ref = dov_apply(U, lat, KAPPA, zo, b[k], TOL, 5000)
+        assert np.abs(out[k] - ref).max() < 1e-10 * np.abs(ref).max()
+    # eps^2 = 1 on the GPU: eps = gamma5 (D_ov - 1)
+    e1 = apply_gamma5(out - b)
+    e2 = apply_gamma5(smpq.smpq_apply_dov(c, e1) - e1)
+    assert np.abs(e2 - b).max() < 1e-9 * np.abs(b).max()
+
+
+def _ragged_setup():
+    dims = (6, 4, 4, 6)
+    lat = Lattice(dims)
+    U = si.near_identity_su3(dims, 0.3, 7)
+    lo, hi = _zolo_interval(U, lat)
+    return dims, lat, U, lo, hi
+
+
+def test_qx_point_sources_fp64():
+    dims, lat, U, lo, hi = _ragged_setup()
+    zo = zolotarev(14, lo, hi)
+    sites = np.array([0, 300, 575])
+    c = _ctx(dims, U)
+    smpq.smpq_set_zolotarev(c, 14, lo, hi)
+    smpq.smpq_set_solver(c, smpq.SMPQ_FP64, TOL, 5000, 0)
+    q, st = smpq.smpq_compute_qx_points(c, sites)
+    col, _ = point_colouring(lat)
+    ref = qx_probing(U, lat, KAPPA, zo, col, sites, TOL, 5000)
+    assert np.abs(q - ref[sites].real).max() < 1e-10
+    assert st["n_sources"] == 36
+
+
+@pytest.mark.parametrize("mode,r", [(0, 2), (1, 2), (2, 2)])
+def test_qx_smp_classes_fp64_and_mixed(mode, r):
+    dims = (4, 4, 4, 8) if mode != 0 else (6, 4, 4, 6)
+    lat = Lattice(dims)
+    U = si.near_identity_su3(dims, 0.3, 8)
+    lo, hi = _zolo_interval(U, lat)
+    zo = zolotarev(14, lo, hi)
+    col, ncls = colouring(lat, (r,) * 4, mode)
+    classes = [0, ncls - 1]
+    c = _ctx(dims, U)
+    nc, ns = smpq.smpq_set_scheme(c, (r,) * 4, mode)
+    assert nc == ncls and ns == 12 * ncls
+    assert np.array_equal(smpq.smpq_get_coloring(c), col)
+    smpq.smpq_set_zolotarev(c, 14, lo, hi)
+    ref = qx_probing(U, lat, KAPPA, zo, col, classes, TOL, 5000)
+    smpq.smpq_set_solver(c, smpq.SMPQ_FP64, TOL, 5000, 0)
+    q64, qi64, st = smpq.smpq_compute_qx_classes(c, classes)
+    assert np.abs(q64 - ref.real).max() < 1e-10
+    assert np.abs(qi64 - ref.imag).max() < 1e-10
+    smpq.smpq_set_solver(c, smpq.SMPQ_MIXED_FP32, TOL, 5000, 50)
+    q32, qi32, st32 = smpq.smpq_compute_qx_classes(c, classes)
+    assert np.abs(q32 - ref.real).max() < 1e-5
+    assert st32["n_reliable_updates"] > 0
+
+
+def test_free_field_density_is_zero():
+    dims = (6, 4, 4, 6)
+    V = int(np.prod(dims))
+    U = np.zeros((V, 4, 3, 3), dtype=np.complex128)
+    U[:] = np.eye(3)
+    c = _ctx(dims, U)
+    smpq.smpq_set_zolotarev(c, 14, 0.15, 2.7)
+    smpq.smpq_set_scheme(c, (2, 2, 2, 2), 0)
+    for prec in (smpq.SMPQ_FP64, smpq.SMPQ_MIXED_FP32):
+        smpq.smpq_set_solver(c, prec, TOL, 5000, 50)
+        q, qi, Q, st = smpq.smpq_compute_qx(c)
+        assert np.abs(q).max() < (1e-12 if prec == smpq.SMPQ_FP64 else 1e-6)
+        assert abs(Q) < (1e-10 if prec == smpq.SMPQ_FP64 else 1e-4)
+
+
+def test_gauge_covariance_of_point_density():
+    dims, lat, U, lo, hi = _ragged_setup()
+    Ug = si.gauge_transform(U, dims, si.haar_su3(lat.volume, 9))
+    sites = np.array([5, 402])
+    out = []
+    for field in (U, Ug):
+        c = _ctx(dims, field)
+        smpq.smpq_set_zolotarev(c, 14, lo, hi)
+        out.append(smpq.smpq_compute_qx_points(c, sites)[0])
+    assert np.abs(out[0] - out[1]).max() < 1e-11
+
+
+def test_deterministic_and_errors():
+    dims, lat, U, lo, hi = _ragged_setup()
+    c = _ctx(dims, U)
+    smpq.smpq_set_zolotarev(c, 14, lo, hi)
+    smpq.smpq_set_scheme(c, (2, 2, 2, 2), 0)
+    a = smpq.smpq_compute_qx_classes(c, [3])[0]
+    b = smpq.smpq_compute_qx_classes(c, [3])[0]
+    assert np.array_equal(a, b)
+    smpq.smpq_set_solver(c, smpq.SMPQ_FP64, TOL, 3, 0)
+    with pytest.raises(smpq.SmpqError) as e:
+        smpq.smpq_compute_qx_classes(c, [3])
+    assert e.value.status == -5
+    with pytest.raises(smpq.SmpqError):
+        smpq.smpq_compute_qx_classes(c, [99])
+    bad = U.copy()
+    bad[0, 0] *= 1.01
+    with pytest.raises(smpq.SmpqError) as e:
+        smpq.smpq_load_gauge(c, bad)
+    assert e.value.status == -7
