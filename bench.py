@@ -1,0 +1,231 @@
+"""Benchmark: seconds per q(x) map on one MI355X, mixed precision vs plain FP64.
+
+Workload: 16^3 x 32 periodic lattice, near-identity SU(3) links (eps = 0.2, seed 4),
+kappa = 0.21, 14-pole Zolotarev sign function on Lanczos bounds, SMP normal mode with
+r = 4 (256 classes x 12 = 3072 sources), per-shift CG tolerance 1e-12.  One step is one
+whole q(x) map: Lanczos bounds + Zolotarev + every multi-shift CG solve + contraction +
+copy-out of q(x) and Q, with the gauge field already resident in HBM.  The map runs in
+FP32 with FP64 reliable updates every 50 iterations and FP64 accumulation.
+
+Printed: one JSON line.  value = seconds per map (lower is better).  Beside it:
+  roofline      the dominant kernel of the step (HIP events on the library's stream),
+                algorithmic bytes per launch / mean launch duration vs 8 TB/s
+  dslash        the Wilson stencil in situ and standalone (rotating buffers > 1 GB)
+  fp64          the plain FP64 GPU path on a sample of classes, scaled to a map
+  accuracy      mixed vs FP64 GPU on the sample; |Q - round(Q)| of the map
+  cpu_baseline  the FP64 numpy oracle on a bounded sample (single thread), scaled
+"""
+import argparse
+import hashlib
+import json
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+DIMS = (16, 16, 16, 32)
+WORKLOAD = "noise16x32"
+R_GAP = 4
+KAPPA, TOL, POLES, RELIABLE = 0.21, 1e-12, 14, 50
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "wilson_site.h"):
+        with open(os.path.join(ROOT, "paper_1901_02211_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary, if it matches these kernels."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    entry = data.get(kernel)
+    if not entry or entry.get("kernel_hash") != kernel_source_hash():
+        return None
+    return entry
+
+
+def cpu_baseline(total_iters, n_sources, iters_sample):
+    """Time the oracle's multi-shift CG on one source of the workload for a bounded number of
+    iterations in a single-threaded subprocess; scale by the map's measured iteration count."""
+    code = f"""
+import os, sys, time
+sys.path.insert(0, {ROOT!r})
+import numpy as np
+import smpq_inputs as si
+from oracle.lattice import Lattice
+from oracle.dirac import apply_h2
+from oracle.mscg import multishift_cg, NotConverged
+from oracle.lanczos import bounds
+from oracle.zolotarev import zolotarev
+from oracle.probing import colouring
+U = si.workload({WORKLOAD!r}); lat = Lattice({DIMS!r})
+col, _ = colouring(lat, ({R_GAP},) * 4, 0)
+b = np.zeros((lat.volume, 4, 3), dtype=np.complex128); b[col == 0, 0, 0] = 1.0
+c0, c, q, _ = zolotarev({POLES}, 0.14, 2.73)
+s = q.min()
+t0 = time.perf_counter()
+try:
+    multishift_cg(lambda v: apply_h2(U, lat, {KAPPA}, v) + s * v, b, q - s, {TOL}, {iters_sample})
+except NotConverged:
+    pass
+print(time.perf_counter() - t0)
+"""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    if out.returncode != 0:
+        raise RuntimeError(out.stderr)
+    t = float(out.stdout.strip().splitlines()[-1])
+    per_iter = t / iters_sample
+    return {"value": per_iter * total_iters, "unit": "s/map", "cores": 1, "kind": "oracle",
+            "sample": f"{iters_sample} multi-shift CG iterations of one r=4 source on the 16^3x32 field "
+                      f"({t:.1f} s), scaled by the map's {total_iters} iterations over {n_sources} sources",
+            "seconds_per_iteration": per_iter}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--fp64-classes", type=int, default=16, help="classes in the FP64 comparison sample")
+    ap.add_argument("--full-fp64", action="store_true", help="run the FP64 comparison as a whole map")
+    ap.add_argument("--classes", type=int, default=0, help="profile mode: only the first N classes")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=8)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(sources shard over GPUs with no hot-loop communication; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import paper_1901_02211_amd as smpq
+    import smpq_inputs as si
+
+    print(f"bench: building {WORKLOAD} {DIMS}", file=sys.stderr, flush=True)
+    U = si.workload(WORKLOAD)
+    ctx = smpq.smpq_create(DIMS, 0)
+    smpq.smpq_load_gauge(ctx, U)                    # resident in HBM before any timed region
+    ncls, nsrc = smpq.smpq_set_scheme(ctx, (R_GAP,) * 4, 0)
+    smpq.smpq_set_solver(ctx, smpq.SMPQ_MIXED_FP32, TOL, 10000, RELIABLE)
+    classes = list(range(ncls if args.classes == 0 else args.classes))
+
+    def one_map():
+        """One step: Lanczos bounds, Zolotarev coefficients and the whole q(x) map."""
+        t0 = time.perf_counter()
+        lo, hi = smpq.smpq_estimate_bounds(ctx, 300)
+        smpq.smpq_set_zolotarev(ctx, POLES, lo, hi)
+        t1 = time.perf_counter()
+        if args.classes:
+            q, qi, st = smpq.smpq_compute_qx_classes(ctx, classes)
+            Q = float(q.sum())
+        else:
+            q, qi, Q, st = smpq.smpq_compute_qx(ctx)
+        t2 = time.perf_counter()
+        st["t_bounds_s"] = t1 - t0
+        return t2 - t0, q, Q, st
+
+    # untimed set-up: workspace allocation and first launches of every kernel
+    smpq.smpq_set_zolotarev(ctx, POLES, 0.14, 2.73)
+    smpq.smpq_prepare(ctx)
+    smpq.smpq_compute_qx_classes(ctx, [0])
+    smpq.smpq_set_timing(ctx, True)
+    for w in range(args.warmup):
+        print(f"bench: warmup step {w}", file=sys.stderr, flush=True)
+        one_map()
+    times, last = [], None
+    for k in range(args.steps):
+        dt, q, Q, st = one_map()
+        times.append(dt)
+        last = (q, Q, st)
+        print(f"bench: step {k}: {dt:.2f} s, Q = {Q:.6f}, iters {st['total_iters']}, "
+              f"batches {st['n_batches']}", file=sys.stderr, flush=True)
+    q_mixed, Q, st = last
+    ms_per_step = 1000.0 * float(np.mean(times))
+
+    # kernels: dominant by in-situ time
+    kern = {
+        "dslash": dict(ms=st["dslash_ms"], bytes=st["dslash_bytes"], launches=st["dslash_launches"]),
+        "shift_update": dict(ms=st["update_ms"], bytes=st["update_bytes"], launches=st["update_launches"]),
+    }
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    kd = kern[dom]
+    mean_ms = kd["ms"] / kd["launches"]
+    bytes_launch = kd["bytes"] / kd["launches"]
+    achieved = bytes_launch / (mean_ms * 1e-3) / 1e9
+    tr = measured_traffic(dom)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": tr["bytes_per_launch"] if tr else None,
+                "launch_ms": round(mean_ms, 4), "algorithmic_bytes_per_launch": bytes_launch}
+
+    ds_insitu = st["dslash_bytes"] / (st["dslash_ms"] * 1e-3) / 1e9
+    print("bench: standalone stencil", file=sys.stderr, flush=True)
+    ms32, by32 = smpq.smpq_bench_dslash(ctx, smpq.SMPQ_MIXED_FP32, 24, 4, 50)
+    ms64, by64 = smpq.smpq_bench_dslash(ctx, smpq.SMPQ_FP64, 24, 4, 50)
+    dslash = {"insitu_GBs": round(ds_insitu, 1), "insitu_frac": round(ds_insitu / HBM_PEAK_GBS, 4),
+              "standalone_fp32_n24_GBs": round(by32 / ms32 / 1e6, 1),
+              "standalone_fp64_n24_GBs": round(by64 / ms64 / 1e6, 1),
+              "standalone_note": "24 right-hand sides, 4 rotating input/output/link sets (> 1 GB)"}
+
+    # plain FP64 GPU path on a sample of classes (or the whole map)
+    print("bench: FP64 comparison", file=sys.stderr, flush=True)
+    fcls = list(range(ncls)) if args.full_fp64 else list(range(min(args.fp64_classes, len(classes))))
+    smpq.smpq_set_solver(ctx, smpq.SMPQ_FP64, TOL, 10000, 0)
+    smpq.smpq_set_timing(ctx, False)
+    t0 = time.perf_counter()
+    q64, qi64, st64 = smpq.smpq_compute_qx_classes(ctx, fcls)
+    t64 = time.perf_counter() - t0
+    colour = smpq.smpq_get_coloring(ctx)
+    mask = np.isin(colour, fcls)
+    fp64 = {"seconds": round(t64, 3), "classes": len(fcls),
+            "s_per_map": round(t64 * ncls / len(fcls), 3),
+            "scaled": not args.full_fp64, "total_iters": st64["total_iters"]}
+    accuracy = {"max_abs_dq_mixed_vs_fp64": float(np.abs(q_mixed[mask] - q64[mask]).max()),
+                "Q": Q, "abs_Q_minus_round": abs(Q - round(Q)),
+                "max_abs_imag_q": st["max_abs_imag_q"], "sum_imag_q": st["sum_imag_q"],
+                "lam_min": st["lam_min"], "lam_max": st["lam_max"], "zolo_delta": st["zolo_delta"]}
+    if args.full_fp64:
+        accuracy["Q_fp64"] = float(q64.sum())
+
+    cpu = None
+    if not args.no_cpu:
+        print("bench: CPU oracle sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(st["total_iters"], st["n_sources"], args.cpu_iters)
+
+    line = {
+        "metric": "sec per q(x) map + D_W HBM GB/s; mixed/batched vs plain FP64 at 16^3x32",
+        "value": round(ms_per_step / 1000.0, 3), "unit": "s/map",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 1),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "16^3x32 near-identity SU(3) eps=0.2 seed 4, SMP normal mode r=4",
+                   "lattice": list(DIMS), "n_sources": st["n_sources"], "n_batches": st["n_batches"],
+                   "kappa": KAPPA, "zolotarev_poles": POLES, "cg_tol": TOL, "reliable_interval": RELIABLE,
+                   "precision": "FP32 stencil and CG body, FP64 scalars/reliable updates/accumulation",
+                   "classes": len(classes)},
+        "speedup_vs_fp64": round(fp64["s_per_map"] / (ms_per_step / 1000.0) * (len(classes) / ncls), 3),
+        "roofline": roofline, "dslash": dslash, "fp64": fp64, "accuracy": accuracy,
+        "breakdown_s": {"bounds": round(st["t_bounds_s"], 3), "solve": round(st["t_solve_s"], 3),
+                        "contract": round(st["t_contract_s"], 3)},
+        "iterations": {"total": st["total_iters"], "max": st["max_iters"], "reliable_updates": st["n_reliable_updates"],
+                       "mean_active_shifts": round(st["shift_updates"] / max(1, st["total_iters"]), 2)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -185,6 +185,11 @@ smpq_status smpq_compute_qx_classes(smpq_ctx *ctx, const int32_t *classes, int n
 smpq_status smpq_compute_qx_points(smpq_ctx *ctx, const int64_t *sites, int n, double *qx,
                                    smpq_stats *st);
 
+/* Allocate the device workspace that smpq_compute_qx will use with the current scheme,
+ * solver settings and Zolotarev order, without computing anything (compute_qx otherwise
+ * allocates on first use).  ESTATE without a gauge field, scheme or coefficients. */
+smpq_status smpq_prepare(smpq_ctx *ctx);
+
 /* Use `stream` (a hipStream_t) for all device work of the context; NULL restores the
  * context's own stream.  The caller keeps ownership of the stream. */
 smpq_status smpq_set_stream(smpq_ctx *ctx, void *stream);

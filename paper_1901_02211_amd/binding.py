@@ -11,7 +11,7 @@ import numpy as np
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsmpq.so")
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1901_02211_amd.build`")
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1901_02211_amd/build.py`")
 _lib = ctypes.CDLL(LIB_PATH)
 
 __all__ = [
@@ -20,7 +20,7 @@ __all__ = [
     "smpq_set_kappa", "smpq_lanczos", "smpq_estimate_bounds", "smpq_set_zolotarev",
     "smpq_get_zolotarev", "smpq_set_solver", "smpq_set_batch", "smpq_set_scheme",
     "smpq_set_point_scheme", "smpq_get_coloring", "smpq_apply_dw", "smpq_apply_dov",
-    "smpq_compute_qx", "smpq_compute_qx_classes", "smpq_compute_qx_points", "smpq_set_stream",
+    "smpq_compute_qx", "smpq_compute_qx_classes", "smpq_compute_qx_points", "smpq_prepare", "smpq_set_stream",
     "smpq_set_timing", "smpq_bench_dslash",
 ]
 
@@ -66,6 +66,7 @@ _SIG = {
                                                _c_double_p, ctypes.POINTER(SmpqStats)]),
     "smpq_compute_qx_points": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, _c_double_p,
                                               ctypes.POINTER(SmpqStats)]),
+    "smpq_prepare": (ctypes.c_int, [_vp]),
     "smpq_set_stream": (ctypes.c_int, [_vp, _vp]),
     "smpq_set_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
     "smpq_bench_dslash": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_double_p,
@@ -252,6 +253,10 @@ def smpq_compute_qx_points(ctx, sites):
     _check(ctx, _lib.smpq_compute_qx_points(ctx.ptr, s.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(s),
                                             _dp(qx), ctypes.byref(st)))
     return qx, st.as_dict()
+
+
+def smpq_prepare(ctx):
+    _check(ctx, _lib.smpq_prepare(ctx.ptr))
 
 
 def smpq_set_stream(ctx, stream_handle):

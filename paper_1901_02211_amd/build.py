@@ -1,6 +1,7 @@
 """Build libsmpq.so in-tree for gfx950 (hipcc; host C++ with g++).
 
-Run as ``python -m paper_1901_02211_amd.build``.  Every call rebuilds.
+Run as ``python paper_1901_02211_amd/build.py`` (by path: importing the package needs the
+built library).  Every call rebuilds.
 """
 import concurrent.futures as cf
 import os

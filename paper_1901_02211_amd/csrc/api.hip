@@ -272,10 +272,13 @@ int choose_batch(smpq_ctx *c, int prec, int NS, int total_slots, bool multiple_o
     long long B = (long long)(budget / (double)bytes_per_slot(c, prec, NS));
     if (c->max_rhs > 0) B = std::min<long long>(B, c->max_rhs);
     B = std::min<long long>(B, total_slots);
-    if (multiple_of_12) B = (B / 12) * 12;
-    if (B < (multiple_of_12 ? 12 : 1))
-        throw Fail{SMPQ_ENOMEM, "not enough device memory for one batch of right-hand sides"};
-    return (int)B;
+    const int q = multiple_of_12 ? 12 : 1;
+    B = (B / q) * q;
+    if (B < q) throw Fail{SMPQ_ENOMEM, "not enough device memory for one batch of right-hand sides"};
+    // spread the right-hand sides evenly over the batches this limit implies
+    const long long nb = (total_slots + B - 1) / B;
+    const long long even = ((total_slots + nb - 1) / nb + q - 1) / q * q;
+    return (int)std::min(B, even);
 }
 
 void require_gauge_zolo(smpq_ctx *c) {
@@ -316,8 +319,7 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
     const size_t rs64 = 12 * c->vs;
     const void *U = prec == 0 ? c->U64.p : c->U32.p;
     const int lgr = lgr_for(prec);
-    const int np_unit = unit_parts(prec, g), np_ds = dslash_parts(g, lgr), np_ds64 = dslash_parts(g, lgr_for(0));
-    (void)np_ds64;
+    const int np_unit = unit_parts(prec, g), np_ds = dslash_partials(prec, g, lgr);
     Slots act{S.list, S.count, 0};
 
     launch_cg_init(prec, g, src, nslots, NS, c->zolo.c0, w.r.p, w.p.p, w.y.as<double2>(),
@@ -387,12 +389,12 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
         res.active += actv[k];
     }
     if (st) {
-        const double s_t = prec == 0 ? 16.0 : 8.0;     // bytes per complex spinor entry
-        const double u_t = prec == 0 ? 16.0 : 8.0;     // bytes per complex link entry
+        const double s_t = prec == 0 ? 16.0 : 8.0;           // bytes per complex spinor entry
+        const double link_site = prec == 0 ? 576.0 : 192.0;   // link bytes per site (FP32: two rows)
         const double V = c->V;
         // algorithmic bytes: D_W reads links once and each input/output spinor once; the
         // second stencil also reads p for the "+ s0 p" term.  Per active slot-iteration.
-        st->dslash_bytes += (double)iter * 2.0 * 36.0 * u_t * V + (double)res.active * V * 12.0 * s_t * 5.0;
+        st->dslash_bytes += (double)iter * 2.0 * link_site * V + (double)res.active * V * 12.0 * s_t * 5.0;
         st->dslash_launches += 2LL * iter;
         // update kernel: r read, y (FP64) read+write, x0 (FP64) read+write in mixed
         // precision, every listed p_i read, every updated p_i written.
@@ -688,8 +690,9 @@ smpq_status smpq_load_gauge(smpq_ctx *c, const double *U, size_t n) {
         }
         need_device(c);
         const size_t V = c->V;
+        // FP64: all nine entries [mu][k][site]; FP32: rows 0 and 1, [mu][j][site] float4
         std::vector<double> u64(V * 72);
-        std::vector<float> u32(V * 72);
+        std::vector<float> u32(V * 48);
         for (size_t s = 0; s < V; ++s)
             for (int mu = 0; mu < 4; ++mu)
                 for (int k = 0; k < 9; ++k) {
@@ -697,13 +700,16 @@ smpq_status smpq_load_gauge(smpq_ctx *c, const double *U, size_t n) {
                     const size_t d = ((size_t)(mu * 9 + k) * V + s) * 2;
                     u64[d] = src[0];
                     u64[d + 1] = src[1];
-                    u32[d] = (float)src[0];
-                    u32[d + 1] = (float)src[1];
+                    if (k < 6) {
+                        const size_t f = ((size_t)(mu * 3 + k / 2) * V + s) * 4 + 2 * (k % 2);
+                        u32[f] = (float)src[0];
+                        u32[f + 1] = (float)src[1];
+                    }
                 }
         c->U64.ensure(sizeof(double) * V * 72);
-        c->U32.ensure(sizeof(float) * V * 72);
+        c->U32.ensure(sizeof(float) * V * 48);
         HIPCHK(hipMemcpy(c->U64.p, u64.data(), sizeof(double) * V * 72, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(c->U32.p, u32.data(), sizeof(float) * V * 72, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(c->U32.p, u32.data(), sizeof(float) * V * 48, hipMemcpyHostToDevice));
         c->have_gauge = true;
     });
 }
@@ -948,6 +954,18 @@ smpq_status smpq_compute_qx_points(smpq_ctx *c, const int64_t *sites, int n, dou
     });
 }
 
+smpq_status smpq_prepare(smpq_ctx *c) {
+    return guarded(c, [&] {
+        need_device(c);
+        require_gauge_zolo(c);
+        if (!c->have_scheme) throw Fail{SMPQ_ESTATE, "no scheme set"};
+        const int prec = c->prec == SMPQ_FP64 ? 0 : 1;
+        const int B = choose_batch(c, prec, c->zolo.n, 12 * c->n_classes, true);
+        ensure_workspace(c, prec, c->zolo.n, B);
+        ensure_scheme_device(c);
+    });
+}
+
 smpq_status smpq_set_stream(smpq_ctx *c, void *stream) {
     return guarded(c, [&] {
         need_device(c);
@@ -971,7 +989,7 @@ smpq_status smpq_bench_dslash(smpq_ctx *c, smpq_precision prec, int n_rhs, int n
         const Geom g = c->geom();
         const size_t units = p == 0 ? 12 : 6;
         const size_t vbytes = units * 16 * c->vs;
-        const size_t lbytes = (size_t)c->V * 72 * (p == 0 ? 8 : 4);
+        const size_t lbytes = (size_t)c->V * (p == 0 ? 72 * 8 : 48 * 4);
         std::vector<DevMem> ins(n_sets), outs(n_sets), links(n_sets);
         for (int k = 0; k < n_sets; ++k) {
             ins[k].ensure(vbytes * n_rhs);
@@ -1002,7 +1020,7 @@ smpq_status smpq_bench_dslash(smpq_ctx *c, smpq_precision prec, int n_rhs, int n
         HIPCHK(hipGetLastError());
         *ms = t / launches;
         const double u = p == 0 ? 16.0 : 8.0;
-        *bytes = (double)c->V * (36.0 * u + (double)n_rhs * 24.0 * u);
+        *bytes = (double)c->V * ((double)lbytes / c->V + (double)n_rhs * 24.0 * u);
     });
 }
 

@@ -12,7 +12,8 @@ constexpr int kBlock = 256;
 // Geometry + storage strides.  A spinor of one right-hand side is stored as
 // components [unit][site] with unit stride `vs` (the padded volume): FP64 uses 12
 // double2 units (one complex each), FP32 uses 6 float4 units (two complexes each).
-// Links are [mu][row*3 + col][site] complex (double2 or float2).
+// FP64 links are [mu][row*3 + col][site] double2; FP32 links keep the first two rows,
+// [mu][3][site] float4 holding (u00,u01), (u02,u10), (u11,u12).
 struct Geom {
     int nx, ny, nz, nt, V;
     size_t vs;
@@ -63,7 +64,8 @@ void launch_dslash(int prec, bool dag, int lgR, int epi, const void *U, const vo
                    size_t aux_extra, const Geom &g, double kappa, double sigma, Slots sl, int max_slots,
                    double *partial, hipStream_t st);
 __host__ __device__ int site_blocks(const Geom &g);               // blocks of 256 sites
-int dslash_parts(const Geom &g, int lgR);       // partials per slot written by the stencil epilogue
+int dslash_parts(const Geom &g, int lgR);       // partials per slot of the FP64 stencil epilogue
+int dslash_partials(int prec, const Geom &g, int lgR);   // ... of the stencil of precision prec
 int unit_parts(int prec, const Geom &g);        // partials per slot written by element-wise kernels
 size_t partial_stride(const Geom &g);           // slot stride of the partial buffer (>= both)
 

@@ -1,8 +1,10 @@
 // Device kernels of the overlap charge-density path on gfx950 (CDNA4, wave64).
 //
-//  k_dslash        Wilson stencil D_W / D_W^dag (section 1, Eq. 3); R right-hand sides
-//                  interleaved over the lanes of a block share each link fetch; optional
-//                  epilogue "+ sigma aux" with a fused <aux, out> partial for H^2 + sigma (Eq. 4).
+//  k_dslash        Wilson stencil D_W / D_W^dag (section 1, Eq. 3) in FP64: R right-hand
+//                  sides interleaved over the lanes of a block share each link fetch
+//  k_dslash_f32    the FP32 stencil: one site per thread, its eight links held in registers
+//                  for several right-hand sides; both take an optional epilogue
+//                  "+ sigma aux" with a fused <aux, out> partial for H^2 + sigma (Eq. 4).
 //  k_cg_init ...   multi-shift CG for (D_W^dag D_W + q_i) x_i = b (Eqs. 6-8): residual
 //                  update, fused update of every active shift's search direction plus the
 //                  running rational sum y = c_0 b + sum_i c_i x_i, scalar recurrences on the
@@ -43,7 +45,7 @@ struct Store<double> {
 template <>
 struct Store<float> {
     using vec = float4;
-    using link = float2;
+    using link = float4;   // two rows of the SU(3) link: (u00,u01), (u02,u10), (u11,u12)
     static constexpr int units = 6;
     __device__ static __forceinline__ void load(const float4 *p, size_t vs, int s, cpx<float> v[12]) {
 #pragma unroll
@@ -60,13 +62,39 @@ struct Store<float> {
     }
 };
 
+// FP64 links: all nine entries, [mu][row*3 + col][site] double2.
+// FP32 links: the first two rows, [mu][3][site] float4; the third row is rebuilt as
+// conj(row0 x row1), exact for a special unitary matrix.
+__device__ __forceinline__ void unpack_rows(float4 a, float4 b, float4 c, cpx<float> u[9]) {
+    u[0] = {a.x, a.y};
+    u[1] = {a.z, a.w};
+    u[2] = {b.x, b.y};
+    u[3] = {b.z, b.w};
+    u[4] = {c.x, c.y};
+    u[5] = {c.z, c.w};
+    const cpx<float> r0 = cmul(u[1], u[5]) - cmul(u[2], u[4]);
+    const cpx<float> r1 = cmul(u[2], u[3]) - cmul(u[0], u[5]);
+    const cpx<float> r2 = cmul(u[0], u[4]) - cmul(u[1], u[3]);
+    u[6] = {r0.re, -r0.im};
+    u[7] = {r1.re, -r1.im};
+    u[8] = {r2.re, -r2.im};
+}
+
 template <class T>
-__device__ __forceinline__ void load_link(const typename Store<T>::link *U, int V, int mu, int s, cpx<T> u[9]) {
+__device__ __forceinline__ void load_link(const typename Store<T>::link *U, int V, int mu, int s, cpx<T> u[9]);
+
+template <>
+__device__ __forceinline__ void load_link<double>(const double2 *U, int V, int mu, int s, cpx<double> u[9]) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        const auto t = U[(size_t)(mu * 9 + k) * V + s];
+        const double2 t = U[(size_t)(mu * 9 + k) * V + s];
         u[k] = {t.x, t.y};
     }
+}
+
+template <>
+__device__ __forceinline__ void load_link<float>(const float4 *U, int V, int mu, int s, cpx<float> u[9]) {
+    unpack_rows(U[(size_t)(mu * 3) * V + s], U[(size_t)(mu * 3 + 1) * V + s], U[(size_t)(mu * 3 + 2) * V + s], u);
 }
 
 // Hardware dispatches consecutive workgroups round-robin over the 8 XCDs; give each XCD
@@ -181,6 +209,100 @@ __global__ __launch_bounds__(kBlock) void k_dslash(const typename Store<T>::link
     }
 }
 
+// FP32 stencil, one site per thread: the eight two-row links a site needs (U_mu(x) and
+// U_mu(x - mu)) are loaded into registers once and applied to NR right-hand sides in turn,
+// so link bytes are paid once per NR sides without sharing lanes.  Blocks are ordered
+// site-fastest within each XCD's contiguous range.
+template <int NR, bool DAG, int EPI>
+__global__ __launch_bounds__(kBlock) void k_dslash_f32(const float4 *__restrict__ U, const float4 *__restrict__ in,
+                                                       size_t in_stride, size_t in_extra, float4 *__restrict__ out,
+                                                       size_t out_stride, const float4 *__restrict__ aux,
+                                                       size_t aux_stride, size_t aux_extra, Geom g, float kappa,
+                                                       float sigma, Slots sl, int nsb, double *__restrict__ partial,
+                                                       size_t pstride) {
+    constexpr int SF = DAG ? -1 : 1;
+    const int L = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int sb = L % nsb, rg = L / nsb;
+    const int cnt = slot_count(sl);
+    const int k0 = rg * NR;
+    if (k0 >= cnt) return;  // uniform over the block
+    const int s = sb * kBlock + threadIdx.x;
+    const bool site_ok = s < g.V;
+    const int sv = site_ok ? s : 0;
+    const Nbr nb = neighbours(sv, g.nx, g.ny, g.nz, g.nt);
+    float4 lf[4][3], lb[4][3];
+    if (site_ok) {
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                lf[mu][j] = U[(size_t)(mu * 3 + j) * g.V + sv];
+                lb[mu][j] = U[(size_t)(mu * 3 + j) * g.V + nb.bwd[mu]];
+            }
+    }
+    double dot[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) dot[r] = 0.0;
+#pragma unroll 1
+    for (int r = 0; r < NR; ++r) {
+        const int k = k0 + r;
+        if (k >= cnt) break;  // uniform over the block
+        if (!site_ok) continue;
+        const int slot = slot_of(sl, k);
+        const float4 *src = in + slot * in_stride + in_extra;
+        cpx<float> acc[12], u[9], p[12], h[6], w[6];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[c] = {0.f, 0.f};
+#define SMPQ_HOP(MU)                                                                 \
+        unpack_rows(lf[MU][0], lf[MU][1], lf[MU][2], u);                             \
+        Store<float>::load(src, g.vs, nb.fwd[MU], p);                                \
+        project<MU, SF>(p, h);                                                       \
+        su3_mul(u, h, w);                                                            \
+        accumulate<MU, SF>(acc, w);                                                  \
+        unpack_rows(lb[MU][0], lb[MU][1], lb[MU][2], u);                             \
+        Store<float>::load(src, g.vs, nb.bwd[MU], p);                                \
+        project<MU, -SF>(p, h);                                                      \
+        su3_dag_mul(u, h, w);                                                        \
+        accumulate<MU, -SF>(acc, w);
+        SMPQ_HOP(0)
+        SMPQ_HOP(1)
+        SMPQ_HOP(2)
+        SMPQ_HOP(3)
+#undef SMPQ_HOP
+        cpx<float> v[12];
+        Store<float>::load(src, g.vs, sv, v);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) v[c] = v[c] - kappa * acc[c];
+        if constexpr (EPI == 1) {
+            Store<float>::load(aux + slot * aux_stride + aux_extra, g.vs, sv, p);
+            double d = 0.0;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                v[c] = v[c] + sigma * p[c];
+                d += (double)p[c].re * (double)v[c].re + (double)p[c].im * (double)v[c].im;
+            }
+            dot[r] = d;
+        }
+        Store<float>::store(out + slot * out_stride, g.vs, sv, v);
+    }
+    if constexpr (EPI == 1) {
+        __shared__ double lds[NR][kBlock / 64];
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const double t = wave_sum(dot[r]);
+            if (lane == 0) lds[r][wv] = t;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < NR && k0 + (int)threadIdx.x < cnt) {
+            double t = 0.0;
+#pragma unroll
+            for (int i = 0; i < kBlock / 64; ++i) t += lds[threadIdx.x][i];
+            partial[(size_t)slot_of(sl, k0 + threadIdx.x) * pstride + sb] = t;
+        }
+    }
+}
+
 __host__ __device__ int site_blocks(const Geom &g) { return (g.V + kBlock - 1) / kBlock; }
 int dslash_parts(const Geom &g, int lgR) { return (g.V + (kBlock >> lgR) - 1) / (kBlock >> lgR); }
 size_t partial_stride(const Geom &g) { return (size_t)12 * site_blocks(g); }
@@ -200,25 +322,44 @@ static void launch_dslash_t(const void *U, const void *in, size_t in_stride, siz
                        aux_extra, g, (T)kappa, (T)sigma, sl, lgR, nsb, partial, partial_stride(g));
 }
 
+constexpr int kNRF32 = 4;   // right-hand sides per thread in the FP32 stencil
+
+template <bool DAG, int EPI>
+static void launch_dslash_f32(const void *U, const void *in, size_t in_stride, size_t in_extra, void *out,
+                              size_t out_stride, const void *aux, size_t aux_stride, size_t aux_extra, const Geom &g,
+                              double kappa, double sigma, Slots sl, int max_slots, double *partial, hipStream_t st) {
+    const int nsb = site_blocks(g);
+    const int ngr = (max_slots + kNRF32 - 1) / kNRF32;
+    hipLaunchKernelGGL((k_dslash_f32<kNRF32, DAG, EPI>), dim3(nsb * ngr), dim3(kBlock), 0, st, (const float4 *)U,
+                       (const float4 *)in, in_stride, in_extra, (float4 *)out, out_stride, (const float4 *)aux,
+                       aux_stride, aux_extra, g, (float)kappa, (float)sigma, sl, nsb, partial, partial_stride(g));
+}
+
+int dslash_partials(int prec, const Geom &g, int lgR) { return prec == 0 ? dslash_parts(g, lgR) : site_blocks(g); }
+
 void launch_dslash(int prec, bool dag, int lgR, int epi, const void *U, const void *in, size_t in_stride,
                    size_t in_extra, void *out, size_t out_stride, const void *aux, size_t aux_stride, size_t aux_extra,
                    const Geom &g, double kappa, double sigma, Slots sl, int max_slots, double *partial,
                    hipStream_t st) {
-#define SMPQ_DS(T, D, E)                                                                                          \
-    launch_dslash_t<T, D, E>(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra, g, kappa,   \
-                             sigma, sl, max_slots, lgR, partial, st)
     if (prec == 0) {
-        if (!dag && epi == 0) SMPQ_DS(double, false, 0);
-        else if (!dag) SMPQ_DS(double, false, 1);
-        else if (epi == 0) SMPQ_DS(double, true, 0);
-        else SMPQ_DS(double, true, 1);
-    } else {
-        if (!dag && epi == 0) SMPQ_DS(float, false, 0);
-        else if (!dag) SMPQ_DS(float, false, 1);
-        else if (epi == 0) SMPQ_DS(float, true, 0);
-        else SMPQ_DS(float, true, 1);
-    }
+#define SMPQ_DS(D, E)                                                                                          \
+    launch_dslash_t<double, D, E>(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra, g, kappa, \
+                                  sigma, sl, max_slots, lgR, partial, st)
+        if (!dag && epi == 0) SMPQ_DS(false, 0);
+        else if (!dag) SMPQ_DS(false, 1);
+        else if (epi == 0) SMPQ_DS(true, 0);
+        else SMPQ_DS(true, 1);
 #undef SMPQ_DS
+    } else {
+#define SMPQ_DS(D, E)                                                                                       \
+    launch_dslash_f32<D, E>(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra, g, kappa, \
+                            sigma, sl, max_slots, partial, st)
+        if (!dag && epi == 0) SMPQ_DS(false, 0);
+        else if (!dag) SMPQ_DS(false, 1);
+        else if (epi == 0) SMPQ_DS(true, 0);
+        else SMPQ_DS(true, 1);
+#undef SMPQ_DS
+    }
 }
 
 // ------------------------------------------------------------------ element-wise kernels
