@@ -194,6 +194,7 @@ def main():
             "s_per_map": round(t64 * ncls / len(fcls), 3),
             "scaled": not args.full_fp64, "total_iters": st64["total_iters"]}
     accuracy = {"max_abs_dq_mixed_vs_fp64": float(np.abs(q_mixed[mask] - q64[mask]).max()),
+                "dQ_mixed_vs_fp64_on_sample": float(q_mixed[mask].sum() - q64[mask].sum()),
                 "Q": Q, "abs_Q_minus_round": abs(Q - round(Q)),
                 "max_abs_imag_q": st["max_abs_imag_q"], "sum_imag_q": st["sum_imag_q"],
                 "lam_min": st["lam_min"], "lam_max": st["lam_max"], "zolo_delta": st["zolo_delta"]}

@@ -67,7 +67,7 @@ struct DevMem {
 // Device workspace of one batch of right-hand sides.
 struct Workspace {
     int prec = -1, NS = 0, B = 0;
-    DevMem r, tmp, ap, p, y, x0, tmp64, ap64;
+    DevMem r, tmp, ap, p, y, x0, tmp64, ap64, yacc, x0acc;
     DevMem st_d;   // doubles of the MSState
     DevMem st_i;   // ints of the MSState
     DevMem st_l;   // long longs of the MSState
@@ -191,10 +191,18 @@ void spinor_from_device(const smpq_ctx *c, const std::vector<double> &stage, int
 // right-hand sides per stencil block (log2): links are shared by the lanes of one site
 int lgr_for(int prec) { return prec == 0 ? 1 : 2; }
 
+// FP32 path.  The first iterations build most of y and x0 (the residual falls by ~10^3 in
+// the first 50 iterations at these condition numbers), so they accumulate straight into FP64:
+// y for the first kDirectY iterations, x0 until the first reliable update.  Later
+// contributions go to FP32 running sums, folded into FP64 every kFoldInterval iterations
+// (y) and at every reliable update (x0).
+constexpr int kDirectY = 32;
+constexpr int kFoldInterval = 8;
+
 size_t bytes_per_slot(const smpq_ctx *c, int prec, int NS) {
     const size_t v64 = 12 * 16 * c->vs, v32 = 6 * 16 * c->vs;
     if (prec == 0) return (3 + NS) * v64 + v64;
-    return (3 + NS) * v32 + 4 * v64;
+    return (5 + NS) * v32 + 4 * v64;
 }
 
 void ensure_workspace(smpq_ctx *c, int prec, int NS, int B) {
@@ -204,7 +212,7 @@ void ensure_workspace(smpq_ctx *c, int prec, int NS, int B) {
     const size_t vt = prec == 0 ? v64 : v32;
     if (w.prec != prec || w.NS != NS || w.B < B) {
         w.r.release(); w.tmp.release(); w.ap.release(); w.p.release(); w.y.release();
-        w.x0.release(); w.tmp64.release(); w.ap64.release();
+        w.x0.release(); w.tmp64.release(); w.ap64.release(); w.yacc.release(); w.x0acc.release();
         w.prec = prec;
         w.NS = NS;
         w.B = B;
@@ -217,6 +225,8 @@ void ensure_workspace(smpq_ctx *c, int prec, int NS, int B) {
             w.x0.ensure(v64 * B);
             w.tmp64.ensure(v64 * B);
             w.ap64.ensure(v64 * B);
+            w.yacc.ensure(v32 * B);
+            w.x0acc.ensure(v32 * B);
         }
     }
     const size_t pstride = partial_stride(g);
@@ -322,8 +332,9 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
     const int np_unit = unit_parts(prec, g), np_ds = dslash_partials(prec, g, lgr);
     Slots act{S.list, S.count, 0};
 
-    launch_cg_init(prec, g, src, nslots, NS, c->zolo.c0, w.r.p, w.p.p, w.y.as<double2>(),
-                   prec == 1 ? w.x0.as<double2>() : nullptr, S.partial, s);
+    const bool mixed = prec == 1;
+    launch_cg_init(prec, g, src, nslots, NS, c->zolo.c0, w.r.p, w.p.p, w.y.as<double2>(), mixed ? w.yacc.p : nullptr,
+                   mixed ? w.x0.as<double2>() : nullptr, mixed ? w.x0acc.p : nullptr, S.partial, s);
     launch_scalars_init(S, np_unit, s);
     launch_compact(S, s);
     HIPCHK(hipGetLastError());
@@ -347,12 +358,18 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
             launch_r_update(prec, g, S, w.r.p, w.ap.p, s);
             launch_scalars_beta(S, np_unit, s);
             if (c->timing) HIPCHK(hipEventRecord(c->t_update.next(), s));
-            launch_shift_update(prec, g, S, w.r.p, w.p.p, w.y.as<double2>(),
-                                prec == 1 ? w.x0.as<double2>() : nullptr, s);
+            const bool y64 = !mixed || iter < kDirectY;
+            const bool x64 = mixed && (c->reliable == 0 || iter < c->reliable);
+            launch_shift_update(prec, g, S, w.r.p, w.p.p, y64 ? w.y.p : w.yacc.p, y64,
+                                mixed ? (x64 ? w.x0.p : w.x0acc.p) : nullptr, x64, s);
             if (c->timing) HIPCHK(hipEventRecord(c->t_update.next(), s));
             launch_compact(S, s);
             ++iter;
-            if (prec == 1 && c->reliable > 0 && iter % c->reliable == 0) {
+            const bool reliable_now = mixed && c->reliable > 0 && iter % c->reliable == 0;
+            if (mixed && iter > kDirectY && (reliable_now || iter % kFoldInterval == 0))
+                launch_fold(g, act, nslots, w.y.as<double2>(), w.yacc.p, w.x0.as<double2>(),
+                            reliable_now ? w.x0acc.p : nullptr, s);
+            if (reliable_now) {
                 launch_dslash(0, false, lgr_for(0), 0, c->U64.p, w.x0.p, rs64, 0, w.tmp64.p, rs64, nullptr, 0, 0, g, c->kappa,
                               0.0, act, nslots, nullptr, s);
                 launch_dslash(0, true, lgr_for(0), 1, c->U64.p, w.tmp64.p, rs64, 0, w.ap64.p, rs64, w.x0.p, rs64, 0, g,
@@ -369,7 +386,12 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
             st->dslash_ms += c->t_dslash.collect();
             st->update_ms += c->t_update.collect();
         }
-        if (*c->h_count == 0) break;
+        if (*c->h_count == 0) {
+            if (mixed)   // the slots finished at different iterations: fold every one of them
+                launch_fold(g, Slots{nullptr, nullptr, nslots}, nslots, w.y.as<double2>(), w.yacc.p,
+                            w.x0.as<double2>(), w.x0acc.p, s);
+            break;
+        }
         if (iter >= c->max_iter)
             throw Fail{SMPQ_ENOCONV, "multi-shift CG did not converge within max_iter = " + std::to_string(c->max_iter)};
     }
@@ -396,10 +418,24 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
         // second stencil also reads p for the "+ s0 p" term.  Per active slot-iteration.
         st->dslash_bytes += (double)iter * 2.0 * link_site * V + (double)res.active * V * 12.0 * s_t * 5.0;
         st->dslash_launches += 2LL * iter;
-        // update kernel: r read, y (FP64) read+write, x0 (FP64) read+write in mixed
-        // precision, every listed p_i read, every updated p_i written.
-        const double per_active = 12.0 * s_t + 2.0 * 192.0 + (prec == 1 ? 2.0 * 192.0 : 0.0);
-        st->update_bytes += V * ((double)res.active * per_active + (double)(res.entries + res.pupd) * 12.0 * s_t);
+        // update kernel: r read, the running sum read+write and, in the FP32 path, the running
+        // base solution read+write (both in the iteration precision), every listed p_i read,
+        // every updated p_i written.
+        // All slots of a batch start together, so slot k ran iterations 0 .. iters[k]-1: the
+        // first min(iters, kDirectY) of them summed y in FP64, the first min(iters, reliable)
+        // summed x0 in FP64 (FP32 path).
+        double acc_bytes = 0.0;
+        for (int k = 0; k < nslots; ++k) {
+            const double n = iters[k];
+            if (prec == 0) {
+                acc_bytes += n * 2.0 * 192.0;
+            } else {
+                const double ny = std::min<double>(n, kDirectY);
+                const double nx = c->reliable > 0 ? std::min<double>(n, c->reliable) : n;
+                acc_bytes += ny * 2.0 * 192.0 + (n - ny) * 2.0 * 96.0 + nx * 2.0 * 192.0 + (n - nx) * 2.0 * 96.0;
+            }
+        }
+        st->update_bytes += V * ((double)res.active * 12.0 * s_t + acc_bytes + (double)(res.entries + res.pupd) * 12.0 * s_t);
         st->update_launches += iter;
         st->n_reliable_updates += res.n_reliable;
         st->shift_updates += res.entries;

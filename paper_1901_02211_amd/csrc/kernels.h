@@ -69,14 +69,21 @@ int dslash_partials(int prec, const Geom &g, int lgR);   // ... of the stencil o
 int unit_parts(int prec, const Geom &g);        // partials per slot written by element-wise kernels
 size_t partial_stride(const Geom &g);           // slot stride of the partial buffer (>= both)
 
+// r = p_i = b, y = c0 b; FP32 path: yacc = 0, x0 = 0, x0acc = 0 (pass null otherwise)
 void launch_cg_init(int prec, const Geom &g, const Source &src, int nslots, int NS, double c0, void *r,
-                    void *p, double2 *y, double2 *x0, double *partial, hipStream_t st);
+                    void *p, double2 *y, void *yacc, double2 *x0, void *x0acc, double *partial, hipStream_t st);
 void launch_scalars_init(const MSState &s, int npart, hipStream_t st);
 void launch_scalars_alpha(const MSState &s, int npart, hipStream_t st);
 void launch_r_update(int prec, const Geom &g, const MSState &s, void *r, const void *ap, hipStream_t st);
 void launch_scalars_beta(const MSState &s, int npart, hipStream_t st);
-void launch_shift_update(int prec, const Geom &g, const MSState &s, const void *r, void *p, double2 *y,
-                         double2 *x0, hipStream_t st);
+// Shift update.  yt receives sum_i c_i alpha^i p_i: the FP64 y when y64, else a running sum in
+// the storage precision of p.  xt (FP32 path only, else null) receives alpha p_base: the FP64
+// x0 when x64, else a running sum.  The FP64 path always uses y64 (and no xt).
+void launch_shift_update(int prec, const Geom &g, const MSState &s, const void *r, void *p, void *yt, bool y64,
+                         void *xt, bool x64, hipStream_t st);
+// FP32 path: y += yacc, yacc = 0 (and x0 += x0acc, x0acc = 0 when x0acc is not null)
+void launch_fold(const Geom &g, Slots sl, int max_slots, double2 *y, void *yacc, double2 *x0, void *x0acc,
+                 hipStream_t st);
 void launch_compact(const MSState &s, hipStream_t st);
 void launch_reliable(int prec, const Geom &g, const MSState &s, const Source &src, const double2 *ap64,
                      void *r, hipStream_t st);

@@ -426,11 +426,14 @@ __device__ __forceinline__ cpx<double> source_entry(const Source &src, int slot,
 
 int unit_parts(int prec, const Geom &g) { return (prec == 0 ? 12 : 6) * site_blocks(g); }
 
-// r = b, p_i = b for every shift, y = c0 b, x0 = 0; partial = |b|^2 per block.
+// r = b, p_i = b for every shift, y = c0 b (FP64), running accumulators yacc = x0acc = 0 in the
+// iteration precision (FP32 path only; the FP64 path accumulates into y directly and has no x0);
+// partial = |b|^2 per block.
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_cg_init(Geom g, Source src, int NS, double c0,
                                                     typename Store<T>::vec *r, typename Store<T>::vec *p, double2 *y,
-                                                    double2 *x0, double *partial, size_t pstride) {
+                                                    typename Store<T>::vec *yacc, double2 *x0,
+                                                    typename Store<T>::vec *x0acc, double *partial, size_t pstride) {
     constexpr int C = Unit<T>::C;
     const int slot = blockIdx.y;
     const int nsb = site_blocks(g);
@@ -439,32 +442,35 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(Geom g, Source src, int NS, 
     const size_t rs = Store<T>::units * g.vs;
     double nrm = 0.0;
     if (s < g.V) {
-        cpx<T> bt[C];
+        cpx<T> bt[C], z[C];
         double2 *ys = y + (size_t)slot * 12 * g.vs;
 #pragma unroll
         for (int i = 0; i < C; ++i) {
             const int c = u * C + i;
             const cpx<double> b = source_entry(src, slot, c, s, g.vs);
             bt[i] = {(T)b.re, (T)b.im};
+            z[i] = {T(0), T(0)};
             nrm += (double)bt[i].re * bt[i].re + (double)bt[i].im * bt[i].im;
             st64(ys, g.vs, c, s, c0 * b);
             if (x0) st64(x0 + (size_t)slot * 12 * g.vs, g.vs, c, s, {0.0, 0.0});
         }
         Unit<T>::store(r + slot * rs, g.vs, u, s, bt);
         for (int i = 0; i < NS; ++i) Unit<T>::store(p + ((size_t)slot * NS + i) * rs, g.vs, u, s, bt);
+        if (yacc) Unit<T>::store(yacc + slot * rs, g.vs, u, s, z);
+        if (x0acc) Unit<T>::store(x0acc + slot * rs, g.vs, u, s, z);
     }
     block_partial(nrm, partial, (size_t)slot * pstride + blockIdx.x);
 }
 
 void launch_cg_init(int prec, const Geom &g, const Source &src, int nslots, int NS, double c0, void *r, void *p,
-                    double2 *y, double2 *x0, double *partial, hipStream_t st) {
+                    double2 *y, void *yacc, double2 *x0, void *x0acc, double *partial, hipStream_t st) {
     dim3 grid(unit_parts(prec, g), nslots);
     if (prec == 0)
         hipLaunchKernelGGL(k_cg_init<double>, grid, dim3(kBlock), 0, st, g, src, NS, c0, (double2 *)r, (double2 *)p, y,
-                           x0, partial, partial_stride(g));
+                           (double2 *)yacc, x0, (double2 *)x0acc, partial, partial_stride(g));
     else
         hipLaunchKernelGGL(k_cg_init<float>, grid, dim3(kBlock), 0, st, g, src, NS, c0, (float4 *)r, (float4 *)p, y,
-                           x0, partial, partial_stride(g));
+                           (float4 *)yacc, x0, (float4 *)x0acc, partial, partial_stride(g));
 }
 
 // ------------------------------------------------------------------ CG scalars (one wave per slot)
@@ -628,10 +634,14 @@ void launch_scalars_beta(const MSState &s, int npart, hipStream_t st) {
 }
 
 // For every entry of the slot's update list: y += c_i alpha^i p_i (old p_i), then
-// p_i = zeta^i r + beta^i p_i.  x0 += alpha p_base (mixed precision only).
-template <class T>
+// p_i = zeta^i r + beta^i p_i; x0 += alpha p_base where an x0 target is given (FP32 path).
+// The sums go either straight into the FP64 vectors (Y64 / X64) or into running sums in the
+// storage precision of p, which k_fold adds to FP64 every few iterations.  The FP64 path
+// always accumulates into y directly.
+template <class T, bool Y64, bool X64>
 __global__ __launch_bounds__(kBlock) void k_shift_update(Geom g, MSState S, const typename Store<T>::vec *r,
-                                                         typename Store<T>::vec *p, double2 *y, double2 *x0) {
+                                                         typename Store<T>::vec *p, void *yt, void *xt) {
+    using vec = typename Store<T>::vec;
     constexpr int C = Unit<T>::C;
     if ((int)blockIdx.y >= *S.count) return;
     const int slot = S.list[blockIdx.y];
@@ -641,31 +651,45 @@ __global__ __launch_bounds__(kBlock) void k_shift_update(Geom g, MSState S, cons
     if (s >= g.V) return;
     const int n = S.upd_n[slot];
     if (n == 0) return;
-    const size_t rs = Store<T>::units * g.vs;
-    double2 *ys = y + (size_t)slot * 12 * g.vs;
+    const size_t rs = Store<T>::units * g.vs, r64 = 12 * g.vs;
     cpx<T> rv[C];
     Unit<T>::load(r + slot * rs, g.vs, u, s, rv);
-    cpx<double> yv[C];
+    cpx<double> y64[C], x64[C];
+    cpx<T> yl[C], xl[C];
+    if constexpr (Y64) {
 #pragma unroll
-    for (int i = 0; i < C; ++i) yv[i] = ld64(ys, g.vs, u * C + i, s);
+        for (int j = 0; j < C; ++j) y64[j] = ld64((double2 *)yt + slot * r64, g.vs, u * C + j, s);
+    } else {
+        Unit<T>::load((vec *)yt + slot * rs, g.vs, u, s, yl);
+    }
+    bool x_touched = false;
 #pragma unroll 1
     for (int e = 0; e < n; ++e) {
         const int k = slot * S.NS + e;
         const int i = S.upd_idx[k];
         const double cy = S.upd_cy[k];
-        typename Store<T>::vec *pp = p + ((size_t)slot * S.NS + i) * rs;
+        vec *pp = p + ((size_t)slot * S.NS + i) * rs;
         cpx<T> pv[C];
         Unit<T>::load(pp, g.vs, u, s, pv);
         if (cy != 0.0) {
 #pragma unroll
-            for (int j = 0; j < C; ++j) yv[j] = yv[j] + cy * cpx<double>{(double)pv[j].re, (double)pv[j].im};
-            if (x0 && i == S.i0) {
+            for (int j = 0; j < C; ++j) {
+                if constexpr (Y64) y64[j] = y64[j] + cy * cpx<double>{(double)pv[j].re, (double)pv[j].im};
+                else yl[j] = yl[j] + (T)cy * pv[j];
+            }
+            if (xt && i == S.i0) {
                 const double a = S.alpha[slot];
-                double2 *xs = x0 + (size_t)slot * 12 * g.vs;
+                x_touched = true;
+                if constexpr (X64) {
 #pragma unroll
-                for (int j = 0; j < C; ++j)
-                    st64(xs, g.vs, u * C + j, s,
-                         ld64(xs, g.vs, u * C + j, s) + a * cpx<double>{(double)pv[j].re, (double)pv[j].im});
+                    for (int j = 0; j < C; ++j)
+                        x64[j] = ld64((double2 *)xt + slot * r64, g.vs, u * C + j, s) +
+                                 a * cpx<double>{(double)pv[j].re, (double)pv[j].im};
+                } else {
+                    Unit<T>::load((vec *)xt + slot * rs, g.vs, u, s, xl);
+#pragma unroll
+                    for (int j = 0; j < C; ++j) xl[j] = xl[j] + (T)a * pv[j];
+                }
             }
         }
         if (S.upd_pupd[k]) {
@@ -675,19 +699,73 @@ __global__ __launch_bounds__(kBlock) void k_shift_update(Geom g, MSState S, cons
             Unit<T>::store(pp, g.vs, u, s, pv);
         }
     }
+    if constexpr (Y64) {
 #pragma unroll
-    for (int i = 0; i < C; ++i) st64(ys, g.vs, u * C + i, s, yv[i]);
+        for (int j = 0; j < C; ++j) st64((double2 *)yt + slot * r64, g.vs, u * C + j, s, y64[j]);
+    } else {
+        Unit<T>::store((vec *)yt + slot * rs, g.vs, u, s, yl);
+    }
+    if (x_touched) {
+        if constexpr (X64) {
+#pragma unroll
+            for (int j = 0; j < C; ++j) st64((double2 *)xt + slot * r64, g.vs, u * C + j, s, x64[j]);
+        } else {
+            Unit<T>::store((vec *)xt + slot * rs, g.vs, u, s, xl);
+        }
+    }
 }
 
-void launch_shift_update(int prec, const Geom &g, const MSState &s, const void *r, void *p, double2 *y, double2 *x0,
-                         hipStream_t st) {
+void launch_shift_update(int prec, const Geom &g, const MSState &s, const void *r, void *p, void *yt, bool y64,
+                         void *xt, bool x64, hipStream_t st) {
     dim3 grid(unit_parts(prec, g), s.B);
-    if (prec == 0)
-        hipLaunchKernelGGL(k_shift_update<double>, grid, dim3(kBlock), 0, st, g, s, (const double2 *)r, (double2 *)p,
-                           y, x0);
-    else
-        hipLaunchKernelGGL(k_shift_update<float>, grid, dim3(kBlock), 0, st, g, s, (const float4 *)r, (float4 *)p, y,
-                           x0);
+    if (prec == 0) {
+        hipLaunchKernelGGL((k_shift_update<double, true, true>), grid, dim3(kBlock), 0, st, g, s, (const double2 *)r,
+                           (double2 *)p, yt, xt);
+        return;
+    }
+#define SMPQ_SU(Y, X)                                                                                           \
+    hipLaunchKernelGGL((k_shift_update<float, Y, X>), grid, dim3(kBlock), 0, st, g, s, (const float4 *)r, (float4 *)p, \
+                       yt, xt)
+    if (y64 && x64) SMPQ_SU(true, true);
+    else if (y64) SMPQ_SU(true, false);
+    else if (x64) SMPQ_SU(false, true);
+    else SMPQ_SU(false, false);
+#undef SMPQ_SU
+}
+
+// FP32 path: y += yacc, yacc = 0 (and x0 += x0acc, x0acc = 0 when x0acc is given), for the
+// listed slots, in FP64.
+__global__ __launch_bounds__(kBlock) void k_fold(Geom g, Slots sl, double2 *y, float4 *yacc, double2 *x0,
+                                                 float4 *x0acc) {
+    if ((int)blockIdx.y >= slot_count(sl)) return;
+    const int slot = slot_of(sl, blockIdx.y);
+    const int nsb = site_blocks(g);
+    const int u = blockIdx.x / nsb;
+    const int s = (blockIdx.x % nsb) * kBlock + threadIdx.x;
+    if (s >= g.V) return;
+    const size_t rs = 6 * g.vs, ys = 12 * g.vs;
+    const cpx<float> z[2] = {{0.f, 0.f}, {0.f, 0.f}};
+    cpx<float> a[2];
+    Unit<float>::load(yacc + slot * rs, g.vs, u, s, a);
+    double2 *yp = y + slot * ys;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+        st64(yp, g.vs, 2 * u + j, s, ld64(yp, g.vs, 2 * u + j, s) + cpx<double>{(double)a[j].re, (double)a[j].im});
+    Unit<float>::store(yacc + slot * rs, g.vs, u, s, z);
+    if (x0acc) {
+        Unit<float>::load(x0acc + slot * rs, g.vs, u, s, a);
+        double2 *xp = x0 + slot * ys;
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            st64(xp, g.vs, 2 * u + j, s, ld64(xp, g.vs, 2 * u + j, s) + cpx<double>{(double)a[j].re, (double)a[j].im});
+        Unit<float>::store(x0acc + slot * rs, g.vs, u, s, z);
+    }
+}
+
+void launch_fold(const Geom &g, Slots sl, int max_slots, double2 *y, void *yacc, double2 *x0, void *x0acc,
+                 hipStream_t st) {
+    dim3 grid(unit_parts(1, g), max_slots);
+    hipLaunchKernelGGL(k_fold, grid, dim3(kBlock), 0, st, g, sl, y, (float4 *)yacc, x0, (float4 *)x0acc);
 }
 
 // Ordered list of the slots still iterating.

@@ -1,0 +1,111 @@
+"""GPU parity against stored oracle values (tests/golden/*.npz, written by make_golden.py).
+
+Workloads (smpq_inputs.WORKLOADS):
+  noise4      4^4 near-identity eps 0.3: SMP r = 2 full map, full point-source trace (3072
+              sources), dense exact density
+  flux8       8^4 U(1) flux (1,1) + noise 0.1 + random gauge: SMP r = 2 full map, point
+              sources on the seeded 64-site subset, SMP r = 4 on three classes
+  noise16x32  16^3 x 32 eps 0.2: SMP r = 4 classes 0 and 129, computed inside one full-size
+              batch (the batch size the benchmark uses)
+Tolerances: FP64 path max |dq| <= 1e-10; mixed path max |dq| <= 1e-5 and |dQ| <= 1e-4.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import paper_1901_02211_amd as smpq
+import smpq_inputs as si
+from conftest import GOLDEN
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _golden(name):
+    return np.load(os.path.join(GOLDEN, f"{name}.npz"))
+
+
+def _ctx(workload, prec=smpq.SMPQ_FP64):
+    w = si.WORKLOADS[workload]
+    z = _golden(f"{workload}_zolo")
+    c = smpq.smpq_create(w["dims"], 0)
+    smpq.smpq_load_gauge(c, si.workload(workload))
+    smpq.smpq_set_zolotarev(c, int(z["n_poles"]), float(z["lam_min"]), float(z["lam_max"]))
+    smpq.smpq_set_solver(c, prec, TOL, 10000, 50)
+    return c
+
+
+@pytest.mark.parametrize("prec", [smpq.SMPQ_FP64, smpq.SMPQ_MIXED_FP32])
+def test_noise4_smp_full_map(prec):
+    print(f"noise4 SMP r=2 full map, precision {prec}", flush=True)
+    g = _golden("noise4_smp")
+    c = _ctx("noise4", prec)
+    smpq.smpq_set_scheme(c, (2, 2, 2, 2), 0)
+    q, qi, Q, st = smpq.smpq_compute_qx(c)
+    tol = 1e-10 if prec == smpq.SMPQ_FP64 else 1e-5
+    assert np.abs(q - g["qx"]).max() < tol
+    assert np.abs(qi - g["qx_imag"]).max() < tol
+    assert abs(Q - g["qx"].sum()) < (1e-9 if prec == smpq.SMPQ_FP64 else 1e-4)
+    assert st["n_sources"] == 192
+
+
+def test_noise4_point_trace_and_dense():
+    print("noise4 full point-source trace (3072 sources)", flush=True)
+    g = _golden("noise4_point")
+    d = _golden("noise4_smp")
+    c = _ctx("noise4")
+    q, st = smpq.smpq_compute_qx_points(c, np.arange(256))
+    assert np.abs(q - g["qx"]).max() < 1e-10
+    # the exact density from the dense sign function (Eq. 5) and the integer charge
+    assert np.abs(q - d["qx_exact"]).max() < 1e-10
+    assert abs(q.sum() - float(d["Q_exact"])) < 1e-9
+    assert st["n_sources"] == 3072
+
+
+@pytest.mark.parametrize("prec", [smpq.SMPQ_FP64, smpq.SMPQ_MIXED_FP32])
+def test_flux8_smp_full_map(prec):
+    print(f"flux8 SMP r=2 full map, precision {prec}", flush=True)
+    g = _golden("flux8_smp2")
+    c = _ctx("flux8", prec)
+    smpq.smpq_set_scheme(c, (2, 2, 2, 2), 0)
+    q, qi, Q, st = smpq.smpq_compute_qx(c)
+    tol = 1e-10 if prec == smpq.SMPQ_FP64 else 1e-5
+    assert np.abs(q - g["qx"]).max() < tol
+    assert abs(Q - g["qx"].sum()) < (1e-9 if prec == smpq.SMPQ_FP64 else 1e-4)
+
+
+def test_flux8_point_subset():
+    print("flux8 point sources on the 64-site subset", flush=True)
+    g = _golden("flux8_point")
+    sites = si.subset_sites("flux8")
+    assert np.array_equal(sites, g["classes"])
+    c = _ctx("flux8")
+    q, st = smpq.smpq_compute_qx_points(c, sites)
+    assert np.abs(q - g["qx"][sites]).max() < 1e-10
+
+
+def test_flux8_smp4_classes():
+    print("flux8 SMP r=4 classes 0, 85, 255", flush=True)
+    g = _golden("flux8_smp4_part")
+    c = _ctx("flux8")
+    smpq.smpq_set_scheme(c, (4, 4, 4, 4), 0)
+    q, qi, st = smpq.smpq_compute_qx_classes(c, list(g["classes"]))
+    assert np.abs(q - g["qx"]).max() < 1e-10
+
+
+@pytest.mark.parametrize("prec", [smpq.SMPQ_FP64, smpq.SMPQ_MIXED_FP32])
+def test_noise16x32_sampled_classes(prec):
+    print(f"16^3x32 SMP r=4 classes 0, 129 in a full-size batch, precision {prec}", flush=True)
+    g = _golden("noise16x32_part")
+    c = _ctx("noise16x32", prec)
+    smpq.smpq_set_scheme(c, (4, 4, 4, 4), 0)
+    col = smpq.smpq_get_coloring(c)
+    classes = [0, 129] + [k for k in range(1, 63)]          # 64 classes = 768 right-hand sides
+    q, qi, st = smpq.smpq_compute_qx_classes(c, classes)
+    assert st["n_batches"] == 1 and st["n_sources"] == 768
+    mask = np.isin(col, [0, 129])
+    tol = 1e-10 if prec == smpq.SMPQ_FP64 else 1e-5
+    assert np.abs(q[mask] - g["qx"][mask]).max() < tol
+    assert np.abs(qi[mask] - g["qx_imag"][mask]).max() < tol
