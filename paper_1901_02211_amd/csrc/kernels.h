@@ -66,6 +66,7 @@ void launch_dslash(int prec, bool dag, int lgR, int epi, const void *U, const vo
 __host__ __device__ int site_blocks(const Geom &g);               // blocks of 256 sites
 int dslash_parts(const Geom &g, int lgR);       // partials per slot of the FP64 stencil epilogue
 int dslash_partials(int prec, const Geom &g, int lgR);   // ... of the stencil of precision prec
+bool plane_tiled(const Geom &g);                 // FP32 stencil uses the 256-site plane tile
 int unit_parts(int prec, const Geom &g);        // partials per slot written by element-wise kernels
 size_t partial_stride(const Geom &g);           // slot stride of the partial buffer (>= both)
 

@@ -3,7 +3,8 @@
 //  k_dslash        Wilson stencil D_W / D_W^dag (section 1, Eq. 3) in FP64: R right-hand
 //                  sides interleaved over the lanes of a block share each link fetch
 //  k_dslash_f32    the FP32 stencil: one site per thread, its eight links held in registers
-//                  for several right-hand sides; both take an optional epilogue
+//                  for several right-hand sides (k_dslash_f32_plane: the same with one
+//                  16x16 xy-plane per block staged in LDS); all take an optional epilogue
 //                  "+ sigma aux" with a fused <aux, out> partial for H^2 + sigma (Eq. 4).
 //  k_cg_init ...   multi-shift CG for (D_W^dag D_W + q_i) x_i = b (Eqs. 6-8): residual
 //                  update, fused update of every active shift's search direction plus the
@@ -322,13 +323,141 @@ static void launch_dslash_t(const void *U, const void *in, size_t in_stride, siz
                        aux_extra, g, (T)kappa, (T)sigma, sl, lgR, nsb, partial, partial_stride(g));
 }
 
+// FP32 stencil for lattices whose xy-plane has exactly 256 sites: one block is one plane.
+// Per right-hand side the block stages its 256 spinors in LDS; the +-x and +-y neighbours are
+// read from there, the +-z and +-t neighbours from global memory (issued before the barrier),
+// and the links stay in registers across the right-hand sides as in k_dslash_f32.
+template <int NR, bool DAG, int EPI>
+__global__ __launch_bounds__(kBlock) void k_dslash_f32_plane(const float4 *__restrict__ U, const float4 *__restrict__ in,
+                                                             size_t in_stride, size_t in_extra,
+                                                             float4 *__restrict__ out, size_t out_stride,
+                                                             const float4 *__restrict__ aux, size_t aux_stride,
+                                                             size_t aux_extra, Geom g, float kappa, float sigma,
+                                                             Slots sl, int nsb, double *__restrict__ partial,
+                                                             size_t pstride) {
+    constexpr int SF = DAG ? -1 : 1;
+    __shared__ float4 tile[6][kBlock];
+    const int L = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int sb = L % nsb, rg = L / nsb;
+    const int cnt = slot_count(sl);
+    const int k0 = rg * NR;
+    if (k0 >= cnt) return;  // uniform over the block
+    const int base = sb * kBlock;
+    const int s = base + threadIdx.x;  // every site is valid: V is a multiple of the plane
+    const Nbr nb = neighbours(s, g.nx, g.ny, g.nz, g.nt);
+    float4 lf[4][3], lb[4][3];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            lf[mu][j] = U[(size_t)(mu * 3 + j) * g.V + s];
+            lb[mu][j] = U[(size_t)(mu * 3 + j) * g.V + nb.bwd[mu]];
+        }
+    const int xf = nb.fwd[0] - base, xb = nb.bwd[0] - base, yf = nb.fwd[1] - base, yb = nb.bwd[1] - base;
+    double dot[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) dot[r] = 0.0;
+#pragma unroll 1
+    for (int r = 0; r < NR; ++r) {
+        const int k = k0 + r;
+        if (k >= cnt) break;  // uniform over the block
+        const int slot = slot_of(sl, k);
+        const float4 *src = in + slot * in_stride + in_extra;
+        __syncthreads();  // the previous right-hand side is done with the tile
+#pragma unroll
+        for (int j = 0; j < 6; ++j) tile[j][threadIdx.x] = src[j * g.vs + s];
+        cpx<float> acc[12], u[9], p[12], h[6], w[6];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[c] = {0.f, 0.f};
+#define SMPQ_GLOBAL_HOP(MU)                                                          \
+        unpack_rows(lf[MU][0], lf[MU][1], lf[MU][2], u);                             \
+        Store<float>::load(src, g.vs, nb.fwd[MU], p);                                \
+        project<MU, SF>(p, h);                                                       \
+        su3_mul(u, h, w);                                                            \
+        accumulate<MU, SF>(acc, w);                                                  \
+        unpack_rows(lb[MU][0], lb[MU][1], lb[MU][2], u);                             \
+        Store<float>::load(src, g.vs, nb.bwd[MU], p);                                \
+        project<MU, -SF>(p, h);                                                      \
+        su3_dag_mul(u, h, w);                                                        \
+        accumulate<MU, -SF>(acc, w);
+        SMPQ_GLOBAL_HOP(2)
+        SMPQ_GLOBAL_HOP(3)
+#undef SMPQ_GLOBAL_HOP
+        __syncthreads();  // the tile is complete
+#define SMPQ_TILE_LOAD(L, P)                                                         \
+        _Pragma("unroll") for (int j = 0; j < 6; ++j) {                              \
+            const float4 t_ = tile[j][L];                                            \
+            P[2 * j] = {t_.x, t_.y};                                                 \
+            P[2 * j + 1] = {t_.z, t_.w};                                             \
+        }
+#define SMPQ_TILE_HOP(MU, LF, LB)                                                    \
+        unpack_rows(lf[MU][0], lf[MU][1], lf[MU][2], u);                             \
+        SMPQ_TILE_LOAD(LF, p)                                                        \
+        project<MU, SF>(p, h);                                                       \
+        su3_mul(u, h, w);                                                            \
+        accumulate<MU, SF>(acc, w);                                                  \
+        unpack_rows(lb[MU][0], lb[MU][1], lb[MU][2], u);                             \
+        SMPQ_TILE_LOAD(LB, p)                                                        \
+        project<MU, -SF>(p, h);                                                      \
+        su3_dag_mul(u, h, w);                                                        \
+        accumulate<MU, -SF>(acc, w);
+        SMPQ_TILE_HOP(0, xf, xb)
+        SMPQ_TILE_HOP(1, yf, yb)
+#undef SMPQ_TILE_HOP
+        cpx<float> v[12];
+        SMPQ_TILE_LOAD(threadIdx.x, v)
+#undef SMPQ_TILE_LOAD
+#pragma unroll
+        for (int c = 0; c < 12; ++c) v[c] = v[c] - kappa * acc[c];
+        if constexpr (EPI == 1) {
+            Store<float>::load(aux + slot * aux_stride + aux_extra, g.vs, s, p);
+            double d = 0.0;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                v[c] = v[c] + sigma * p[c];
+                d += (double)p[c].re * (double)v[c].re + (double)p[c].im * (double)v[c].im;
+            }
+            dot[r] = d;
+        }
+        Store<float>::store(out + slot * out_stride, g.vs, s, v);
+    }
+    if constexpr (EPI == 1) {
+        __shared__ double lds[NR][kBlock / 64];
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const double t = wave_sum(dot[r]);
+            if (lane == 0) lds[r][wv] = t;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < NR && k0 + (int)threadIdx.x < cnt) {
+            double t = 0.0;
+#pragma unroll
+            for (int i = 0; i < kBlock / 64; ++i) t += lds[threadIdx.x][i];
+            partial[(size_t)slot_of(sl, k0 + threadIdx.x) * pstride + sb] = t;
+        }
+    }
+}
+
+constexpr int kNRPlane = 8;  // right-hand sides per thread in the plane-tiled FP32 stencil
+
 constexpr int kNRF32 = 4;   // right-hand sides per thread in the FP32 stencil
+
+bool plane_tiled(const Geom &g) { return g.nx * g.ny == kBlock; }
 
 template <bool DAG, int EPI>
 static void launch_dslash_f32(const void *U, const void *in, size_t in_stride, size_t in_extra, void *out,
                               size_t out_stride, const void *aux, size_t aux_stride, size_t aux_extra, const Geom &g,
                               double kappa, double sigma, Slots sl, int max_slots, double *partial, hipStream_t st) {
     const int nsb = site_blocks(g);
+    if (plane_tiled(g)) {
+        const int ngr = (max_slots + kNRPlane - 1) / kNRPlane;
+        hipLaunchKernelGGL((k_dslash_f32_plane<kNRPlane, DAG, EPI>), dim3(nsb * ngr), dim3(kBlock), 0, st,
+                           (const float4 *)U, (const float4 *)in, in_stride, in_extra, (float4 *)out, out_stride,
+                           (const float4 *)aux, aux_stride, aux_extra, g, (float)kappa, (float)sigma, sl, nsb,
+                           partial, partial_stride(g));
+        return;
+    }
     const int ngr = (max_slots + kNRF32 - 1) / kNRF32;
     hipLaunchKernelGGL((k_dslash_f32<kNRF32, DAG, EPI>), dim3(nsb * ngr), dim3(kBlock), 0, st, (const float4 *)U,
                        (const float4 *)in, in_stride, in_extra, (float4 *)out, out_stride, (const float4 *)aux,

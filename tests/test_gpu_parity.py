@@ -50,6 +50,37 @@ def test_dslash_parity(dims, nrhs):
         assert np.abs(out32 - ref).max() <= 2e-6 * scale
 
 
+@pytest.mark.parametrize("dims", [(16, 16, 2, 2), (16, 16, 3, 2)])
+@pytest.mark.parametrize("nrhs", [1, 9])
+def test_dslash_parity_plane_tiled(dims, nrhs):
+    """16x16 xy-planes take the FP32 kernel that stages one plane per block in LDS."""
+    print(f"plane-tiled dslash parity dims={dims} nrhs={nrhs}", flush=True)
+    lat = Lattice(dims)
+    U = si.near_identity_su3(dims, 0.5, 11)
+    psi = si.random_spinors(dims, nrhs, 12)
+    c = _ctx(dims, U)
+    for dag in (False, True):
+        ref = np.stack([apply_dw(U, lat, KAPPA, p, dagger=dag) for p in psi])
+        out32 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_MIXED_FP32)
+        assert np.abs(out32 - ref).max() <= 2e-6 * np.abs(ref).max()
+
+
+def test_qx_plane_tiled_mixed():
+    dims = (16, 16, 2, 2)
+    lat = Lattice(dims)
+    U = si.near_identity_su3(dims, 0.3, 13)
+    lo, hi = _zolo_interval(U, lat)
+    zo = zolotarev(14, lo, hi)
+    col, ncls = colouring(lat, (2, 2, 2, 2), 0)
+    ref = qx_probing(U, lat, KAPPA, zo, col, [5], TOL, 5000)
+    c = _ctx(dims, U)
+    smpq.smpq_set_scheme(c, (2, 2, 2, 2), 0)
+    smpq.smpq_set_zolotarev(c, 14, lo, hi)
+    smpq.smpq_set_solver(c, smpq.SMPQ_MIXED_FP32, TOL, 5000, 50)
+    q32 = smpq.smpq_compute_qx_classes(c, [5])[0]
+    assert np.abs(q32 - ref.real).max() < 1e-5
+
+
 def test_dslash_gamma5_hermiticity_and_adjoint():
     dims = (6, 4, 4, 6)
     U = si.near_identity_su3(dims, 0.5, 3)
