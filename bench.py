@@ -44,7 +44,8 @@ def kernel_source_hash():
 
 
 def measured_traffic(kernel):
-    """HBM bytes per launch from the committed counter summary, if it matches these kernels."""
+    """Counter-measured HBM bytes / algorithmic bytes of a kernel, from the committed summary,
+    if it was measured on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -168,14 +169,19 @@ def main():
     tr = measured_traffic(dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": tr["bytes_per_launch"] if tr else None,
-                "launch_ms": round(mean_ms, 4), "algorithmic_bytes_per_launch": bytes_launch}
+                "traffic": round(tr["traffic_over_algorithmic"] * bytes_launch) if tr else None,
+                "traffic_over_algorithmic": tr["traffic_over_algorithmic"] if tr else None,
+                "launch_ms": round(mean_ms, 4), "launches": kd["launches"],
+                "algorithmic_bytes_per_launch": bytes_launch}
 
     ds_insitu = st["dslash_bytes"] / (st["dslash_ms"] * 1e-3) / 1e9
+    trd = measured_traffic("dslash")
     print("bench: standalone stencil", file=sys.stderr, flush=True)
     ms32, by32 = smpq.smpq_bench_dslash(ctx, smpq.SMPQ_MIXED_FP32, 24, 4, 50)
     ms64, by64 = smpq.smpq_bench_dslash(ctx, smpq.SMPQ_FP64, 24, 4, 50)
     dslash = {"insitu_GBs": round(ds_insitu, 1), "insitu_frac": round(ds_insitu / HBM_PEAK_GBS, 4),
+              "launches": st["dslash_launches"], "algorithmic_bytes": st["dslash_bytes"],
+              "traffic_over_algorithmic": trd["traffic_over_algorithmic"] if trd else None,
               "standalone_fp32_n24_GBs": round(by32 / ms32 / 1e6, 1),
               "standalone_fp64_n24_GBs": round(by64 / ms64 / 1e6, 1),
               "standalone_note": "24 right-hand sides, 4 rotating input/output/link sets (> 1 GB)"}
