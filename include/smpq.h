@@ -198,6 +198,10 @@ smpq_status smpq_set_stream(smpq_ctx *ctx, void *stream);
  * kernels inside the solver; results appear in smpq_stats. */
 smpq_status smpq_set_timing(smpq_ctx *ctx, int enable);
 
+/* Run each group of CG iterations as a captured HIP graph (1, the default) or as eager
+ * launches (0).  Per-kernel timing (smpq_set_timing) always uses eager launches. */
+smpq_status smpq_set_graphs(smpq_ctx *ctx, int enable);
+
 /* Standalone timing of the Wilson stencil: `launches` applications of D_W in the
  * given precision to n_rhs right-hand sides, rotating through n_sets disjoint
  * input/output/link sets so that consecutive launches do not reuse cached data.

@@ -21,7 +21,7 @@ __all__ = [
     "smpq_get_zolotarev", "smpq_set_solver", "smpq_set_batch", "smpq_set_scheme",
     "smpq_set_point_scheme", "smpq_get_coloring", "smpq_apply_dw", "smpq_apply_dov",
     "smpq_compute_qx", "smpq_compute_qx_classes", "smpq_compute_qx_points", "smpq_prepare", "smpq_set_stream",
-    "smpq_set_timing", "smpq_bench_dslash",
+    "smpq_set_timing", "smpq_set_graphs", "smpq_bench_dslash",
 ]
 
 SMPQ_FP64 = 0
@@ -69,6 +69,7 @@ _SIG = {
     "smpq_prepare": (ctypes.c_int, [_vp]),
     "smpq_set_stream": (ctypes.c_int, [_vp, _vp]),
     "smpq_set_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "smpq_set_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
     "smpq_bench_dslash": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_double_p,
                                          _c_double_p]),
 }
@@ -266,6 +267,10 @@ def smpq_set_stream(ctx, stream_handle):
 
 def smpq_set_timing(ctx, enable=True):
     _check(ctx, _lib.smpq_set_timing(ctx.ptr, int(bool(enable))))
+
+
+def smpq_set_graphs(ctx, enable=True):
+    _check(ctx, _lib.smpq_set_graphs(ctx.ptr, int(bool(enable))))
 
 
 def smpq_bench_dslash(ctx, precision, n_rhs, n_sets, launches):

@@ -89,17 +89,28 @@ struct EventTimer {
         }
         return ev[used++];
     }
+    // record the next event on the stream; inside a stream capture it becomes an event node
+    // of the graph, recorded again at every replay
+    void record(hipStream_t s, bool captured) {
+        hipEvent_t e = next();
+        HIPCHK(captured ? hipEventRecordWithFlags(e, s, hipEventRecordExternal) : hipEventRecord(e, s));
+    }
     // sum of elapsed times of consecutive (start, stop) pairs; requires the stream synced
-    double collect() {
+    double sum() const {
         double ms = 0.0;
         for (size_t i = 0; i + 1 < used; i += 2) {
             float t = 0.f;
             HIPCHK(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
             ms += t;
         }
-        used = 0;
         return ms;
     }
+};
+
+// Event pools of one group of iterations; for a captured group they are fixed at capture
+// and read after every replay.
+struct GroupTimers {
+    EventTimer dslash, update;
 };
 
 }  // namespace
@@ -131,7 +142,16 @@ struct smpq_ctx {
     Workspace ws;
     DevMem qx, qxi, lz;
     bool timing = false;
-    EventTimer t_dslash, t_update;
+    bool use_graphs = true;
+    // captured groups of kGroup CG iterations, one per accumulation variant; rebuilt when
+    // anything they capture (workspace, links, coefficients, solver settings) changes
+    // [timed][variant]; the timed graphs carry event nodes around the stencil and update kernels
+    hipGraphExec_t graphs[2][4] = {{nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr}};
+    long long graph_gen[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}};
+    GroupTimers graph_timers[4];
+    GroupTimers eager_timers;
+    bool graph_timing_ok = true;
+    long long gen = 0;
     int *h_count = nullptr;     // pinned
     Geom geom() const { return Geom{dims[0], dims[1], dims[2], dims[3], V, vs}; }
 };
@@ -191,13 +211,14 @@ void spinor_from_device(const smpq_ctx *c, const std::vector<double> &stage, int
 // right-hand sides per stencil block (log2): links are shared by the lanes of one site
 int lgr_for(int prec) { return prec == 0 ? 1 : 2; }
 
-// FP32 path.  The first iterations build most of y and x0 (the residual falls by ~10^3 in
-// the first 50 iterations at these condition numbers), so they accumulate straight into FP64:
-// y for the first kDirectY iterations, x0 until the first reliable update.  Later
-// contributions go to FP32 running sums, folded into FP64 every kFoldInterval iterations
-// (y) and at every reliable update (x0).
-constexpr int kDirectY = 32;
-constexpr int kFoldInterval = 8;
+// The CG body runs in groups of kGroup iterations; the host reads the number of active
+// right-hand sides after each group.  FP32 path: the first iterations build most of y and x0
+// (the residual falls by ~10^3 in the first 50 iterations at these condition numbers), so they
+// accumulate straight into FP64: y for the first kDirectY iterations, x0 until the first
+// reliable update.  Later contributions go to FP32 running sums, folded into FP64 at the end
+// of every group (y) and at every reliable update (x0).
+constexpr int kGroup = 10;
+constexpr int kDirectY = 30;   // a multiple of kGroup
 
 size_t bytes_per_slot(const smpq_ctx *c, int prec, int NS) {
     const size_t v64 = 12 * 16 * c->vs, v32 = 6 * 16 * c->vs;
@@ -205,29 +226,32 @@ size_t bytes_per_slot(const smpq_ctx *c, int prec, int NS) {
     return (5 + NS) * v32 + 4 * v64;
 }
 
+// Device workspace for at least B right-hand sides of the given precision and shift count.
+// Everything, including the per-RHS CG state, is sized and laid out for the capacity w.B, the
+// slot range every launch covers; a new layout invalidates the captured graphs.
 void ensure_workspace(smpq_ctx *c, int prec, int NS, int B) {
     Workspace &w = c->ws;
     const Geom g = c->geom();
     const size_t v64 = 12 * 16 * c->vs, v32 = 6 * 16 * c->vs;
     const size_t vt = prec == 0 ? v64 : v32;
-    if (w.prec != prec || w.NS != NS || w.B < B) {
-        w.r.release(); w.tmp.release(); w.ap.release(); w.p.release(); w.y.release();
-        w.x0.release(); w.tmp64.release(); w.ap64.release(); w.yacc.release(); w.x0acc.release();
-        w.prec = prec;
-        w.NS = NS;
-        w.B = B;
-        w.r.ensure(vt * B);
-        w.tmp.ensure(vt * B);
-        w.ap.ensure(vt * B);
-        w.p.ensure(vt * B * NS);
-        w.y.ensure(v64 * B);
-        if (prec == 1) {
-            w.x0.ensure(v64 * B);
-            w.tmp64.ensure(v64 * B);
-            w.ap64.ensure(v64 * B);
-            w.yacc.ensure(v32 * B);
-            w.x0acc.ensure(v32 * B);
-        }
+    if (w.prec == prec && w.NS == NS && w.B >= B && w.S.rr) return;
+    c->gen++;
+    w.r.release(); w.tmp.release(); w.ap.release(); w.p.release(); w.y.release();
+    w.x0.release(); w.tmp64.release(); w.ap64.release(); w.yacc.release(); w.x0acc.release();
+    w.prec = prec;
+    w.NS = NS;
+    w.B = B;
+    w.r.ensure(vt * B);
+    w.tmp.ensure(vt * B);
+    w.ap.ensure(vt * B);
+    w.p.ensure(vt * B * NS);
+    w.y.ensure(v64 * B);
+    if (prec == 1) {
+        w.x0.ensure(v64 * B);
+        w.tmp64.ensure(v64 * B);
+        w.ap64.ensure(v64 * B);
+        w.yacc.ensure(v32 * B);
+        w.x0acc.ensure(v32 * B);
     }
     const size_t pstride = partial_stride(g);
     w.st_d.ensure(sizeof(double) * ((size_t)B * (5 + 3 * NS + 3 * NS)));
@@ -270,6 +294,7 @@ void ensure_workspace(smpq_ctx *c, int prec, int NS, int B) {
     S.list = w.list.as<int>();
     S.count = w.count.as<int>();
     S.NS = NS;
+    S.B = B;
 }
 
 int choose_batch(smpq_ctx *c, int prec, int NS, int total_slots, bool multiple_of_12) {
@@ -278,6 +303,8 @@ int choose_batch(smpq_ctx *c, int prec, int NS, int total_slots, bool multiple_o
     // memory already held by a workspace of the same shape is reusable
     size_t held = 0;
     if (c->ws.prec == prec && c->ws.NS == NS) held = bytes_per_slot(c, prec, NS) * c->ws.B;
+    else held = (size_t)c->ws.r.bytes + c->ws.tmp.bytes + c->ws.ap.bytes + c->ws.p.bytes + c->ws.y.bytes +
+                c->ws.x0.bytes + c->ws.tmp64.bytes + c->ws.ap64.bytes + c->ws.yacc.bytes + c->ws.x0acc.bytes;
     const double budget = 0.80 * (double)(freeb + held);
     long long B = (long long)(budget / (double)bytes_per_slot(c, prec, NS));
     if (c->max_rhs > 0) B = std::min<long long>(B, c->max_rhs);
@@ -310,12 +337,108 @@ struct BatchResult {
     long long iters_sum = 0, iters_max = 0, n_reliable = 0, entries = 0, pupd = 0, active = 0;
 };
 
+// One CG iteration for every active slot of the batch (capacity-sized launches; inactive
+// slots exit at once).  y64 / x64 select FP64 or FP32-running-sum accumulation (FP32 path).
+// With timers, events bracket the two stencil launches and the update launch.
+void enqueue_iteration(smpq_ctx *c, int prec, const MSState &S, bool y64, bool x64, GroupTimers *tm,
+                       bool captured) {
+    Workspace &w = c->ws;
+    const Geom g = c->geom();
+    hipStream_t s = c->stream;
+    const int NS = S.NS, B = S.B;
+    const size_t rs = (prec == 0 ? 12 : 6) * c->vs;
+    const void *U = prec == 0 ? c->U64.p : c->U32.p;
+    const int lgr = lgr_for(prec);
+    const int np_unit = unit_parts(prec, g), np_ds = dslash_partials(prec, g, lgr);
+    const bool mixed = prec == 1;
+    const Slots act{S.list, S.count, 0};
+    if (tm) tm->dslash.record(s, captured);
+    launch_dslash(prec, false, lgr, 0, U, w.p.p, NS * rs, S.i0 * rs, w.tmp.p, rs, nullptr, 0, 0, g, c->kappa, 0.0, act,
+                  B, nullptr, s);
+    if (tm) {
+        tm->dslash.record(s, captured);
+        tm->dslash.record(s, captured);
+    }
+    launch_dslash(prec, true, lgr, 1, U, w.tmp.p, rs, 0, w.ap.p, rs, w.p.p, NS * rs, S.i0 * rs, g, c->kappa,
+                  c->zolo.q[0], act, B, S.partial, s);
+    if (tm) tm->dslash.record(s, captured);
+    launch_scalars_alpha(S, np_ds, s);
+    launch_r_update(prec, g, S, w.r.p, w.ap.p, s);
+    launch_scalars_beta(S, np_unit, s);
+    if (tm) tm->update.record(s, captured);
+    launch_shift_update(prec, g, S, w.r.p, w.p.p, y64 ? w.y.p : w.yacc.p, y64,
+                        mixed ? (x64 ? w.x0.p : w.x0acc.p) : nullptr, x64, s);
+    if (tm) tm->update.record(s, captured);
+    launch_compact(S, s);
+}
+
+// One group of kGroup iterations starting at iteration it0, plus the fold of the FP32 running
+// sum of y at its end when the group used it.
+void enqueue_group(smpq_ctx *c, int prec, const MSState &S, int it0, GroupTimers *tm, bool captured) {
+    const bool mixed = prec == 1;
+    const bool y64 = !mixed || it0 < kDirectY;
+    const bool x64 = mixed && (c->reliable == 0 || it0 < c->reliable);
+    for (int gi = 0; gi < kGroup; ++gi) enqueue_iteration(c, prec, S, y64, x64, tm, captured);
+    if (mixed && !y64)
+        launch_fold(c->geom(), Slots{S.list, S.count, 0}, S.B, c->ws.y.as<double2>(), c->ws.yacc.p, nullptr, nullptr,
+                    c->stream);
+}
+
+// Graph variant of a group (0: FP64 path; 1-3: FP32 path with FP64 y and x0 / FP32 y and FP64 x0
+// / FP32 y and x0); -1 when the group is launched eagerly.
+int group_variant(const smpq_ctx *c, int prec, int it0) {
+    if (prec == 0) return 0;
+    if (c->reliable % kGroup != 0) return -1;   // x0 accumulation would switch inside a group
+    const bool y64 = it0 < kDirectY;
+    const bool x64 = c->reliable == 0 || it0 < c->reliable;
+    return y64 ? (x64 ? 1 : -1) : (x64 ? 2 : 3);
+}
+
+// Launch one group, as a captured graph where possible.  Returns the timers to read after
+// the stream has synchronised (null when not timing).
+GroupTimers *launch_group(smpq_ctx *c, int prec, const MSState &S, int it0) {
+    const bool timed = c->timing;
+    const int v = (!c->use_graphs || (timed && !c->graph_timing_ok)) ? -1 : group_variant(c, prec, it0);
+    if (v < 0) {
+        GroupTimers *tm = timed ? &c->eager_timers : nullptr;
+        if (tm) tm->dslash.used = tm->update.used = 0;
+        enqueue_group(c, prec, S, it0, tm, false);
+        return tm;
+    }
+    const int t = timed ? 1 : 0;
+    GroupTimers *tm = timed ? &c->graph_timers[v] : nullptr;
+    if (!c->graphs[t][v] || c->graph_gen[t][v] != c->gen) {
+        if (c->graphs[t][v]) HIPCHK(hipGraphExecDestroy(c->graphs[t][v]));
+        c->graphs[t][v] = nullptr;
+        if (tm) tm->dslash.used = tm->update.used = 0;
+        hipGraph_t graph = nullptr;
+        HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        try {
+            enqueue_group(c, prec, S, it0, tm, true);
+        } catch (const Fail &) {
+            (void)hipStreamEndCapture(c->stream, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            if (!timed) throw;
+            c->graph_timing_ok = false;   // no event nodes in graphs: time eagerly from now on
+            return launch_group(c, prec, S, it0);
+        }
+        HIPCHK(hipStreamEndCapture(c->stream, &graph));
+        const hipError_t e = hipGraphInstantiateWithFlags(&c->graphs[t][v], graph, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(e);
+        c->graph_gen[t][v] = c->gen;
+    }
+    HIPCHK(hipGraphLaunch(c->graphs[t][v], c->stream));
+    return tm;
+}
+
 // Multi-shift CG for the first nslots slots of the workspace, sources from src.
 // On return y[slot] = c_0 b + sum_i c_i x_i (Eq. 4 without the leading H).
 BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq_stats *st) {
     Workspace &w = c->ws;
     MSState S = w.S;
-    S.B = nslots;
+    S.B = w.B;           // launches are sized for the workspace capacity; slots >= nslots start done
     S.i0 = 0;            // q ascending: the smallest shift is the base system
     S.tol = c->tol;
     S.c = c->zc.as<double>();
@@ -324,67 +447,39 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
     const Geom g = c->geom();
     hipStream_t s = c->stream;
     const double s0 = c->zolo.q[0];
-    const size_t units = prec == 0 ? 12 : 6;
-    const size_t rs = units * c->vs;     // per-slot stride in storage units
     const size_t rs64 = 12 * c->vs;
-    const void *U = prec == 0 ? c->U64.p : c->U32.p;
-    const int lgr = lgr_for(prec);
-    const int np_unit = unit_parts(prec, g), np_ds = dslash_partials(prec, g, lgr);
-    Slots act{S.list, S.count, 0};
-
+    const int np_unit = unit_parts(prec, g);
+    const Slots act{S.list, S.count, 0};
     const bool mixed = prec == 1;
+
     launch_cg_init(prec, g, src, nslots, NS, c->zolo.c0, w.r.p, w.p.p, w.y.as<double2>(), mixed ? w.yacc.p : nullptr,
                    mixed ? w.x0.as<double2>() : nullptr, mixed ? w.x0acc.p : nullptr, S.partial, s);
-    launch_scalars_init(S, np_unit, s);
+    launch_scalars_init(S, np_unit, nslots, s);
     launch_compact(S, s);
     HIPCHK(hipGetLastError());
 
     BatchResult res;
-    const int G = 8;
     int iter = 0;
     for (;;) {
-        for (int gi = 0; gi < G; ++gi) {
-            if (c->timing) HIPCHK(hipEventRecord(c->t_dslash.next(), s));
-            launch_dslash(prec, false, lgr, 0, U, w.p.p, NS * rs, S.i0 * rs, w.tmp.p, rs, nullptr, 0, 0, g,
-                          c->kappa, 0.0, act, nslots, nullptr, s);
-            if (c->timing) {
-                HIPCHK(hipEventRecord(c->t_dslash.next(), s));
-                HIPCHK(hipEventRecord(c->t_dslash.next(), s));
-            }
-            launch_dslash(prec, true, lgr, 1, U, w.tmp.p, rs, 0, w.ap.p, rs, w.p.p, NS * rs, S.i0 * rs, g, c->kappa,
-                          s0, act, nslots, S.partial, s);
-            if (c->timing) HIPCHK(hipEventRecord(c->t_dslash.next(), s));
-            launch_scalars_alpha(S, np_ds, s);
-            launch_r_update(prec, g, S, w.r.p, w.ap.p, s);
-            launch_scalars_beta(S, np_unit, s);
-            if (c->timing) HIPCHK(hipEventRecord(c->t_update.next(), s));
-            const bool y64 = !mixed || iter < kDirectY;
-            const bool x64 = mixed && (c->reliable == 0 || iter < c->reliable);
-            launch_shift_update(prec, g, S, w.r.p, w.p.p, y64 ? w.y.p : w.yacc.p, y64,
-                                mixed ? (x64 ? w.x0.p : w.x0acc.p) : nullptr, x64, s);
-            if (c->timing) HIPCHK(hipEventRecord(c->t_update.next(), s));
-            launch_compact(S, s);
-            ++iter;
-            const bool reliable_now = mixed && c->reliable > 0 && iter % c->reliable == 0;
-            if (mixed && iter > kDirectY && (reliable_now || iter % kFoldInterval == 0))
-                launch_fold(g, act, nslots, w.y.as<double2>(), w.yacc.p, w.x0.as<double2>(),
-                            reliable_now ? w.x0acc.p : nullptr, s);
-            if (reliable_now) {
-                launch_dslash(0, false, lgr_for(0), 0, c->U64.p, w.x0.p, rs64, 0, w.tmp64.p, rs64, nullptr, 0, 0, g, c->kappa,
-                              0.0, act, nslots, nullptr, s);
-                launch_dslash(0, true, lgr_for(0), 1, c->U64.p, w.tmp64.p, rs64, 0, w.ap64.p, rs64, w.x0.p, rs64, 0, g,
-                              c->kappa, s0, act, nslots, S.partial, s);
-                launch_reliable(prec, g, S, src, w.ap64.as<double2>(), w.r.p, s);
-                launch_scalars_rr(S, np_unit, s);
-                res.n_reliable++;
-            }
+        GroupTimers *tm = launch_group(c, prec, S, iter);
+        iter += kGroup;
+        if (mixed && c->reliable > 0 && iter % c->reliable == 0) {
+            // residual replacement: fold the running base solution, r = b - (H^2 + s0) x0 in FP64
+            launch_fold(g, act, S.B, w.y.as<double2>(), w.yacc.p, w.x0.as<double2>(), w.x0acc.p, s);
+            launch_dslash(0, false, lgr_for(0), 0, c->U64.p, w.x0.p, rs64, 0, w.tmp64.p, rs64, nullptr, 0, 0, g,
+                          c->kappa, 0.0, act, S.B, nullptr, s);
+            launch_dslash(0, true, lgr_for(0), 1, c->U64.p, w.tmp64.p, rs64, 0, w.ap64.p, rs64, w.x0.p, rs64, 0, g,
+                          c->kappa, s0, act, S.B, S.partial, s);
+            launch_reliable(prec, g, S, src, w.ap64.as<double2>(), w.r.p, s);
+            launch_scalars_rr(S, np_unit, s);
+            res.n_reliable++;
         }
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(c->h_count, S.count, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        if (c->timing && st) {
-            st->dslash_ms += c->t_dslash.collect();
-            st->update_ms += c->t_update.collect();
+        if (tm && st) {
+            st->dslash_ms += tm->dslash.sum();
+            st->update_ms += tm->update.sum();
         }
         if (*c->h_count == 0) {
             if (mixed)   // the slots finished at different iterations: fold every one of them
@@ -416,8 +511,10 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
         const double V = c->V;
         // algorithmic bytes: D_W reads links once and each input/output spinor once; the
         // second stencil also reads p for the "+ s0 p" term.  Per active slot-iteration.
-        st->dslash_bytes += (double)iter * 2.0 * link_site * V + (double)res.active * V * 12.0 * s_t * 5.0;
-        st->dslash_launches += 2LL * iter;
+        // every slot starts at iteration 0, so iterations_max launches carried work
+        const double launched = (double)res.iters_max;
+        st->dslash_bytes += launched * 2.0 * link_site * V + (double)res.active * V * 12.0 * s_t * 5.0;
+        st->dslash_launches += 2LL * res.iters_max;
         // update kernel: r read, the running sum read+write and, in the FP32 path, the running
         // base solution read+write (both in the iteration precision), every listed p_i read,
         // every updated p_i written.
@@ -436,7 +533,7 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
             }
         }
         st->update_bytes += V * ((double)res.active * 12.0 * s_t + acc_bytes + (double)(res.entries + res.pupd) * 12.0 * s_t);
-        st->update_launches += iter;
+        st->update_launches += res.iters_max;
         st->n_reliable_updates += res.n_reliable;
         st->shift_updates += res.entries;
     }
@@ -521,6 +618,7 @@ void set_zolo(smpq_ctx *c, int n, double lo, double hi) {
         throw Fail{SMPQ_ENUMERIC, e.what()};
     }
     c->have_zolo = true;
+    c->gen++;
     if (c->device >= 0) upload_zolo(c);
 }
 
@@ -678,6 +776,9 @@ void smpq_destroy(smpq_ctx *c) {
     hipStream_t own = c->own;
     int *hc = c->h_count;
     int dev = c->device;
+    for (auto &row : c->graphs)
+        for (auto &gx : row)
+            if (gx) (void)hipGraphExecDestroy(gx);
     delete c;
     if (dev >= 0) {
         if (hc) (void)hipHostFree(hc);
@@ -747,6 +848,7 @@ smpq_status smpq_load_gauge(smpq_ctx *c, const double *U, size_t n) {
         HIPCHK(hipMemcpy(c->U64.p, u64.data(), sizeof(double) * V * 72, hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(c->U32.p, u32.data(), sizeof(float) * V * 48, hipMemcpyHostToDevice));
         c->have_gauge = true;
+        c->gen++;
     });
 }
 
@@ -754,6 +856,7 @@ smpq_status smpq_set_kappa(smpq_ctx *c, double kappa) {
     return guarded(c, [&] {
         if (!(kappa > 0.0 && kappa < 0.25)) throw Fail{SMPQ_EINVAL, "kappa must be in (0, 0.25)"};
         c->kappa = kappa;
+        c->gen++;
     });
 }
 
@@ -807,6 +910,7 @@ smpq_status smpq_set_solver(smpq_ctx *c, smpq_precision prec, double tol, int ma
         c->tol = tol;
         c->max_iter = max_iter;
         c->reliable = reliable;
+        c->gen++;
     });
 }
 
@@ -1007,11 +1111,16 @@ smpq_status smpq_set_stream(smpq_ctx *c, void *stream) {
         need_device(c);
         HIPCHK(hipStreamSynchronize(c->stream));
         c->stream = stream ? static_cast<hipStream_t>(stream) : c->own;
+        c->gen++;
     });
 }
 
 smpq_status smpq_set_timing(smpq_ctx *c, int enable) {
     return guarded(c, [&] { c->timing = enable != 0; });
+}
+
+smpq_status smpq_set_graphs(smpq_ctx *c, int enable) {
+    return guarded(c, [&] { c->use_graphs = enable != 0; });
 }
 
 smpq_status smpq_bench_dslash(smpq_ctx *c, smpq_precision prec, int n_rhs, int n_sets, int launches, double *ms,

@@ -73,7 +73,7 @@ size_t partial_stride(const Geom &g);           // slot stride of the partial bu
 // r = p_i = b, y = c0 b; FP32 path: yacc = 0, x0 = 0, x0acc = 0 (pass null otherwise)
 void launch_cg_init(int prec, const Geom &g, const Source &src, int nslots, int NS, double c0, void *r,
                     void *p, double2 *y, void *yacc, double2 *x0, void *x0acc, double *partial, hipStream_t st);
-void launch_scalars_init(const MSState &s, int npart, hipStream_t st);
+void launch_scalars_init(const MSState &s, int npart, int nslots, hipStream_t st);
 void launch_scalars_alpha(const MSState &s, int npart, hipStream_t st);
 void launch_r_update(int prec, const Geom &g, const MSState &s, void *r, const void *ap, hipStream_t st);
 void launch_scalars_beta(const MSState &s, int npart, hipStream_t st);

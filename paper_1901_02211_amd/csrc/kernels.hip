@@ -603,9 +603,10 @@ void launch_cg_init(int prec, const Geom &g, const Source &src, int nslots, int 
 }
 
 // ------------------------------------------------------------------ CG scalars (one wave per slot)
-__global__ void k_scalars_init(MSState S, int npart) {
+// Slots >= nslots are not part of this batch and start finished.
+__global__ void k_scalars_init(MSState S, int npart, int nslots) {
     const int slot = blockIdx.x;
-    const double rr = wave_sum_partials(S.partial + (size_t)slot * S.pstride, npart);
+    const double rr = slot < nslots ? wave_sum_partials(S.partial + (size_t)slot * S.pstride, npart) : 0.0;
     if (threadIdx.x != 0) return;
     S.rr[slot] = rr;
     S.bnorm[slot] = sqrt(rr);
@@ -629,8 +630,8 @@ __global__ void k_scalars_init(MSState S, int npart) {
     S.cnt_active[slot] = 0;
 }
 
-void launch_scalars_init(const MSState &s, int npart, hipStream_t st) {
-    hipLaunchKernelGGL(k_scalars_init, dim3(s.B), dim3(64), 0, st, s, npart);
+void launch_scalars_init(const MSState &s, int npart, int nslots, hipStream_t st) {
+    hipLaunchKernelGGL(k_scalars_init, dim3(s.B), dim3(64), 0, st, s, npart, nslots);
 }
 
 // alpha_k = |r_k|^2 / <p_k, A p_k>; for each active shift the new zeta.

@@ -223,3 +223,29 @@ def test_deterministic_and_errors():
     with pytest.raises(smpq.SmpqError) as e:
         smpq.smpq_load_gauge(c, bad)
     assert e.value.status == -7
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_graphs_match_eager_and_timed(prec):
+    """Captured groups of iterations (with and without event nodes) give bitwise the same q(x)
+    as eager launches; a smaller batch afterwards re-captures against the new layout."""
+    dims, lat, U, lo, hi = _ragged_setup()
+    c = _ctx(dims, U)
+    smpq.smpq_set_zolotarev(c, 14, lo, hi)
+    smpq.smpq_set_scheme(c, (2, 2, 2, 2), 0)
+    smpq.smpq_set_solver(c, prec, TOL, 5000, 50)
+    out = []
+    for graphs, timing in ((True, False), (False, False), (True, True), (False, True)):
+        smpq.smpq_set_graphs(c, graphs)
+        smpq.smpq_set_timing(c, timing)
+        q, qi, st = smpq.smpq_compute_qx_classes(c, [1, 6, 9])
+        out.append(q)
+        if timing:
+            assert st["dslash_ms"] > 0 and st["update_ms"] > 0 and st["dslash_launches"] > 0
+    for q in out[1:]:
+        assert np.array_equal(q, out[0])
+    smpq.smpq_set_graphs(c, True)
+    smpq.smpq_set_timing(c, False)
+    smpq.smpq_set_batch(c, 12)
+    q2 = smpq.smpq_compute_qx_classes(c, [1, 6, 9])[0]
+    assert np.abs(q2 - out[0]).max() < (1e-13 if prec == 0 else 1e-6)
