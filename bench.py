@@ -141,6 +141,9 @@ def main():
     # untimed set-up: workspace allocation and first launches of every kernel
     smpq.smpq_set_zolotarev(ctx, POLES, 0.14, 2.73)
     smpq.smpq_prepare(ctx)
+    tuning = smpq.smpq_autotune(ctx, 96)
+    print(f"bench: stencil variants (f32 kind, f32 rhs/thread, f64 log2 rhs/block) = {tuning}",
+          file=sys.stderr, flush=True)
     smpq.smpq_compute_qx_classes(ctx, [0])
     smpq.smpq_set_timing(ctx, True)
     for w in range(args.warmup):
@@ -222,7 +225,9 @@ def main():
                    "lattice": list(DIMS), "n_sources": st["n_sources"], "n_batches": st["n_batches"],
                    "kappa": KAPPA, "zolotarev_poles": POLES, "cg_tol": TOL, "reliable_interval": RELIABLE,
                    "precision": "FP32 stencil and CG body, FP64 scalars/reliable updates/accumulation",
-                   "classes": len(classes)},
+                   "classes": len(classes),
+                   "stencil_variants": {"f32_kind": ["site", "plane"][tuning[0]], "f32_rhs_per_thread": tuning[1],
+                                        "f64_rhs_per_block": 1 << tuning[2]}},
         "speedup_vs_fp64": round(fp64["s_per_map"] / (ms_per_step / 1000.0) * (len(classes) / ncls), 3),
         "roofline": roofline, "dslash": dslash, "fp64": fp64, "accuracy": accuracy,
         "breakdown_s": {"bounds": round(st["t_bounds_s"], 3), "solve": round(st["t_solve_s"], 3),

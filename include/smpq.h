@@ -210,6 +210,21 @@ smpq_status smpq_set_graphs(smpq_ctx *ctx, int enable);
 smpq_status smpq_bench_dslash(smpq_ctx *ctx, smpq_precision prec, int n_rhs, int n_sets,
                               int launches, double *ms_per_launch, double *bytes_per_launch);
 
+/* Choose the stencil variants for this lattice by timing them on n_rhs right-hand sides
+ * (two rotating buffer sets, 10 launches each): FP32 kind (0: one site per thread; 1: one
+ * 16x16 xy-plane per block staged in LDS, only when nx*ny = 256) with 2, 4 or 8 (kind 0) or
+ * 4, 8 or 16 (kind 1) right-hand sides per thread, and the FP64 stencil with 1, 2 or 4
+ * right-hand sides interleaved per block (*f64_lgr = log2).  The choice is kept by the
+ * context; outputs may be NULL.  Without this call the context uses kind 1 / 8 where the
+ * plane fits, else kind 0 / 4, and f64_lgr = 1. */
+smpq_status smpq_autotune(smpq_ctx *ctx, int n_rhs, int *f32_kind, int *f32_nr, int *f64_lgr);
+
+/* Select the stencil variants explicitly (same meaning as the outputs of smpq_autotune).
+ * SMPQ_EINVAL if a variant is not built or does not fit the lattice (kind 1 needs
+ * nx*ny = 256); the previous choice is then kept.  Results do not depend on the choice
+ * beyond rounding order in FP32. */
+smpq_status smpq_set_tuning(smpq_ctx *ctx, int f32_kind, int f32_nr, int f64_lgr);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,7 +21,8 @@ __all__ = [
     "smpq_get_zolotarev", "smpq_set_solver", "smpq_set_batch", "smpq_set_scheme",
     "smpq_set_point_scheme", "smpq_get_coloring", "smpq_apply_dw", "smpq_apply_dov",
     "smpq_compute_qx", "smpq_compute_qx_classes", "smpq_compute_qx_points", "smpq_prepare", "smpq_set_stream",
-    "smpq_set_timing", "smpq_set_graphs", "smpq_bench_dslash",
+    "smpq_set_timing", "smpq_set_graphs", "smpq_bench_dslash", "smpq_autotune",
+    "smpq_set_tuning",
 ]
 
 SMPQ_FP64 = 0
@@ -72,6 +73,8 @@ _SIG = {
     "smpq_set_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
     "smpq_bench_dslash": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_double_p,
                                          _c_double_p]),
+    "smpq_autotune": (ctypes.c_int, [_vp, ctypes.c_int, _c_int_p, _c_int_p, _c_int_p]),
+    "smpq_set_tuning": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
 }
 EXPORTS = tuple(_SIG)
 for _name, (_res, _args) in _SIG.items():
@@ -278,3 +281,14 @@ def smpq_bench_dslash(ctx, precision, n_rhs, n_sets, launches):
     _check(ctx, _lib.smpq_bench_dslash(ctx.ptr, int(precision), int(n_rhs), int(n_sets), int(launches),
                                        ctypes.byref(ms), ctypes.byref(by)))
     return ms.value, by.value
+
+
+def smpq_autotune(ctx, n_rhs=48):
+    """Returns (f32_kind, f32_nr, f64_lgr) chosen by timing on this lattice."""
+    k, n, l = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(ctx, _lib.smpq_autotune(ctx.ptr, int(n_rhs), ctypes.byref(k), ctypes.byref(n), ctypes.byref(l)))
+    return k.value, n.value, l.value
+
+
+def smpq_set_tuning(ctx, f32_kind, f32_nr, f64_lgr):
+    _check(ctx, _lib.smpq_set_tuning(ctx.ptr, int(f32_kind), int(f32_nr), int(f64_lgr)))

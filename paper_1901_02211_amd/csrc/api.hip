@@ -153,7 +153,9 @@ struct smpq_ctx {
     bool graph_timing_ok = true;
     long long gen = 0;
     int *h_count = nullptr;     // pinned
-    Geom geom() const { return Geom{dims[0], dims[1], dims[2], dims[3], V, vs}; }
+    // stencil variant (see Geom); defaults: plane tile where the xy-plane has 256 sites
+    int f32_kind = 0, f32_nr = 4, f64_lgr = 1;
+    Geom geom() const { return Geom{dims[0], dims[1], dims[2], dims[3], V, vs, f32_kind, f32_nr, f64_lgr}; }
 };
 
 namespace {
@@ -208,8 +210,6 @@ void spinor_from_device(const smpq_ctx *c, const std::vector<double> &stage, int
             }
 }
 
-// right-hand sides per stencil block (log2): links are shared by the lanes of one site
-int lgr_for(int prec) { return prec == 0 ? 1 : 2; }
 
 // The CG body runs in groups of kGroup iterations; the host reads the number of active
 // right-hand sides after each group.  FP32 path: the first iterations build most of y and x0
@@ -348,18 +348,17 @@ void enqueue_iteration(smpq_ctx *c, int prec, const MSState &S, bool y64, bool x
     const int NS = S.NS, B = S.B;
     const size_t rs = (prec == 0 ? 12 : 6) * c->vs;
     const void *U = prec == 0 ? c->U64.p : c->U32.p;
-    const int lgr = lgr_for(prec);
-    const int np_unit = unit_parts(prec, g), np_ds = dslash_partials(prec, g, lgr);
+    const int np_unit = unit_parts(prec, g), np_ds = dslash_partials(prec, g);
     const bool mixed = prec == 1;
     const Slots act{S.list, S.count, 0};
     if (tm) tm->dslash.record(s, captured);
-    launch_dslash(prec, false, lgr, 0, U, w.p.p, NS * rs, S.i0 * rs, w.tmp.p, rs, nullptr, 0, 0, g, c->kappa, 0.0, act,
+    launch_dslash(prec, false, 0, U, w.p.p, NS * rs, S.i0 * rs, w.tmp.p, rs, nullptr, 0, 0, g, c->kappa, 0.0, act,
                   B, nullptr, s);
     if (tm) {
         tm->dslash.record(s, captured);
         tm->dslash.record(s, captured);
     }
-    launch_dslash(prec, true, lgr, 1, U, w.tmp.p, rs, 0, w.ap.p, rs, w.p.p, NS * rs, S.i0 * rs, g, c->kappa,
+    launch_dslash(prec, true, 1, U, w.tmp.p, rs, 0, w.ap.p, rs, w.p.p, NS * rs, S.i0 * rs, g, c->kappa,
                   c->zolo.q[0], act, B, S.partial, s);
     if (tm) tm->dslash.record(s, captured);
     launch_scalars_alpha(S, np_ds, s);
@@ -466,9 +465,9 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
         if (mixed && c->reliable > 0 && iter % c->reliable == 0) {
             // residual replacement: fold the running base solution, r = b - (H^2 + s0) x0 in FP64
             launch_fold(g, act, S.B, w.y.as<double2>(), w.yacc.p, w.x0.as<double2>(), w.x0acc.p, s);
-            launch_dslash(0, false, lgr_for(0), 0, c->U64.p, w.x0.p, rs64, 0, w.tmp64.p, rs64, nullptr, 0, 0, g,
+            launch_dslash(0, false, 0, c->U64.p, w.x0.p, rs64, 0, w.tmp64.p, rs64, nullptr, 0, 0, g,
                           c->kappa, 0.0, act, S.B, nullptr, s);
-            launch_dslash(0, true, lgr_for(0), 1, c->U64.p, w.tmp64.p, rs64, 0, w.ap64.p, rs64, w.x0.p, rs64, 0, g,
+            launch_dslash(0, true, 1, c->U64.p, w.tmp64.p, rs64, 0, w.ap64.p, rs64, w.x0.p, rs64, 0, g,
                           c->kappa, s0, act, S.B, S.partial, s);
             launch_reliable(prec, g, S, src, w.ap64.as<double2>(), w.r.p, s);
             launch_scalars_rr(S, np_unit, s);
@@ -565,7 +564,7 @@ void lanczos(smpq_ctx *c, int steps, uint64_t seed, double *tmin, double *tmax) 
     const size_t v64 = 12 * 16 * c->vs;
     c->lz.ensure(4 * v64);
     double2 *v = c->lz.as<double2>(), *vp = v + 12 * c->vs, *w = vp + 12 * c->vs, *t = w + 12 * c->vs;
-    const int np_ds = dslash_parts(g, 0), np_unit = unit_parts(0, g);
+    const int np_ds = dslash_partials(0, g), np_unit = unit_parts(0, g);
     DevMem part;
     part.ensure(sizeof(double) * partial_stride(g));
     std::vector<double> h((size_t)24 * c->V), stage;
@@ -581,9 +580,9 @@ void lanczos(smpq_ctx *c, int steps, uint64_t seed, double *tmin, double *tmax) 
     Slots one{nullptr, nullptr, 1};
     double bprev = 0.0;
     for (int j = 0; j < steps; ++j) {
-        launch_dslash(0, false, 0, 0, c->U64.p, v, 0, 0, t, 0, nullptr, 0, 0, g, c->kappa, 0.0, one, 1, nullptr,
+        launch_dslash(0, false, 0, c->U64.p, v, 0, 0, t, 0, nullptr, 0, 0, g, c->kappa, 0.0, one, 1, nullptr,
                       c->stream);
-        launch_dslash(0, true, 0, 1, c->U64.p, t, 0, 0, w, 0, v, 0, 0, g, c->kappa, 0.0, one, 1, part.as<double>(),
+        launch_dslash(0, true, 1, c->U64.p, t, 0, 0, w, 0, v, 0, 0, g, c->kappa, 0.0, one, 1, part.as<double>(),
                       c->stream);
         HIPCHK(hipMemcpyAsync(hp.data(), part.p, sizeof(double) * np_ds, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
@@ -713,6 +712,45 @@ void finish_q(smpq_ctx *c, double *qx, double *qxi, smpq_stats *st) {
     }
 }
 
+// Mean duration of the stencil (D_W, epilogue 0) on n_rhs right-hand sides, rotating through
+// n_sets disjoint input/output/link sets; *bytes = algorithmic bytes per launch.
+double time_dslash(smpq_ctx *c, int p, int n_rhs, int n_sets, int launches, double *bytes) {
+    const Geom g = c->geom();
+    const size_t units = p == 0 ? 12 : 6;
+    const size_t vbytes = units * 16 * c->vs;
+    const size_t lbytes = (size_t)c->V * (p == 0 ? 72 * 8 : 48 * 4);
+    std::vector<DevMem> ins(n_sets), outs(n_sets), links(n_sets);
+    for (int k = 0; k < n_sets; ++k) {
+        ins[k].ensure(vbytes * n_rhs);
+        outs[k].ensure(vbytes * n_rhs);
+        links[k].ensure(lbytes);
+        HIPCHK(hipMemcpyAsync(links[k].p, p == 0 ? c->U64.p : c->U32.p, lbytes, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemsetAsync(ins[k].p, 0, vbytes * n_rhs, c->stream));
+    }
+    Slots sl{nullptr, nullptr, n_rhs};
+    auto one = [&](int i) {
+        const int k = i % n_sets;
+        launch_dslash(p, false, 0, links[k].p, ins[k].p, units * c->vs, 0, outs[k].p, units * c->vs, nullptr, 0, 0, g,
+                      c->kappa, 0.0, sl, n_rhs, nullptr, c->stream);
+    };
+    for (int i = 0; i < n_sets; ++i) one(i);   // warm-up
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, c->stream));
+    for (int i = 0; i < launches; ++i) one(i);
+    HIPCHK(hipEventRecord(e1, c->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(hipGetLastError());
+    const double u = p == 0 ? 16.0 : 8.0;
+    *bytes = (double)c->V * ((double)lbytes / c->V + (double)n_rhs * 24.0 * u);
+    return t / launches;
+}
+
 }  // namespace
 
 // =============================================================================== C ABI
@@ -748,6 +786,10 @@ smpq_status smpq_create(const int dims[4], int device, smpq_ctx **out) {
     c->V = (int)V;
     c->vs = (size_t)((V + 255) / 256) * 256;
     c->device = device;
+    if (dims[0] * dims[1] == 256) {
+        c->f32_kind = 1;
+        c->f32_nr = 8;
+    }
     if (device >= 0) {
         int n = 0;
         if (hipGetDeviceCount(&n) != hipSuccess || device >= n) {
@@ -984,13 +1026,13 @@ smpq_status smpq_apply_dw(smpq_ctx *c, const double *in, double *out, int n, int
         HIPCHK(hipMemcpyAsync(a.p, stage.data(), v64 * n, hipMemcpyHostToDevice, c->stream));
         Slots sl{nullptr, nullptr, n};
         if (prec == SMPQ_FP64) {
-            launch_dslash(0, dagger != 0, lgr_for(0), 0, c->U64.p, a.p, 12 * c->vs, 0, b.p, 12 * c->vs, nullptr, 0, 0, g,
+            launch_dslash(0, dagger != 0, 0, c->U64.p, a.p, 12 * c->vs, 0, b.p, 12 * c->vs, nullptr, 0, 0, g,
                           c->kappa, 0.0, sl, n, nullptr, c->stream);
         } else {
             a32.ensure(v32 * n);
             b32.ensure(v32 * n);
             launch_convert(1, g, a.p, a32.p, n, c->stream);
-            launch_dslash(1, dagger != 0, lgr_for(1), 0, c->U32.p, a32.p, 6 * c->vs, 0, b32.p, 6 * c->vs, nullptr, 0, 0, g,
+            launch_dslash(1, dagger != 0, 0, c->U32.p, a32.p, 6 * c->vs, 0, b32.p, 6 * c->vs, nullptr, 0, 0, g,
                           c->kappa, 0.0, sl, n, nullptr, c->stream);
             launch_convert(0, g, b32.p, b.p, n, c->stream);
         }
@@ -1025,7 +1067,7 @@ smpq_status smpq_apply_dov(smpq_ctx *c, const double *in, double *out, int n) {
             run_batch(c, prec, nb, src, nullptr);
             // D_ov b = b + gamma5 eps b = b + D_W y   (eps b = gamma5 D_W y)
             Slots sl{nullptr, nullptr, nb};
-            launch_dslash(0, false, lgr_for(0), 1, c->U64.p, c->ws.y.p, 12 * c->vs, 0,
+            launch_dslash(0, false, 1, c->U64.p, c->ws.y.p, 12 * c->vs, 0,
                           bout.as<double2>() + (size_t)k0 * 12 * c->vs, 12 * c->vs, bptr, 12 * c->vs, 0, g, c->kappa,
                           1.0, sl, nb, c->ws.partial.as<double>(), c->stream);
             HIPCHK(hipGetLastError());
@@ -1130,42 +1172,61 @@ smpq_status smpq_bench_dslash(smpq_ctx *c, smpq_precision prec, int n_rhs, int n
         if (prec != SMPQ_FP64 && prec != SMPQ_MIXED_FP32) throw Fail{SMPQ_EINVAL, "unknown precision"};
         need_device(c);
         if (!c->have_gauge) throw Fail{SMPQ_ESTATE, "no gauge field loaded"};
-        const int p = prec == SMPQ_FP64 ? 0 : 1;
-        const Geom g = c->geom();
-        const size_t units = p == 0 ? 12 : 6;
-        const size_t vbytes = units * 16 * c->vs;
-        const size_t lbytes = (size_t)c->V * (p == 0 ? 72 * 8 : 48 * 4);
-        std::vector<DevMem> ins(n_sets), outs(n_sets), links(n_sets);
-        for (int k = 0; k < n_sets; ++k) {
-            ins[k].ensure(vbytes * n_rhs);
-            outs[k].ensure(vbytes * n_rhs);
-            links[k].ensure(lbytes);
-            HIPCHK(hipMemcpyAsync(links[k].p, p == 0 ? c->U64.p : c->U32.p, lbytes, hipMemcpyDeviceToDevice,
-                                  c->stream));
-            HIPCHK(hipMemsetAsync(ins[k].p, 0, vbytes * n_rhs, c->stream));
+        *ms = time_dslash(c, prec == SMPQ_FP64 ? 0 : 1, n_rhs, n_sets, launches, bytes);
+    });
+}
+
+smpq_status smpq_set_tuning(smpq_ctx *c, int f32_kind, int f32_nr, int f64_lgr) {
+    return guarded(c, [&] {
+        Geom g = c->geom();
+        g.f32_kind = f32_kind;
+        g.f32_nr = f32_nr;
+        g.f64_lgr = f64_lgr;
+        if (!valid_tuning(0, g) || !valid_tuning(1, g))
+            throw Fail{SMPQ_EINVAL, "unsupported stencil variant for this lattice"};
+        c->f32_kind = f32_kind;
+        c->f32_nr = f32_nr;
+        c->f64_lgr = f64_lgr;
+        c->gen++;
+    });
+}
+
+smpq_status smpq_autotune(smpq_ctx *c, int n_rhs, int *f32_kind, int *f32_nr, int *f64_lgr) {
+    return guarded(c, [&] {
+        if (n_rhs < 1) throw Fail{SMPQ_EINVAL, "n_rhs must be >= 1"};
+        need_device(c);
+        if (!c->have_gauge) throw Fail{SMPQ_ESTATE, "no gauge field loaded"};
+        double by;
+        std::vector<std::pair<int, int>> cand = {{0, 2}, {0, 4}, {0, 8}};
+        if (plane_tileable(c->geom())) cand.insert(cand.end(), {{1, 4}, {1, 8}, {1, 16}});
+        double best = INFINITY;
+        std::pair<int, int> pick = {c->f32_kind, c->f32_nr};
+        for (auto kn : cand) {
+            c->f32_kind = kn.first;
+            c->f32_nr = kn.second;
+            const double t = time_dslash(c, 1, n_rhs, 2, 10, &by);
+            if (t < best) {
+                best = t;
+                pick = kn;
+            }
         }
-        Slots sl{nullptr, nullptr, n_rhs};
-        auto one = [&](int i) {
-            const int k = i % n_sets;
-            launch_dslash(p, false, lgr_for(p), 0, links[k].p, ins[k].p, units * c->vs, 0, outs[k].p, units * c->vs,
-                          nullptr, 0, 0, g, c->kappa, 0.0, sl, n_rhs, nullptr, c->stream);
-        };
-        for (int i = 0; i < n_sets; ++i) one(i);   // warm-up
-        hipEvent_t e0, e1;
-        HIPCHK(hipEventCreate(&e0));
-        HIPCHK(hipEventCreate(&e1));
-        HIPCHK(hipEventRecord(e0, c->stream));
-        for (int i = 0; i < launches; ++i) one(i);
-        HIPCHK(hipEventRecord(e1, c->stream));
-        HIPCHK(hipEventSynchronize(e1));
-        float t = 0.f;
-        HIPCHK(hipEventElapsedTime(&t, e0, e1));
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        HIPCHK(hipGetLastError());
-        *ms = t / launches;
-        const double u = p == 0 ? 16.0 : 8.0;
-        *bytes = (double)c->V * ((double)lbytes / c->V + (double)n_rhs * 24.0 * u);
+        c->f32_kind = pick.first;
+        c->f32_nr = pick.second;
+        best = INFINITY;
+        int lpick = c->f64_lgr;
+        for (int l = 0; l <= 2; ++l) {
+            c->f64_lgr = l;
+            const double t = time_dslash(c, 0, n_rhs, 2, 10, &by);
+            if (t < best) {
+                best = t;
+                lpick = l;
+            }
+        }
+        c->f64_lgr = lpick;
+        c->gen++;   // captured graphs used the previous variants
+        if (f32_kind) *f32_kind = c->f32_kind;
+        if (f32_nr) *f32_nr = c->f32_nr;
+        if (f64_lgr) *f64_lgr = c->f64_lgr;
     });
 }
 

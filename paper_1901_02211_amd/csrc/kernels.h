@@ -17,6 +17,10 @@ constexpr int kBlock = 256;
 struct Geom {
     int nx, ny, nz, nt, V;
     size_t vs;
+    // stencil tuning (chosen per lattice, see smpq_autotune): FP32 kernel kind (0: one site per
+    // thread, 1: 16x16 xy-plane per block in LDS), FP32 right-hand sides per thread, and log2 of
+    // the right-hand sides interleaved over the lanes of an FP64 block
+    int f32_kind, f32_nr, f64_lgr;
 };
 
 // Right-hand-side addressing: slot k of a launch uses offset (slot * slot_stride + extra)
@@ -57,16 +61,16 @@ enum { kStatusOK = 0, kStatusBreakdown = 1 };
 
 // out = in - kappa * hop(in)  [epi = 0]
 // out = in - kappa * hop(in) + sigma * aux, partial[slot][block] = Re <aux, out>  [epi = 1]
-// prec: 0 = FP64, 1 = FP32.  dag selects D_W^dag.  2^lgR right-hand sides share a block
-// (lgR <= 3); the epilogue writes dslash_parts(g, lgR) partials per slot.
-void launch_dslash(int prec, bool dag, int lgR, int epi, const void *U, const void *in, size_t in_stride,
+// prec: 0 = FP64, 1 = FP32.  dag selects D_W^dag.  The kernel variant comes from g's tuning
+// fields; the epilogue writes dslash_partials(prec, g) partials per slot.
+void launch_dslash(int prec, bool dag, int epi, const void *U, const void *in, size_t in_stride,
                    size_t in_extra, void *out, size_t out_stride, const void *aux, size_t aux_stride,
                    size_t aux_extra, const Geom &g, double kappa, double sigma, Slots sl, int max_slots,
                    double *partial, hipStream_t st);
-__host__ __device__ int site_blocks(const Geom &g);               // blocks of 256 sites
-int dslash_parts(const Geom &g, int lgR);       // partials per slot of the FP64 stencil epilogue
-int dslash_partials(int prec, const Geom &g, int lgR);   // ... of the stencil of precision prec
-bool plane_tiled(const Geom &g);                 // FP32 stencil uses the 256-site plane tile
+__host__ __device__ int site_blocks(const Geom &g);   // blocks of 256 sites
+int dslash_partials(int prec, const Geom &g);         // partials per slot of the stencil epilogue
+bool plane_tileable(const Geom &g);                    // the xy-plane has exactly 256 sites
+bool valid_tuning(int prec, const Geom &g);            // g's tuning names an instantiated variant
 int unit_parts(int prec, const Geom &g);        // partials per slot written by element-wise kernels
 size_t partial_stride(const Geom &g);           // slot stride of the partial buffer (>= both)
 

@@ -16,6 +16,8 @@
 // right-hand side), so every FP64 result is bitwise reproducible from run to run.
 #include <hip/hip_runtime.h>
 
+#include <stdexcept>
+
 #include "kernels.h"
 #include "wilson_site.h"
 
@@ -304,29 +306,6 @@ __global__ __launch_bounds__(kBlock) void k_dslash_f32(const float4 *__restrict_
     }
 }
 
-__host__ __device__ int site_blocks(const Geom &g) { return (g.V + kBlock - 1) / kBlock; }
-int dslash_parts(const Geom &g, int lgR) { return (g.V + (kBlock >> lgR) - 1) / (kBlock >> lgR); }
-size_t partial_stride(const Geom &g) { return (size_t)12 * site_blocks(g); }
-
-template <class T, bool DAG, int EPI>
-static void launch_dslash_t(const void *U, const void *in, size_t in_stride, size_t in_extra, void *out,
-                            size_t out_stride, const void *aux, size_t aux_stride, size_t aux_extra, const Geom &g,
-                            double kappa, double sigma, Slots sl, int max_slots, int lgR, double *partial,
-                            hipStream_t st) {
-    using vec = typename Store<T>::vec;
-    using link = typename Store<T>::link;
-    const int R = 1 << lgR;
-    const int nsb = dslash_parts(g, lgR);
-    const int ngr = (max_slots + R - 1) / R;
-    hipLaunchKernelGGL((k_dslash<T, DAG, EPI>), dim3(nsb * ngr), dim3(kBlock), 0, st, (const link *)U,
-                       (const vec *)in, in_stride, in_extra, (vec *)out, out_stride, (const vec *)aux, aux_stride,
-                       aux_extra, g, (T)kappa, (T)sigma, sl, lgR, nsb, partial, partial_stride(g));
-}
-
-// FP32 stencil for lattices whose xy-plane has exactly 256 sites: one block is one plane.
-// Per right-hand side the block stages its 256 spinors in LDS; the +-x and +-y neighbours are
-// read from there, the +-z and +-t neighbours from global memory (issued before the barrier),
-// and the links stay in registers across the right-hand sides as in k_dslash_f32.
 template <int NR, bool DAG, int EPI>
 __global__ __launch_bounds__(kBlock) void k_dslash_f32_plane(const float4 *__restrict__ U, const float4 *__restrict__ in,
                                                              size_t in_stride, size_t in_extra,
@@ -439,56 +418,83 @@ __global__ __launch_bounds__(kBlock) void k_dslash_f32_plane(const float4 *__res
     }
 }
 
-constexpr int kNRPlane = 8;  // right-hand sides per thread in the plane-tiled FP32 stencil
+__host__ __device__ int site_blocks(const Geom &g) { return (g.V + kBlock - 1) / kBlock; }
+static int fp64_parts(const Geom &g) { return (g.V + (kBlock >> g.f64_lgr) - 1) / (kBlock >> g.f64_lgr); }
+size_t partial_stride(const Geom &g) { return (size_t)12 * site_blocks(g); }
+bool plane_tileable(const Geom &g) { return g.nx * g.ny == kBlock; }
+int dslash_partials(int prec, const Geom &g) { return prec == 0 ? fp64_parts(g) : site_blocks(g); }
 
-constexpr int kNRF32 = 4;   // right-hand sides per thread in the FP32 stencil
-
-bool plane_tiled(const Geom &g) { return g.nx * g.ny == kBlock; }
-
-template <bool DAG, int EPI>
-static void launch_dslash_f32(const void *U, const void *in, size_t in_stride, size_t in_extra, void *out,
-                              size_t out_stride, const void *aux, size_t aux_stride, size_t aux_extra, const Geom &g,
-                              double kappa, double sigma, Slots sl, int max_slots, double *partial, hipStream_t st) {
-    const int nsb = site_blocks(g);
-    if (plane_tiled(g)) {
-        const int ngr = (max_slots + kNRPlane - 1) / kNRPlane;
-        hipLaunchKernelGGL((k_dslash_f32_plane<kNRPlane, DAG, EPI>), dim3(nsb * ngr), dim3(kBlock), 0, st,
-                           (const float4 *)U, (const float4 *)in, in_stride, in_extra, (float4 *)out, out_stride,
-                           (const float4 *)aux, aux_stride, aux_extra, g, (float)kappa, (float)sigma, sl, nsb,
-                           partial, partial_stride(g));
-        return;
-    }
-    const int ngr = (max_slots + kNRF32 - 1) / kNRF32;
-    hipLaunchKernelGGL((k_dslash_f32<kNRF32, DAG, EPI>), dim3(nsb * ngr), dim3(kBlock), 0, st, (const float4 *)U,
-                       (const float4 *)in, in_stride, in_extra, (float4 *)out, out_stride, (const float4 *)aux,
-                       aux_stride, aux_extra, g, (float)kappa, (float)sigma, sl, nsb, partial, partial_stride(g));
+bool valid_tuning(int prec, const Geom &g) {
+    if (prec == 0) return g.f64_lgr >= 0 && g.f64_lgr <= 2;
+    if (g.f32_kind == 1) return plane_tileable(g) && (g.f32_nr == 4 || g.f32_nr == 8 || g.f32_nr == 16);
+    return g.f32_kind == 0 && (g.f32_nr == 2 || g.f32_nr == 4 || g.f32_nr == 8);
 }
 
-int dslash_partials(int prec, const Geom &g, int lgR) { return prec == 0 ? dslash_parts(g, lgR) : site_blocks(g); }
+template <class T, bool DAG, int EPI>
+static void launch_dslash_t(const void *U, const void *in, size_t in_stride, size_t in_extra, void *out,
+                            size_t out_stride, const void *aux, size_t aux_stride, size_t aux_extra, const Geom &g,
+                            double kappa, double sigma, Slots sl, int max_slots, double *partial, hipStream_t st) {
+    using vec = typename Store<T>::vec;
+    using link = typename Store<T>::link;
+    const int lgR = g.f64_lgr;
+    const int R = 1 << lgR;
+    const int nsb = fp64_parts(g);
+    const int ngr = (max_slots + R - 1) / R;
+    hipLaunchKernelGGL((k_dslash<T, DAG, EPI>), dim3(nsb * ngr), dim3(kBlock), 0, st, (const link *)U,
+                       (const vec *)in, in_stride, in_extra, (vec *)out, out_stride, (const vec *)aux, aux_stride,
+                       aux_extra, g, (T)kappa, (T)sigma, sl, lgR, nsb, partial, partial_stride(g));
+}
 
-void launch_dslash(int prec, bool dag, int lgR, int epi, const void *U, const void *in, size_t in_stride,
-                   size_t in_extra, void *out, size_t out_stride, const void *aux, size_t aux_stride, size_t aux_extra,
-                   const Geom &g, double kappa, double sigma, Slots sl, int max_slots, double *partial,
-                   hipStream_t st) {
-    if (prec == 0) {
-#define SMPQ_DS(D, E)                                                                                          \
-    launch_dslash_t<double, D, E>(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra, g, kappa, \
-                                  sigma, sl, max_slots, lgR, partial, st)
-        if (!dag && epi == 0) SMPQ_DS(false, 0);
-        else if (!dag) SMPQ_DS(false, 1);
-        else if (epi == 0) SMPQ_DS(true, 0);
-        else SMPQ_DS(true, 1);
-#undef SMPQ_DS
+template <int NR, bool DAG, int EPI, bool PLANE>
+static void launch_f32(const void *U, const void *in, size_t in_stride, size_t in_extra, void *out, size_t out_stride,
+                       const void *aux, size_t aux_stride, size_t aux_extra, const Geom &g, double kappa, double sigma,
+                       Slots sl, int max_slots, double *partial, hipStream_t st) {
+    const int nsb = site_blocks(g);
+    const int ngr = (max_slots + NR - 1) / NR;
+    if constexpr (PLANE)
+        hipLaunchKernelGGL((k_dslash_f32_plane<NR, DAG, EPI>), dim3(nsb * ngr), dim3(kBlock), 0, st,
+                           (const float4 *)U, (const float4 *)in, in_stride, in_extra, (float4 *)out, out_stride,
+                           (const float4 *)aux, aux_stride, aux_extra, g, (float)kappa, (float)sigma, sl, nsb, partial,
+                           partial_stride(g));
+    else
+        hipLaunchKernelGGL((k_dslash_f32<NR, DAG, EPI>), dim3(nsb * ngr), dim3(kBlock), 0, st, (const float4 *)U,
+                           (const float4 *)in, in_stride, in_extra, (float4 *)out, out_stride, (const float4 *)aux,
+                           aux_stride, aux_extra, g, (float)kappa, (float)sigma, sl, nsb, partial, partial_stride(g));
+}
+
+template <bool DAG, int EPI>
+static void launch_f32_tuned(const void *U, const void *in, size_t in_stride, size_t in_extra, void *out,
+                             size_t out_stride, const void *aux, size_t aux_stride, size_t aux_extra, const Geom &g,
+                             double kappa, double sigma, Slots sl, int max_slots, double *partial, hipStream_t st) {
+#define SMPQ_F32(NR, PL)                                                                                       \
+    launch_f32<NR, DAG, EPI, PL>(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra, g, kappa, \
+                                 sigma, sl, max_slots, partial, st)
+    if (g.f32_kind == 1) {
+        if (g.f32_nr == 4) SMPQ_F32(4, true);
+        else if (g.f32_nr == 16) SMPQ_F32(16, true);
+        else SMPQ_F32(8, true);
     } else {
-#define SMPQ_DS(D, E)                                                                                       \
-    launch_dslash_f32<D, E>(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra, g, kappa, \
-                            sigma, sl, max_slots, partial, st)
-        if (!dag && epi == 0) SMPQ_DS(false, 0);
-        else if (!dag) SMPQ_DS(false, 1);
-        else if (epi == 0) SMPQ_DS(true, 0);
-        else SMPQ_DS(true, 1);
-#undef SMPQ_DS
+        if (g.f32_nr == 2) SMPQ_F32(2, false);
+        else if (g.f32_nr == 8) SMPQ_F32(8, false);
+        else SMPQ_F32(4, false);
     }
+#undef SMPQ_F32
+}
+
+void launch_dslash(int prec, bool dag, int epi, const void *U, const void *in, size_t in_stride, size_t in_extra,
+                   void *out, size_t out_stride, const void *aux, size_t aux_stride, size_t aux_extra, const Geom &g,
+                   double kappa, double sigma, Slots sl, int max_slots, double *partial, hipStream_t st) {
+    using Fn = void (*)(const void *, const void *, size_t, size_t, void *, size_t, const void *, size_t, size_t,
+                        const Geom &, double, double, Slots, int, double *, hipStream_t);
+    if (!valid_tuning(prec, g)) throw std::invalid_argument("stencil variant does not fit this lattice");
+    static const Fn table[2][2][2] = {
+        {{launch_dslash_t<double, false, 0>, launch_dslash_t<double, false, 1>},
+         {launch_dslash_t<double, true, 0>, launch_dslash_t<double, true, 1>}},
+        {{launch_f32_tuned<false, 0>, launch_f32_tuned<false, 1>},
+         {launch_f32_tuned<true, 0>, launch_f32_tuned<true, 1>}}};
+    table[prec == 0 ? 0 : 1][dag ? 1 : 0][epi == 1 ? 1 : 0](U, in, in_stride, in_extra, out, out_stride, aux,
+                                                            aux_stride, aux_extra, g, kappa, sigma, sl, max_slots,
+                                                            partial, st);
 }
 
 // ------------------------------------------------------------------ element-wise kernels

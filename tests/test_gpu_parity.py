@@ -33,9 +33,15 @@ def _zolo_interval(U, lat):
     return bounds(U, lat, KAPPA, 300, seed=0)
 
 
+SITE_VARIANTS = [(0, nr, lgr) for nr, lgr in ((2, 0), (4, 1), (8, 2))]
+PLANE_VARIANTS = [(1, nr, lgr) for nr, lgr in ((4, 0), (8, 1), (16, 2))]
+
+
 @pytest.mark.parametrize("dims", [(6, 4, 4, 6), (5, 3, 4, 7), (4, 4, 4, 4)])
 @pytest.mark.parametrize("nrhs", [1, 3, 5])
 def test_dslash_parity(dims, nrhs):
+    """Every site-major FP32 variant (2, 4, 8 right-hand sides per thread) and every FP64
+    interleave (1, 2, 4 right-hand sides per block) against the oracle."""
     print(f"dslash parity dims={dims} nrhs={nrhs}", flush=True)
     lat = Lattice(dims)
     U = si.near_identity_su3(dims, 0.5, 1)
@@ -44,16 +50,22 @@ def test_dslash_parity(dims, nrhs):
     for dag in (False, True):
         ref = np.stack([apply_dw(U, lat, KAPPA, p, dagger=dag) for p in psi])
         scale = np.abs(ref).max()
-        out64 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_FP64)
-        assert np.abs(out64 - ref).max() <= 1e-13 * scale
-        out32 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_MIXED_FP32)
-        assert np.abs(out32 - ref).max() <= 2e-6 * scale
+        for tune in SITE_VARIANTS:
+            smpq.smpq_set_tuning(c, *tune)
+            out64 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_FP64)
+            assert np.abs(out64 - ref).max() <= 1e-13 * scale, tune
+            out32 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_MIXED_FP32)
+            assert np.abs(out32 - ref).max() <= 2e-6 * scale, tune
+    # the plane kernel needs 16x16 xy-planes
+    with pytest.raises(smpq.SmpqError):
+        smpq.smpq_set_tuning(c, 1, 8, 1)
 
 
 @pytest.mark.parametrize("dims", [(16, 16, 2, 2), (16, 16, 3, 2)])
-@pytest.mark.parametrize("nrhs", [1, 9])
+@pytest.mark.parametrize("nrhs", [1, 9, 17])
 def test_dslash_parity_plane_tiled(dims, nrhs):
-    """16x16 xy-planes take the FP32 kernel that stages one plane per block in LDS."""
+    """16x16 xy-planes: the FP32 kernel that stages one plane per block in LDS, with 4, 8 and
+    16 right-hand sides per thread (17 leaves a ragged group for each)."""
     print(f"plane-tiled dslash parity dims={dims} nrhs={nrhs}", flush=True)
     lat = Lattice(dims)
     U = si.near_identity_su3(dims, 0.5, 11)
@@ -61,8 +73,28 @@ def test_dslash_parity_plane_tiled(dims, nrhs):
     c = _ctx(dims, U)
     for dag in (False, True):
         ref = np.stack([apply_dw(U, lat, KAPPA, p, dagger=dag) for p in psi])
-        out32 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_MIXED_FP32)
-        assert np.abs(out32 - ref).max() <= 2e-6 * np.abs(ref).max()
+        for tune in PLANE_VARIANTS:
+            smpq.smpq_set_tuning(c, *tune)
+            out32 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_MIXED_FP32)
+            assert np.abs(out32 - ref).max() <= 2e-6 * np.abs(ref).max(), tune
+            out64 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_FP64)
+            assert np.abs(out64 - ref).max() <= 1e-13 * np.abs(ref).max(), tune
+
+
+def test_autotune_picks_a_valid_variant_and_keeps_parity():
+    dims = (16, 16, 2, 2)
+    print(f"autotune on {dims}", flush=True)
+    lat = Lattice(dims)
+    U = si.near_identity_su3(dims, 0.5, 13)
+    psi = si.random_spinors(dims, 3, 14)
+    c = _ctx(dims, U)
+    kind, nr, lgr = smpq.smpq_autotune(c, 8)
+    assert (kind, nr, lgr) in [(k, n, l) for k, n, _ in SITE_VARIANTS + PLANE_VARIANTS for l in range(3)]
+    ref = np.stack([apply_dw(U, lat, KAPPA, p) for p in psi])
+    out32 = smpq.smpq_apply_dw(c, psi, precision=smpq.SMPQ_MIXED_FP32)
+    assert np.abs(out32 - ref).max() <= 2e-6 * np.abs(ref).max()
+    out64 = smpq.smpq_apply_dw(c, psi, precision=smpq.SMPQ_FP64)
+    assert np.abs(out64 - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
 def test_qx_plane_tiled_mixed():
