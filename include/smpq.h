@@ -210,6 +210,27 @@ smpq_status smpq_set_graphs(smpq_ctx *ctx, int enable);
 smpq_status smpq_bench_dslash(smpq_ctx *ctx, smpq_precision prec, int n_rhs, int n_sets,
                               int launches, double *ms_per_launch, double *bytes_per_launch);
 
+/* Cap the device memory (bytes) the right-hand-side workspace of this context may take; the
+ * batch size follows from it.  0 (the default) means 80% of the free device memory. */
+smpq_status smpq_set_memory_limit(smpq_ctx *ctx, size_t bytes);
+
+/* q(x) for several contexts at once on one device (configurations of different volume, each
+ * with its own scheme, coefficients and precision): the q(x) of Eq. 16 per context, as
+ * smpq_compute_qx_classes.  Contexts are prepared one after another (bounds by Lanczos when
+ * no coefficients were set); contexts without a memory limit then share 80% of the free
+ * device memory in proportion to V x (number of classes), and every context solves on its own
+ * stream from its own host thread, so the batches of different contexts overlap on the GPU.
+ *   ctxs[n_ctx]      distinct contexts on one device, with distinct streams, gauge and scheme set
+ *   classes, n_classes  per-context class lists (NULL, or classes[k] NULL: every class)
+ *   qx[k]            V_k doubles, written in full (sites of unlisted classes are 0)
+ *   qx_imag          NULL, or per context NULL or V_k doubles
+ *   st               NULL or n_ctx records
+ *   failed           NULL or set to the index of the first failing context (-1 on success)
+ * Returns the status of the first failing context (its message in smpq_last_error). */
+smpq_status smpq_compute_qx_multi(smpq_ctx *const *ctxs, int n_ctx, const int32_t *const *classes,
+                                  const int *n_classes, double *const *qx, double *const *qx_imag,
+                                  smpq_stats *st, int *failed);
+
 /* Choose the stencil variants for this lattice by timing them on n_rhs right-hand sides
  * (two rotating buffer sets, 10 launches each): FP32 kind (0: one site per thread; 1: one
  * 16x16 xy-plane per block staged in LDS, only when nx*ny = 256) with 2, 4 or 8 (kind 0) or

@@ -22,7 +22,7 @@ __all__ = [
     "smpq_set_point_scheme", "smpq_get_coloring", "smpq_apply_dw", "smpq_apply_dov",
     "smpq_compute_qx", "smpq_compute_qx_classes", "smpq_compute_qx_points", "smpq_prepare", "smpq_set_stream",
     "smpq_set_timing", "smpq_set_graphs", "smpq_bench_dslash", "smpq_autotune",
-    "smpq_set_tuning",
+    "smpq_set_tuning", "smpq_set_memory_limit", "smpq_compute_qx_multi",
 ]
 
 SMPQ_FP64 = 0
@@ -75,6 +75,11 @@ _SIG = {
                                          _c_double_p]),
     "smpq_autotune": (ctypes.c_int, [_vp, ctypes.c_int, _c_int_p, _c_int_p, _c_int_p]),
     "smpq_set_tuning": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "smpq_set_memory_limit": (ctypes.c_int, [_vp, ctypes.c_size_t]),
+    "smpq_compute_qx_multi": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int,
+                                             ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)), _c_int_p,
+                                             ctypes.POINTER(_c_double_p), ctypes.POINTER(_c_double_p),
+                                             ctypes.POINTER(SmpqStats), _c_int_p]),
 }
 EXPORTS = tuple(_SIG)
 for _name, (_res, _args) in _SIG.items():
@@ -292,3 +297,40 @@ def smpq_autotune(ctx, n_rhs=48):
 
 def smpq_set_tuning(ctx, f32_kind, f32_nr, f64_lgr):
     _check(ctx, _lib.smpq_set_tuning(ctx.ptr, int(f32_kind), int(f32_nr), int(f64_lgr)))
+
+
+def smpq_set_memory_limit(ctx, nbytes):
+    _check(ctx, _lib.smpq_set_memory_limit(ctx.ptr, int(nbytes)))
+
+
+def smpq_compute_qx_multi(ctxs, classes=None):
+    """q(x) of several contexts solved concurrently.  classes: None, or one entry per context
+    (None for every class).  Returns a list of (qx, qx_imag, stats dict)."""
+    n = len(ctxs)
+    ptrs = (_vp * n)(*[c.ptr for c in ctxs])
+    qx = [np.zeros(c.volume) for c in ctxs]
+    qi = [np.zeros(c.volume) for c in ctxs]
+    qxp = (_c_double_p * n)(*[_dp(a) for a in qx])
+    qip = (_c_double_p * n)(*[_dp(a) for a in qi])
+    st = (SmpqStats * n)()
+    failed = ctypes.c_int(-1)
+    cl_arrays, clp, ncl = [], None, None
+    if classes is not None:
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        clp = (i32p * n)()
+        ncl = (ctypes.c_int * n)()
+        for k, cl in enumerate(classes):
+            if cl is None:
+                clp[k] = i32p()
+                ncl[k] = -1
+            else:
+                a = np.ascontiguousarray(cl, dtype=np.int32)
+                cl_arrays.append(a)
+                clp[k] = a.ctypes.data_as(i32p)
+                ncl[k] = len(a)
+    rc = _lib.smpq_compute_qx_multi(ptrs, n, clp, ncl, qxp, qip, st, ctypes.byref(failed))
+    if rc != 0:
+        k = failed.value
+        msg = _lib.smpq_last_error(ctxs[k].ptr).decode() if 0 <= k < n else ""
+        raise SmpqError(rc, f"context {k}: {msg}")
+    return [(qx[k], qi[k], st[k].as_dict()) for k in range(n)]

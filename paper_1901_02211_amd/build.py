@@ -46,7 +46,7 @@ def build(verbose=False):
                 print(r.stdout + r.stderr, file=sys.stderr)
     objs = [os.path.join(BUILD, s + ".o") for s in HIP_SOURCES + HOST_SOURCES]
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs)
+    _run([HIPCC, "-shared", "-fPIC", "-pthread", "--offload-arch=gfx950", "-o", tmp] + objs)
     os.replace(tmp, LIB)
     return LIB
 

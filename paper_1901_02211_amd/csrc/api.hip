@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/smpq.h"
@@ -133,6 +134,8 @@ struct smpq_ctx {
     int max_iter = 10000;
     int reliable = 50;
     int max_rhs = 0;
+    size_t mem_limit = 0;   // workspace bytes a batch may use (0: 80% of free device memory)
+    size_t run_limit = 0;   // share assigned by a multi-context call while it runs
     bool have_scheme = false;
     std::vector<int32_t> colour;
     int n_classes = 0;
@@ -297,15 +300,32 @@ void ensure_workspace(smpq_ctx *c, int prec, int NS, int B) {
     S.B = B;
 }
 
+// Free the right-hand-side vectors of the workspace (the next ensure_workspace lays it out again).
+void release_workspace(smpq_ctx *c) {
+    Workspace &w = c->ws;
+    w.r.release(); w.tmp.release(); w.ap.release(); w.p.release(); w.y.release();
+    w.x0.release(); w.tmp64.release(); w.ap64.release(); w.yacc.release(); w.x0acc.release();
+    w.prec = -1;
+    w.B = 0;
+    w.S.rr = nullptr;
+    c->gen++;
+}
+
+size_t workspace_bytes(const smpq_ctx *c) {
+    const Workspace &w = c->ws;
+    return (size_t)w.r.bytes + w.tmp.bytes + w.ap.bytes + w.p.bytes + w.y.bytes + w.x0.bytes + w.tmp64.bytes +
+           w.ap64.bytes + w.yacc.bytes + w.x0acc.bytes;
+}
+
 int choose_batch(smpq_ctx *c, int prec, int NS, int total_slots, bool multiple_of_12) {
     size_t freeb = 0, totalb = 0;
     HIPCHK(hipMemGetInfo(&freeb, &totalb));
     // memory already held by a workspace of the same shape is reusable
     size_t held = 0;
     if (c->ws.prec == prec && c->ws.NS == NS) held = bytes_per_slot(c, prec, NS) * c->ws.B;
-    else held = (size_t)c->ws.r.bytes + c->ws.tmp.bytes + c->ws.ap.bytes + c->ws.p.bytes + c->ws.y.bytes +
-                c->ws.x0.bytes + c->ws.tmp64.bytes + c->ws.ap64.bytes + c->ws.yacc.bytes + c->ws.x0acc.bytes;
-    const double budget = 0.80 * (double)(freeb + held);
+    else held = workspace_bytes(c);
+    const size_t limit = c->run_limit > 0 ? c->run_limit : c->mem_limit;
+    const double budget = limit > 0 ? (double)limit : 0.80 * (double)(freeb + held);
     long long B = (long long)(budget / (double)bytes_per_slot(c, prec, NS));
     if (c->max_rhs > 0) B = std::min<long long>(B, c->max_rhs);
     B = std::min<long long>(B, total_slots);
@@ -712,6 +732,24 @@ void finish_q(smpq_ctx *c, double *qx, double *qxi, smpq_stats *st) {
     }
 }
 
+// Checked class list of the context's scheme; classes == NULL with n < 0 means every class.
+std::vector<int> class_list(const smpq_ctx *c, const int32_t *classes, int n) {
+    if (!c->have_scheme) throw Fail{SMPQ_ESTATE, "no scheme set"};
+    if (!classes && n < 0) {
+        std::vector<int> all(c->n_classes);
+        for (int i = 0; i < c->n_classes; ++i) all[i] = i;
+        return all;
+    }
+    if (n < 0 || (!classes && n > 0)) throw Fail{SMPQ_EINVAL, "bad class list"};
+    std::vector<int> cls(classes, classes + n);
+    std::vector<char> seen(c->n_classes, 0);
+    for (int v : cls) {
+        if (v < 0 || v >= c->n_classes) throw Fail{SMPQ_EINVAL, "class index out of range"};
+        if (seen[v]++) throw Fail{SMPQ_EINVAL, "duplicate class index"};
+    }
+    return cls;
+}
+
 // Mean duration of the stencil (D_W, epilogue 0) on n_rhs right-hand sides, rotating through
 // n_sets disjoint input/output/link sets; *bytes = algorithmic bytes per launch.
 double time_dslash(smpq_ctx *c, int p, int n_rhs, int n_sets, int launches, double *bytes) {
@@ -1101,19 +1139,121 @@ smpq_status smpq_compute_qx_classes(smpq_ctx *c, const int32_t *classes, int n, 
                                     smpq_stats *st) {
     return guarded(c, [&] {
         if (!qx || (!classes && n > 0) || n < 0) throw Fail{SMPQ_EINVAL, "bad class list or output"};
-        if (!c->have_scheme) throw Fail{SMPQ_ESTATE, "no scheme set"};
-        std::vector<int> cls(classes, classes + n);
-        std::vector<char> seen(c->n_classes, 0);
-        for (int v : cls) {
-            if (v < 0 || v >= c->n_classes) throw Fail{SMPQ_EINVAL, "class index out of range"};
-            if (seen[v]++) throw Fail{SMPQ_EINVAL, "duplicate class index"};
-        }
+        const std::vector<int> cls = class_list(c, classes, n);
         if (st) std::memset(st, 0, sizeof(*st));
         prepare_q(c, st);
         ensure_scheme_device(c);
         qx_classes(c, cls, false, st);
         finish_q(c, qx, qxi, st);
     });
+}
+
+smpq_status smpq_set_memory_limit(smpq_ctx *c, size_t bytes) {
+    return guarded(c, [&] { c->mem_limit = bytes; });
+}
+
+smpq_status smpq_compute_qx_multi(smpq_ctx *const *ctxs, int n_ctx, const int32_t *const *classes,
+                                  const int *n_classes, double *const *qx, double *const *qxi, smpq_stats *st,
+                                  int *failed) {
+    if (failed) *failed = -1;
+    if (n_ctx < 1 || !ctxs || !qx || (classes && !n_classes)) return SMPQ_EINVAL;
+    for (int k = 0; k < n_ctx; ++k)
+        if (!ctxs[k] || !qx[k]) {
+            if (failed) *failed = k;
+            return SMPQ_EINVAL;
+        }
+    std::vector<std::vector<int>> cls(n_ctx);
+    std::vector<double> work(n_ctx, 0.0);
+    std::vector<int> planned(n_ctx, 0);
+    auto give_up = [&](int k, smpq_status s) {
+        for (int j = 0; j < n_ctx; ++j) ctxs[j]->run_limit = 0;
+        if (failed) *failed = k;
+        return s;
+    };
+    // host-side checks of every context first, then the set-up one context after another:
+    // bounds, device arrays of the scheme and of the output
+    for (int k = 0; k < n_ctx; ++k) {
+        smpq_ctx *c = ctxs[k];
+        const smpq_status s = guarded(c, [&] {
+            for (int j = 0; j < k; ++j) {
+                if (ctxs[j] == c) throw Fail{SMPQ_EINVAL, "context listed twice"};
+                if (c->stream && ctxs[j]->stream == c->stream) throw Fail{SMPQ_EINVAL, "contexts share a stream"};
+            }
+            cls[k] = class_list(c, classes ? classes[k] : nullptr, classes && classes[k] ? n_classes[k] : -1);
+        });
+        if (s != SMPQ_OK) return give_up(k, s);
+    }
+    for (int k = 0; k < n_ctx; ++k) {
+        smpq_ctx *c = ctxs[k];
+        const smpq_status s = guarded(c, [&] {
+            need_device(c);
+            if (c->device != ctxs[0]->device) throw Fail{SMPQ_EINVAL, "contexts on different devices"};
+            if (st) std::memset(&st[k], 0, sizeof(smpq_stats));
+            prepare_q(c, st ? &st[k] : nullptr);
+            ensure_scheme_device(c);
+            work[k] = (double)c->V * (double)cls[k].size();
+        });
+        if (s != SMPQ_OK) return give_up(k, s);
+    }
+    // device memory: contexts without a limit of their own share 80% of what is free (plus what
+    // their workspaces already hold) in proportion to their work, V x classes
+    {
+        size_t freeb = 0, totalb = 0, held = 0, fixed = 0;
+        double wsum = 0.0;
+        if (hipSetDevice(ctxs[0]->device) != hipSuccess || hipMemGetInfo(&freeb, &totalb) != hipSuccess)
+            return give_up(0, SMPQ_EDEVICE);
+        for (int k = 0; k < n_ctx; ++k) {
+            held += workspace_bytes(ctxs[k]);
+            if (ctxs[k]->mem_limit > 0) fixed += ctxs[k]->mem_limit;
+            else wsum += work[k];
+        }
+        const double pool = std::max(0.0, 0.80 * (double)(freeb + held) - (double)fixed);
+        for (int k = 0; k < n_ctx; ++k) {
+            smpq_ctx *c = ctxs[k];
+            c->run_limit = c->mem_limit > 0 ? c->mem_limit : (size_t)(pool * work[k] / std::max(wsum, 1.0));
+        }
+        for (int k = 0; k < n_ctx; ++k) {
+            smpq_ctx *c = ctxs[k];
+            const smpq_status s = guarded(c, [&] {
+                const int prec = c->prec == SMPQ_FP64 ? 0 : 1;
+                if (cls[k].empty()) return;
+                planned[k] = choose_batch(c, prec, c->zolo.n, (int)cls[k].size() * 12, true);
+                if (c->ws.prec != prec || c->ws.NS != c->zolo.n || c->ws.B != planned[k]) release_workspace(c);
+            });
+            if (s != SMPQ_OK) return give_up(k, s);
+        }
+        for (int k = 0; k < n_ctx; ++k) {
+            smpq_ctx *c = ctxs[k];
+            const smpq_status s = guarded(c, [&] {
+                if (planned[k] > 0) ensure_workspace(c, c->prec == SMPQ_FP64 ? 0 : 1, c->zolo.n, planned[k]);
+            });
+            if (s != SMPQ_OK) return give_up(k, s);
+        }
+    }
+    // the solves: one host thread per context, each on the context's own stream
+    std::vector<smpq_status> res(n_ctx, SMPQ_OK);
+    {
+        std::vector<std::thread> th;
+        th.reserve(n_ctx);
+        for (int k = 0; k < n_ctx; ++k)
+            th.emplace_back([&, k] {
+                smpq_ctx *c = ctxs[k];
+                smpq_stats *sk = st ? &st[k] : nullptr;
+                res[k] = guarded(c, [&] {
+                    need_device(c);
+                    qx_classes(c, cls[k], false, sk);
+                    finish_q(c, qx[k], qxi ? qxi[k] : nullptr, sk);
+                });
+            });
+        for (auto &t : th) t.join();
+    }
+    for (int k = 0; k < n_ctx; ++k) ctxs[k]->run_limit = 0;
+    for (int k = 0; k < n_ctx; ++k)
+        if (res[k] != SMPQ_OK) {
+            if (failed) *failed = k;
+            return res[k];
+        }
+    return SMPQ_OK;
 }
 
 smpq_status smpq_compute_qx_points(smpq_ctx *c, const int64_t *sites, int n, double *qx, smpq_stats *st) {

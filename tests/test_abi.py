@@ -107,3 +107,22 @@ def test_argument_errors():
         smpq.smpq_compute_qx_points(c, [0])
     assert e.value.status == -4
     assert smpq.smpq_strerror(-5) == "solver did not converge"
+
+
+def test_multi_context_argument_errors():
+    """Host-side checks of smpq_compute_qx_multi, before any device work."""
+    a = smpq.smpq_create((4, 4, 4, 4), -1)
+    b = smpq.smpq_create((2, 2, 2, 2), -1)
+    with pytest.raises(smpq.SmpqError) as e:          # no scheme on the first context
+        smpq.smpq_compute_qx_multi([a, b])
+    assert e.value.status == -6 and "context 0" in str(e.value)
+    smpq.smpq_set_scheme(a, (2, 2, 2, 2), 0)
+    smpq.smpq_set_scheme(b, (2, 2, 2, 2), 0)
+    with pytest.raises(smpq.SmpqError) as e:          # class index out of range on the second
+        smpq.smpq_compute_qx_multi([a, b], [None, [0, 1, 99]])
+    assert e.value.status == -1 and "context 1" in str(e.value)
+    with pytest.raises(smpq.SmpqError) as e:          # host-only contexts cannot solve
+        smpq.smpq_compute_qx_multi([a, b], [[0], None])
+    assert e.value.status == -4
+    smpq.smpq_set_memory_limit(a, 1 << 30)
+    smpq.smpq_set_memory_limit(a, 0)
