@@ -11,9 +11,19 @@ Jobs (each writes tests/golden/<job>.npz):
   flux8_point     same field: point sources on the 64 sites of the seeded subset (768 sources).
   flux8_smp4_part same field: SMP r = 4, classes 0, 85 and 255 (36 of 3072 sources).
   noise16x32_part 16^3 x 32 (eps 0.2, seed 4): SMP r = 4, classes 0 and 129 (24 of 3072 sources).
+  noise16_part    16^4 (eps 0.1, seed 6): SMP r = 4, classes 0 and 200 (24 of 3072 sources).
+  noise24_part    24^4 (eps 0.2, seed 7): SMP r = 6, class 777 (12 of 15552 sources).
+  flux24x48_part  24^3 x 48 flux (1,1) + noise 0.15 (seed 5): SMP r = 6, class 5 (12 of 15552).
+  noise32x64_dov  32^3 x 64 (eps 0.3, seed 8): D_ov applied to one SMP r = 8 source (class 0,
+                  spin 0, colour 0), kept on the 512 sites of the class and 64 seeded sites.
 
-Every job uses kappa = 0.21, 14 Zolotarev poles on [0.9 sqrt(theta_min), 1.02 sqrt(theta_max)]
-from 300 Lanczos steps of the oracle (start vector: SplitMix64 stream 0), CG tolerance 1e-12.
+Every job uses kappa = 0.21, 14 Zolotarev poles and CG tolerance 1e-12.  Up to 16^3 x 32 the
+interval is [0.9 sqrt(theta_min), 1.02 sqrt(theta_max)] from 300 Lanczos steps of the oracle
+(start vector: SplitMix64 stream 0); on the larger lattices, where the oracle's fully
+reorthogonalised Lanczos would hold 300 vectors of 0.1-0.4 GB, it is the fixed interval
+[0.15, 2.75], which contains the free-field range [1 - 4 kappa, 1 + 8 kappa] = [0.16, 2.68] that
+near-identity noise narrows (both sides use the same coefficients, so parity does not depend on
+how tight the interval is).
 Sources run in parallel processes; each site's contributions are summed in (class, alpha, a)
 order.
 """
@@ -29,7 +39,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 import smpq_inputs as si  # noqa: E402
-from oracle.charge import charge_from_spectrum, eps_dense, h_spectrum, qx_from_eps, source_contribution  # noqa: E402
+from oracle.charge import (charge_from_spectrum, dov_apply, eps_dense, h_spectrum, qx_from_eps,  # noqa: E402
+                           source_contribution)
 from oracle.lanczos import bounds  # noqa: E402
 from oracle.lattice import Lattice  # noqa: E402
 from oracle.probing import colouring, point_colouring  # noqa: E402
@@ -45,7 +56,14 @@ JOBS = {
     "flux8_point": ("flux8", ("point",), "subset", False),
     "flux8_smp4_part": ("flux8", ("smp", 4), [0, 85, 255], False),
     "noise16x32_part": ("noise16x32", ("smp", 4), [0, 129], False),
+    "noise16_part": ("noise16", ("smp", 4), [0, 200], False),
+    "noise24_part": ("noise24", ("smp", 6), [777], False),
+    "flux24x48_part": ("flux24x48", ("smp", 6), [5], False),
+    "noise32x64_dov": ("noise32x64", ("dov", 8), [0], False),
 }
+FIXED_INTERVAL = {"noise16": (0.15, 2.75), "noise24": (0.15, 2.75), "flux24x48": (0.15, 2.75),
+                  "noise32x64": (0.15, 2.75)}
+DOV_SAMPLE_SEED, DOV_SAMPLE_N = 9, 64
 
 _G = {}
 
@@ -72,17 +90,39 @@ def zolo_for(name):
     path = os.path.join(HERE, f"{name}_zolo.npz")
     if os.path.exists(path):
         return
-    U = si.workload(name)
-    lat = Lattice(si.WORKLOADS[name]["dims"])
-    lo, hi = bounds(U, lat, KAPPA, STEPS, seed=0)
+    if name in FIXED_INTERVAL:
+        lo, hi = FIXED_INTERVAL[name]
+    else:
+        U = si.workload(name)
+        lat = Lattice(si.WORKLOADS[name]["dims"])
+        lo, hi = bounds(U, lat, KAPPA, STEPS, seed=0)
     c0, c, q, delta = zolotarev(NPOLES, lo, hi)
     np.savez(path, lam_min=lo, lam_max=hi, c0=c0, c=c, q=q, delta=delta, n_poles=NPOLES, kappa=KAPPA)
     print(f"{name}: interval [{lo:.6f}, {hi:.6f}], delta {delta:.3e}", flush=True)
 
 
+def run_dov(job, name, r, cls):
+    """One probing source of class cls[0] (spin 0, colour 0): D_ov phi on sampled sites."""
+    lat = Lattice(si.WORKLOADS[name]["dims"])
+    U = si.workload(name)
+    zo = np.load(os.path.join(HERE, f"{name}_zolo.npz"))
+    col, _ = colouring(lat, (r,) * 4, 0)
+    b = np.zeros((lat.volume, 4, 3), dtype=np.complex128)
+    b[col == cls[0], 0, 0] = 1.0
+    t0 = time.time()
+    out = dov_apply(U, lat, KAPPA, (float(zo["c0"]), zo["c"], zo["q"]), b, TOL, MAXIT)
+    rng = np.random.default_rng(DOV_SAMPLE_SEED)
+    sites = np.union1d(np.nonzero(col == cls[0])[0], rng.choice(lat.volume, DOV_SAMPLE_N, replace=False))
+    np.savez_compressed(os.path.join(HERE, f"{job}.npz"), sites=sites, dov=out[sites], cls=np.array(cls),
+                        r=np.array(r), seconds=time.time() - t0)
+    print(f"{job}: done in {time.time() - t0:.0f} s", flush=True)
+
+
 def run(job, procs):
     name, scheme, classes, dense = JOBS[job]
     zolo_for(name)
+    if scheme[0] == "dov":
+        return run_dov(job, name, scheme[1], classes)
     lat = Lattice(si.WORKLOADS[name]["dims"])
     if scheme[0] == "point":
         sites = si.subset_sites(name) if classes == "subset" else np.arange(lat.volume)

@@ -140,3 +140,47 @@ def test_multi_context_uneven_volumes(prec):
     tol = 1e-10 if prec == smpq.SMPQ_FP64 else 1e-5
     assert np.abs(multi[0][0] - _golden("noise4_smp")["qx"]).max() < tol
     assert np.abs(multi[1][0] - _golden("flux8_smp2")["qx"]).max() < tol
+
+
+# Larger lattices at full size: the stored classes are solved inside a batch of the size the
+# device memory allows for that lattice (padding classes fill it), as a whole-map run would.
+LARGE = [("noise16_part", "noise16", 4, 64), ("noise24_part", "noise24", 6, 24),
+         ("flux24x48_part", "flux24x48", 6, 11)]
+
+
+@pytest.mark.parametrize("prec", [smpq.SMPQ_FP64, smpq.SMPQ_MIXED_FP32])
+@pytest.mark.parametrize("job,workload,r,per_batch", LARGE)
+def test_large_lattice_sampled_classes(job, workload, r, per_batch, prec):
+    print(f"{job}: r={r}, {per_batch} classes per batch, precision {prec}", flush=True)
+    g = _golden(job)
+    c = _ctx(workload, prec)
+    smpq.smpq_set_scheme(c, (r,) * 4, 0)
+    want = [int(k) for k in g["classes"]]
+    classes = want + [k for k in range(1, 10 * per_batch) if k not in want][:per_batch - len(want)]
+    q, qi, st = smpq.smpq_compute_qx_classes(c, classes)
+    assert st["n_sources"] == 12 * per_batch
+    mask = np.isin(smpq.smpq_get_coloring(c), want)
+    tol = 1e-10 if prec == smpq.SMPQ_FP64 else 1e-5
+    assert np.abs(q[mask] - g["qx"][mask]).max() < tol
+    assert np.abs(qi[mask] - g["qx_imag"][mask]).max() < tol
+    # every probing source gives a real phi^dag eps phi: Im q sums to zero over each class
+    col = smpq.smpq_get_coloring(c)
+    for k in classes[:4]:
+        assert abs(qi[col == k].sum()) < (1e-9 if prec == smpq.SMPQ_FP64 else 1e-5)
+
+
+def test_noise32x64_dov_sampled_sites():
+    """D_ov on one SMP source of the 32^3 x 64 lattice (V = 2097152), FP64, at full size."""
+    print("32^3x64 D_ov of one probing source", flush=True)
+    g = _golden("noise32x64_dov")
+    w = si.WORKLOADS["noise32x64"]
+    c = _ctx("noise32x64", smpq.SMPQ_FP64)
+    r = int(g["r"])
+    smpq.smpq_set_scheme(c, (r,) * 4, 0)
+    col = smpq.smpq_get_coloring(c)
+    b = np.zeros((1, col.size, 4, 3), dtype=np.complex128)
+    b[0, col == int(g["cls"][0]), 0, 0] = 1.0
+    out = smpq.smpq_apply_dov(c, b)[0]
+    sites = g["sites"]
+    assert np.abs(out[sites] - g["dov"]).max() < 1e-10 * np.abs(g["dov"]).max()
+    assert w["dims"] == (32, 32, 32, 64)
