@@ -1,11 +1,17 @@
 """Benchmark: seconds per q(x) map on one MI355X, mixed precision vs plain FP64.
 
-Workload: 16^3 x 32 periodic lattice, near-identity SU(3) links (eps = 0.2, seed 4),
+Default workload: 16^3 x 32 periodic lattice, near-identity SU(3) links (eps = 0.2, seed 4),
 kappa = 0.21, 14-pole Zolotarev sign function on Lanczos bounds, SMP normal mode with
 r = 4 (256 classes x 12 = 3072 sources), per-shift CG tolerance 1e-12.  One step is one
 whole q(x) map: Lanczos bounds + Zolotarev + every multi-shift CG solve + contraction +
 copy-out of q(x) and Q, with the gauge field already resident in HBM.  The map runs in
 FP32 with FP64 reliable updates every 50 iterations and FP64 accumulation.
+
+--workload selects another lattice of the same family (24^3x48 flux, 16^4, 24^4, 32^3x64);
+maps that take minutes are timed on a sample of classes and the value is extrapolated by
+classes/sample (labelled "extrapolated").  --workload uneven times 16^4 + 24^4 + 32^3x64
+together, the same fraction of classes of each, concurrently (one stream per lattice) and
+one after another.
 
 Printed: one JSON line.  value = seconds per map (lower is better).  Beside it:
   roofline      the dominant kernel of the step (HIP events on the library's stream),
@@ -29,10 +35,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-DIMS = (16, 16, 16, 32)
-WORKLOAD = "noise16x32"
-R_GAP = 4
 KAPPA, TOL, POLES, RELIABLE = 0.21, 1e-12, 14, 50
+# workload -> gap r, default sample of classes (0 = whole map), FP64 comparison classes, description
+BENCH = {
+    "noise16x32": (4, 0, 16, "16^3x32 near-identity SU(3) eps=0.2 seed 4, SMP normal mode r=4"),
+    "flux24x48": (6, 24, 6, "24^3x48 U(1) flux (1,1) x near-identity eps=0.15 seed 5, SMP normal mode r=6"),
+    "noise16": (4, 0, 16, "16^4 near-identity SU(3) eps=0.1 seed 6, SMP normal mode r=4"),
+    "noise24": (6, 48, 12, "24^4 near-identity SU(3) eps=0.2 seed 7, SMP normal mode r=6"),
+    "noise32x64": (8, 16, 4, "32^3x64 near-identity SU(3) eps=0.3 seed 8, SMP normal mode r=8"),
+}
+UNEVEN = ("noise16", "noise24", "noise32x64")
 
 
 def kernel_source_hash():
@@ -57,7 +69,7 @@ def measured_traffic(kernel):
     return entry
 
 
-def cpu_baseline(total_iters, n_sources, iters_sample):
+def cpu_baseline(workload, dims, r_gap, total_iters, n_sources, iters_sample):
     """Time the oracle's multi-shift CG on one source of the workload for a bounded number of
     iterations in a single-threaded subprocess; scale by the map's measured iteration count."""
     code = f"""
@@ -71,8 +83,8 @@ from oracle.mscg import multishift_cg, NotConverged
 from oracle.lanczos import bounds
 from oracle.zolotarev import zolotarev
 from oracle.probing import colouring
-U = si.workload({WORKLOAD!r}); lat = Lattice({DIMS!r})
-col, _ = colouring(lat, ({R_GAP},) * 4, 0)
+U = si.workload({workload!r}); lat = Lattice({tuple(dims)!r})
+col, _ = colouring(lat, ({r_gap},) * 4, 0)
 b = np.zeros((lat.volume, 4, 3), dtype=np.complex128); b[col == 0, 0, 0] = 1.0
 c0, c, q, _ = zolotarev({POLES}, 0.14, 2.73)
 s = q.min()
@@ -90,9 +102,57 @@ print(time.perf_counter() - t0)
     t = float(out.stdout.strip().splitlines()[-1])
     per_iter = t / iters_sample
     return {"value": per_iter * total_iters, "unit": "s/map", "cores": 1, "kind": "oracle",
-            "sample": f"{iters_sample} multi-shift CG iterations of one r=4 source on the 16^3x32 field "
+            "sample": f"{iters_sample} multi-shift CG iterations of one r={r_gap} source on the {workload} field "
                       f"({t:.1f} s), scaled by the map's {total_iters} iterations over {n_sources} sources",
             "seconds_per_iteration": per_iter}
+
+
+def uneven(args, smpq, si):
+    """16^4 + 24^4 + 32^3x64 together: the same fraction of the classes of each lattice, solved
+    concurrently (smpq_compute_qx_multi) and one after another; both scaled to whole maps."""
+    frac = 1.0 / 256 if args.classes < 0 else 1.0 / max(1, args.classes)
+    ctxs, plan = [], []
+    for name in UNEVEN:
+        r = BENCH[name][0]
+        print(f"bench: building {name}", file=sys.stderr, flush=True)
+        c = smpq.smpq_create(si.WORKLOADS[name]["dims"], 0)
+        smpq.smpq_load_gauge(c, si.workload(name))
+        ncls, _ = smpq.smpq_set_scheme(c, (r,) * 4, 0)
+        smpq.smpq_set_solver(c, smpq.SMPQ_MIXED_FP32, TOL, 10000, RELIABLE)
+        smpq.smpq_set_zolotarev(c, POLES, *smpq.smpq_estimate_bounds(c, 300))
+        smpq.smpq_autotune(c, 48)
+        k = max(1, round(ncls * frac))
+        ctxs.append(c)
+        plan.append((name, ncls, list(range(k))))
+    for c, (_, _, cl) in zip(ctxs, plan):   # untimed: workspaces, graphs, first launches
+        smpq.smpq_compute_qx_classes(c, cl[:1])
+    t0 = time.perf_counter()
+    seq = [smpq.smpq_compute_qx_classes(c, cl) for c, (_, _, cl) in zip(ctxs, plan)]
+    t_seq = time.perf_counter() - t0
+    print(f"bench: one after another {t_seq:.2f} s", file=sys.stderr, flush=True)
+    smpq.smpq_compute_qx_multi(ctxs, [cl[:1] for _, _, cl in plan])
+    t0 = time.perf_counter()
+    par = smpq.smpq_compute_qx_multi(ctxs, [cl for _, _, cl in plan])
+    t_par = time.perf_counter() - t0
+    print(f"bench: concurrent {t_par:.2f} s", file=sys.stderr, flush=True)
+    same = all(np.array_equal(a[0], b[0]) for a, b in zip(seq, par))
+    scale = sum(n for _, n, _ in plan) / sum(len(cl) for _, _, cl in plan)
+    line = {
+        "metric": "sec per set of q(x) maps (16^4 + 24^4 + 32^3x64), concurrent",
+        "value": round(t_par * scale, 3), "unit": "s/set", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(1000 * t_par * scale, 1), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "16^4 r=4 + 24^4 r=6 + 32^3x64 r=8, near-identity SU(3), mixed precision",
+                   "lattices": {n: {"classes_timed": len(cl), "classes_per_map": nc,
+                                    "sources_timed": 12 * len(cl),
+                                    "iterations": st[2]["total_iters"], "batches": st[2]["n_batches"]}
+                                for (n, nc, cl), st in zip(plan, par)},
+                   "extrapolated": True, "fraction_of_each_map": frac},
+        "sequential_s_per_set": round(t_seq * scale, 3),
+        "concurrent_over_sequential": round(t_par / t_seq, 4),
+        "results_identical": same,
+    }
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -100,11 +160,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--fp64-classes", type=int, default=16, help="classes in the FP64 comparison sample")
+    ap.add_argument("--workload", default="noise16x32", choices=sorted(BENCH) + ["uneven"])
+    ap.add_argument("--fp64-classes", type=int, default=-1, help="classes in the FP64 comparison sample")
     ap.add_argument("--full-fp64", action="store_true", help="run the FP64 comparison as a whole map")
-    ap.add_argument("--classes", type=int, default=0, help="profile mode: only the first N classes")
+    ap.add_argument("--classes", type=int, default=-1,
+                    help="time only the first N classes and extrapolate (0 = whole map)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--cpu-iters", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -115,13 +177,25 @@ def main():
     import paper_1901_02211_amd as smpq
     import smpq_inputs as si
 
+    if args.workload == "uneven":
+        return uneven(args, smpq, si)
+    WORKLOAD = args.workload
+    DIMS = si.WORKLOADS[WORKLOAD]["dims"]
+    R_GAP, sample, fp64_default, desc = BENCH[WORKLOAD]
+    if args.classes < 0:
+        args.classes = sample
+    if args.fp64_classes < 0:
+        args.fp64_classes = fp64_default
+    if args.cpu_iters <= 0:
+        args.cpu_iters = max(2, round(8 * 131072 / int(np.prod(DIMS))))
     print(f"bench: building {WORKLOAD} {DIMS}", file=sys.stderr, flush=True)
     U = si.workload(WORKLOAD)
     ctx = smpq.smpq_create(DIMS, 0)
     smpq.smpq_load_gauge(ctx, U)                    # resident in HBM before any timed region
     ncls, nsrc = smpq.smpq_set_scheme(ctx, (R_GAP,) * 4, 0)
     smpq.smpq_set_solver(ctx, smpq.SMPQ_MIXED_FP32, TOL, 10000, RELIABLE)
-    classes = list(range(ncls if args.classes == 0 else args.classes))
+    classes = list(range(ncls if args.classes == 0 else min(args.classes, ncls)))
+    scale = ncls / len(classes)             # extrapolation factor of a sampled map
 
     def one_map():
         """One step: Lanczos bounds, Zolotarev coefficients and the whole q(x) map."""
@@ -140,10 +214,10 @@ def main():
 
     # untimed set-up: workspace allocation and first launches of every kernel
     smpq.smpq_set_zolotarev(ctx, POLES, 0.14, 2.73)
-    smpq.smpq_prepare(ctx)
     tuning = smpq.smpq_autotune(ctx, 96)
     print(f"bench: stencil variants (f32 kind, f32 rhs/thread, f64 log2 rhs/block) = {tuning}",
           file=sys.stderr, flush=True)
+    smpq.smpq_prepare(ctx)
     smpq.smpq_compute_qx_classes(ctx, [0])
     smpq.smpq_set_timing(ctx, True)
     for w in range(args.warmup):
@@ -157,7 +231,7 @@ def main():
         print(f"bench: step {k}: {dt:.2f} s, Q = {Q:.6f}, iters {st['total_iters']}, "
               f"batches {st['n_batches']}", file=sys.stderr, flush=True)
     q_mixed, Q, st = last
-    ms_per_step = 1000.0 * float(np.mean(times))
+    ms_per_step = 1000.0 * float(np.mean(times)) * scale
 
     # kernels: dominant by in-situ time
     kern = {
@@ -204,7 +278,8 @@ def main():
             "scaled": not args.full_fp64, "total_iters": st64["total_iters"]}
     accuracy = {"max_abs_dq_mixed_vs_fp64": float(np.abs(q_mixed[mask] - q64[mask]).max()),
                 "dQ_mixed_vs_fp64_on_sample": float(q_mixed[mask].sum() - q64[mask].sum()),
-                "Q": Q, "abs_Q_minus_round": abs(Q - round(Q)),
+                "Q": Q if scale == 1.0 else None,
+                "abs_Q_minus_round": abs(Q - round(Q)) if scale == 1.0 else None,
                 "max_abs_imag_q": st["max_abs_imag_q"], "sum_imag_q": st["sum_imag_q"],
                 "lam_min": st["lam_min"], "lam_max": st["lam_max"], "zolo_delta": st["zolo_delta"]}
     if args.full_fp64:
@@ -213,22 +288,25 @@ def main():
     cpu = None
     if not args.no_cpu:
         print("bench: CPU oracle sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(st["total_iters"], st["n_sources"], args.cpu_iters)
+        cpu = cpu_baseline(WORKLOAD, DIMS, R_GAP, round(st["total_iters"] * scale), round(st["n_sources"] * scale),
+                           args.cpu_iters)
 
     line = {
-        "metric": "sec per q(x) map + D_W HBM GB/s; mixed/batched vs plain FP64 at 16^3x32",
+        "metric": "sec per q(x) map + D_W HBM GB/s; mixed/batched vs plain FP64 at 16^3x32"
+                  if WORKLOAD == "noise16x32" else f"sec per q(x) map, {WORKLOAD}",
         "value": round(ms_per_step / 1000.0, 3), "unit": "s/map",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 1),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "16^3x32 near-identity SU(3) eps=0.2 seed 4, SMP normal mode r=4",
+        "config": {"workload": desc,
                    "lattice": list(DIMS), "n_sources": st["n_sources"], "n_batches": st["n_batches"],
                    "kappa": KAPPA, "zolotarev_poles": POLES, "cg_tol": TOL, "reliable_interval": RELIABLE,
                    "precision": "FP32 stencil and CG body, FP64 scalars/reliable updates/accumulation",
-                   "classes": len(classes),
+                   "classes": len(classes), "classes_per_map": ncls,
+                   "extrapolated": scale != 1.0,
                    "stencil_variants": {"f32_kind": ["site", "plane"][tuning[0]], "f32_rhs_per_thread": tuning[1],
                                         "f64_rhs_per_block": 1 << tuning[2]}},
-        "speedup_vs_fp64": round(fp64["s_per_map"] / (ms_per_step / 1000.0) * (len(classes) / ncls), 3),
+        "speedup_vs_fp64": round(fp64["s_per_map"] / (ms_per_step / 1000.0), 3),
         "roofline": roofline, "dslash": dslash, "fp64": fp64, "accuracy": accuracy,
         "breakdown_s": {"bounds": round(st["t_bounds_s"], 3), "solve": round(st["t_solve_s"], 3),
                         "contract": round(st["t_contract_s"], 3)},

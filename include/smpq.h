@@ -206,7 +206,8 @@ smpq_status smpq_set_graphs(smpq_ctx *ctx, int enable);
  * given precision to n_rhs right-hand sides, rotating through n_sets disjoint
  * input/output/link sets so that consecutive launches do not reuse cached data.
  * Returns the mean duration per launch (HIP events) and the algorithmic bytes per
- * launch (links once, every input and output spinor once). */
+ * launch (links once, every input and output spinor once).  The buffers take at most half
+ * of the free device memory: n_rhs is lowered to fit (SMPQ_ENOMEM if one does not). */
 smpq_status smpq_bench_dslash(smpq_ctx *ctx, smpq_precision prec, int n_rhs, int n_sets,
                               int launches, double *ms_per_launch, double *bytes_per_launch);
 
@@ -232,7 +233,8 @@ smpq_status smpq_compute_qx_multi(smpq_ctx *const *ctxs, int n_ctx, const int32_
                                   smpq_stats *st, int *failed);
 
 /* Choose the stencil variants for this lattice by timing them on n_rhs right-hand sides
- * (two rotating buffer sets, 10 launches each): FP32 kind (0: one site per thread; 1: one
+ * (two rotating buffer sets, 10 launches each; fewer right-hand sides where they would take
+ * more than half of the free device memory): FP32 kind (0: one site per thread; 1: one
  * 16x16 xy-plane per block staged in LDS, only when nx*ny = 256) with 2, 4 or 8 (kind 0) or
  * 4, 8 or 16 (kind 1) right-hand sides per thread, and the FP64 stencil with 1, 2 or 4
  * right-hand sides interleaved per block (*f64_lgr = log2).  The choice is kept by the

@@ -757,6 +757,12 @@ double time_dslash(smpq_ctx *c, int p, int n_rhs, int n_sets, int launches, doub
     const size_t units = p == 0 ? 12 : 6;
     const size_t vbytes = units * 16 * c->vs;
     const size_t lbytes = (size_t)c->V * (p == 0 ? 72 * 8 : 48 * 4);
+    // at most half of the free device memory: fewer right-hand sides if need be
+    size_t freeb = 0, totalb = 0;
+    HIPCHK(hipMemGetInfo(&freeb, &totalb));
+    const size_t per_rhs = 2 * vbytes * n_sets;
+    if (freeb / 2 < lbytes * n_sets + per_rhs) throw Fail{SMPQ_ENOMEM, "not enough device memory to time the stencil"};
+    n_rhs = (int)std::min<size_t>(n_rhs, (freeb / 2 - lbytes * n_sets) / per_rhs);
     std::vector<DevMem> ins(n_sets), outs(n_sets), links(n_sets);
     for (int k = 0; k < n_sets; ++k) {
         ins[k].ensure(vbytes * n_rhs);
@@ -1199,18 +1205,52 @@ smpq_status smpq_compute_qx_multi(smpq_ctx *const *ctxs, int n_ctx, const int32_
     // their workspaces already hold) in proportion to their work, V x classes
     {
         size_t freeb = 0, totalb = 0, held = 0, fixed = 0;
-        double wsum = 0.0;
         if (hipSetDevice(ctxs[0]->device) != hipSuccess || hipMemGetInfo(&freeb, &totalb) != hipSuccess)
             return give_up(0, SMPQ_EDEVICE);
         for (int k = 0; k < n_ctx; ++k) {
             held += workspace_bytes(ctxs[k]);
             if (ctxs[k]->mem_limit > 0) fixed += ctxs[k]->mem_limit;
-            else wsum += work[k];
         }
-        const double pool = std::max(0.0, 0.80 * (double)(freeb + held) - (double)fixed);
+        double pool = std::max(0.0, 0.80 * (double)(freeb + held) - (double)fixed);
+        // every context first gets one batch of 12 right-hand sides; the rest goes out in
+        // proportion to the work, never beyond what a context can use (all its sources at
+        // once), with what a capped context leaves handed on to the others
+        std::vector<double> share(n_ctx, 0.0), cap(n_ctx, 0.0), slotb(n_ctx, 0.0);
+        std::vector<char> open(n_ctx, 0);
         for (int k = 0; k < n_ctx; ++k) {
             smpq_ctx *c = ctxs[k];
-            c->run_limit = c->mem_limit > 0 ? c->mem_limit : (size_t)(pool * work[k] / std::max(wsum, 1.0));
+            if (c->mem_limit > 0 || cls[k].empty()) continue;
+            const double slot = (double)bytes_per_slot(c, c->prec == SMPQ_FP64 ? 0 : 1, c->zolo.n);
+            slotb[k] = slot;
+            share[k] = 12.0 * slot;
+            cap[k] = 12.0 * (double)cls[k].size() * slot;
+            pool -= share[k];
+            open[k] = 1;
+        }
+        if (pool < 0.0) return give_up(0, SMPQ_ENOMEM);
+        for (int round = 0; round < n_ctx && pool > 0.0; ++round) {
+            double wopen = 0.0;
+            for (int k = 0; k < n_ctx; ++k)
+                if (open[k]) wopen += work[k];
+            if (wopen <= 0.0) break;
+            double left = 0.0;
+            for (int k = 0; k < n_ctx; ++k) {
+                if (!open[k]) continue;
+                const double add = pool * work[k] / wopen;
+                if (share[k] + add >= cap[k]) {
+                    left += share[k] + add - cap[k];
+                    share[k] = cap[k];
+                    open[k] = 0;
+                } else {
+                    share[k] += add;
+                }
+            }
+            pool = left;
+        }
+        for (int k = 0; k < n_ctx; ++k) {
+            smpq_ctx *c = ctxs[k];
+            // half a slot of slack so that rounding cannot drop the last whole slot
+            c->run_limit = c->mem_limit > 0 ? c->mem_limit : (size_t)(share[k] + 0.5 * slotb[k]);
         }
         for (int k = 0; k < n_ctx; ++k) {
             smpq_ctx *c = ctxs[k];
