@@ -215,8 +215,7 @@ def main():
     # untimed set-up: workspace allocation and first launches of every kernel
     smpq.smpq_set_zolotarev(ctx, POLES, 0.14, 2.73)
     tuning = smpq.smpq_autotune(ctx, 96)
-    print(f"bench: stencil variants (f32 kind, f32 rhs/thread, f64 log2 rhs/block) = {tuning}",
-          file=sys.stderr, flush=True)
+    print(f"bench: stencil variants {tuning}", file=sys.stderr, flush=True)
     smpq.smpq_prepare(ctx)
     smpq.smpq_compute_qx_classes(ctx, [0])
     smpq.smpq_set_timing(ctx, True)
@@ -304,8 +303,10 @@ def main():
                    "precision": "FP32 stencil and CG body, FP64 scalars/reliable updates/accumulation",
                    "classes": len(classes), "classes_per_map": ncls,
                    "extrapolated": scale != 1.0,
-                   "stencil_variants": {"f32_kind": ["site", "plane"][tuning[0]], "f32_rhs_per_thread": tuning[1],
-                                        "f64_rhs_per_block": 1 << tuning[2]}},
+                   "stencil_variants": {"f32_kind": ["site", "plane", "xy-tile"][tuning["f32_kind"]],
+                                        "f32_rhs_per_thread": tuning["f32_nr"],
+                                        "plane_band": tuning["plane_band"],
+                                        "f64_rhs_per_block": 1 << tuning["f64_lgr"]}},
         "speedup_vs_fp64": round(fp64["s_per_map"] / (ms_per_step / 1000.0), 3),
         "roofline": roofline, "dslash": dslash, "fp64": fp64, "accuracy": accuracy,
         "breakdown_s": {"bounds": round(st["t_bounds_s"], 3), "solve": round(st["t_solve_s"], 3),

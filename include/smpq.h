@@ -232,21 +232,33 @@ smpq_status smpq_compute_qx_multi(smpq_ctx *const *ctxs, int n_ctx, const int32_
                                   const int *n_classes, double *const *qx, double *const *qx_imag,
                                   smpq_stats *st, int *failed);
 
-/* Choose the stencil variants for this lattice by timing them on n_rhs right-hand sides
- * (two rotating buffer sets, 10 launches each; fewer right-hand sides where they would take
- * more than half of the free device memory): FP32 kind (0: one site per thread; 1: one
- * 16x16 xy-plane per block staged in LDS, only when nx*ny = 256) with 2, 4 or 8 (kind 0) or
- * 4, 8 or 16 (kind 1) right-hand sides per thread, and the FP64 stencil with 1, 2 or 4
- * right-hand sides interleaved per block (*f64_lgr = log2).  The choice is kept by the
- * context; outputs may be NULL.  Without this call the context uses kind 1 / 8 where the
- * plane fits, else kind 0 / 4, and f64_lgr = 1. */
-smpq_status smpq_autotune(smpq_ctx *ctx, int n_rhs, int *f32_kind, int *f32_nr, int *f64_lgr);
+/* Stencil variants.  f32_kind: 0 = one site per thread (f32_nr = 2, 4 or 8 right-hand sides
+ * per thread, links held in registers across them); 1 = one 16x16 xy-plane per block staged
+ * in LDS (nx*ny = 256; f32_nr = 4, 8 or 16); 2 = xy-tiles of ty rows plus one halo row on
+ * each side staged in LDS, ty the largest divisor of ny with nx*ty <= 256 and a multiple of 64
+ * (nx <= 64; f32_nr = 4, 8 or 16).  plane_band (kinds 1 and 2; 1, 2 or 4, dividing nz): the
+ * blocks take the (z, t) planes in bands of that many z with t running inside a band, so the
+ * +-t neighbours of a plane were read shortly before (1 = z fastest).  f64_lgr: the FP64
+ * stencil interleaves 2^f64_lgr = 1, 2 or 4 right-hand sides over the lanes of a block.
+ * Results do not depend on the variant beyond the rounding order of FP32 sums. */
+typedef struct {
+    int f32_kind, f32_nr, f64_lgr, plane_band;
+} smpq_tuning;
 
-/* Select the stencil variants explicitly (same meaning as the outputs of smpq_autotune).
- * SMPQ_EINVAL if a variant is not built or does not fit the lattice (kind 1 needs
- * nx*ny = 256); the previous choice is then kept.  Results do not depend on the choice
- * beyond rounding order in FP32. */
-smpq_status smpq_set_tuning(smpq_ctx *ctx, int f32_kind, int f32_nr, int f64_lgr);
+/* Choose the variants for this lattice by timing each on n_rhs right-hand sides (two
+ * rotating buffer sets, 10 launches each; fewer right-hand sides where they would take more
+ * than half of the free device memory).  The choice is kept by the context and written to
+ * *chosen (may be NULL); on an error the previous choice is kept.  Without this call a
+ * context uses kind 1 / 8 where the plane fits, else kind 2 / 8 where a tile fits, else kind
+ * 0 / 4, with plane_band 1 and f64_lgr 1. */
+smpq_status smpq_autotune(smpq_ctx *ctx, int n_rhs, smpq_tuning *chosen);
+
+/* Select the variants explicitly.  SMPQ_EINVAL (previous choice kept) if a variant is not
+ * built or does not fit the lattice. */
+smpq_status smpq_set_tuning(smpq_ctx *ctx, const smpq_tuning *tuning);
+
+/* The variants in use. */
+smpq_status smpq_get_tuning(smpq_ctx *ctx, smpq_tuning *tuning);
 
 #ifdef __cplusplus
 }

@@ -15,14 +15,14 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 __all__ = [
-    "SMPQ_FP64", "SMPQ_MIXED_FP32", "SmpqError", "SmpqStats", "LIB_PATH", "EXPORTS",
+    "SMPQ_FP64", "SMPQ_MIXED_FP32", "SmpqError", "SmpqStats", "SmpqTuning", "LIB_PATH", "EXPORTS",
     "smpq_create", "smpq_destroy", "smpq_strerror", "smpq_last_error", "smpq_load_gauge",
     "smpq_set_kappa", "smpq_lanczos", "smpq_estimate_bounds", "smpq_set_zolotarev",
     "smpq_get_zolotarev", "smpq_set_solver", "smpq_set_batch", "smpq_set_scheme",
     "smpq_set_point_scheme", "smpq_get_coloring", "smpq_apply_dw", "smpq_apply_dov",
     "smpq_compute_qx", "smpq_compute_qx_classes", "smpq_compute_qx_points", "smpq_prepare", "smpq_set_stream",
     "smpq_set_timing", "smpq_set_graphs", "smpq_bench_dslash", "smpq_autotune",
-    "smpq_set_tuning", "smpq_set_memory_limit", "smpq_compute_qx_multi",
+    "smpq_set_tuning", "smpq_get_tuning", "smpq_set_memory_limit", "smpq_compute_qx_multi",
 ]
 
 SMPQ_FP64 = 0
@@ -30,6 +30,13 @@ SMPQ_MIXED_FP32 = 1
 _c_int_p = ctypes.POINTER(ctypes.c_int)
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p
+
+
+class SmpqTuning(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int) for n in ("f32_kind", "f32_nr", "f64_lgr", "plane_band")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
 
 
 class SmpqStats(ctypes.Structure):
@@ -73,8 +80,9 @@ _SIG = {
     "smpq_set_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
     "smpq_bench_dslash": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_double_p,
                                          _c_double_p]),
-    "smpq_autotune": (ctypes.c_int, [_vp, ctypes.c_int, _c_int_p, _c_int_p, _c_int_p]),
-    "smpq_set_tuning": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "smpq_autotune": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(SmpqTuning)]),
+    "smpq_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(SmpqTuning)]),
+    "smpq_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(SmpqTuning)]),
     "smpq_set_memory_limit": (ctypes.c_int, [_vp, ctypes.c_size_t]),
     "smpq_compute_qx_multi": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int,
                                              ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)), _c_int_p,
@@ -289,14 +297,21 @@ def smpq_bench_dslash(ctx, precision, n_rhs, n_sets, launches):
 
 
 def smpq_autotune(ctx, n_rhs=48):
-    """Returns (f32_kind, f32_nr, f64_lgr) chosen by timing on this lattice."""
-    k, n, l = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-    _check(ctx, _lib.smpq_autotune(ctx.ptr, int(n_rhs), ctypes.byref(k), ctypes.byref(n), ctypes.byref(l)))
-    return k.value, n.value, l.value
+    """Times the stencil variants on this lattice; returns the chosen ones as a dict."""
+    t = SmpqTuning()
+    _check(ctx, _lib.smpq_autotune(ctx.ptr, int(n_rhs), ctypes.byref(t)))
+    return t.as_dict()
 
 
-def smpq_set_tuning(ctx, f32_kind, f32_nr, f64_lgr):
-    _check(ctx, _lib.smpq_set_tuning(ctx.ptr, int(f32_kind), int(f32_nr), int(f64_lgr)))
+def smpq_set_tuning(ctx, f32_kind, f32_nr, f64_lgr, plane_band=1):
+    t = SmpqTuning(int(f32_kind), int(f32_nr), int(f64_lgr), int(plane_band))
+    _check(ctx, _lib.smpq_set_tuning(ctx.ptr, ctypes.byref(t)))
+
+
+def smpq_get_tuning(ctx):
+    t = SmpqTuning()
+    _check(ctx, _lib.smpq_get_tuning(ctx.ptr, ctypes.byref(t)))
+    return t.as_dict()
 
 
 def smpq_set_memory_limit(ctx, nbytes):

@@ -157,8 +157,11 @@ struct smpq_ctx {
     long long gen = 0;
     int *h_count = nullptr;     // pinned
     // stencil variant (see Geom); defaults: plane tile where the xy-plane has 256 sites
-    int f32_kind = 0, f32_nr = 4, f64_lgr = 1;
-    Geom geom() const { return Geom{dims[0], dims[1], dims[2], dims[3], V, vs, f32_kind, f32_nr, f64_lgr}; }
+    int f32_kind = 0, f32_nr = 4, f64_lgr = 1, band = 1;
+    Geom geom() const {
+        return Geom{dims[0], dims[1], dims[2], dims[3], V, vs, f32_kind, f32_nr, f64_lgr, band,
+                    tile_rows(dims[0], dims[1])};
+    }
 };
 
 namespace {
@@ -833,6 +836,9 @@ smpq_status smpq_create(const int dims[4], int device, smpq_ctx **out) {
     if (dims[0] * dims[1] == 256) {
         c->f32_kind = 1;
         c->f32_nr = 8;
+    } else if (tile_rows(dims[0], dims[1]) > 0) {
+        c->f32_kind = 2;
+        c->f32_nr = 8;
     }
     if (device >= 0) {
         int n = 0;
@@ -1356,57 +1362,85 @@ smpq_status smpq_bench_dslash(smpq_ctx *c, smpq_precision prec, int n_rhs, int n
     });
 }
 
-smpq_status smpq_set_tuning(smpq_ctx *c, int f32_kind, int f32_nr, int f64_lgr) {
+smpq_status smpq_set_tuning(smpq_ctx *c, const smpq_tuning *t) {
     return guarded(c, [&] {
+        if (!t) throw Fail{SMPQ_EINVAL, "null tuning"};
         Geom g = c->geom();
-        g.f32_kind = f32_kind;
-        g.f32_nr = f32_nr;
-        g.f64_lgr = f64_lgr;
+        g.f32_kind = t->f32_kind;
+        g.f32_nr = t->f32_nr;
+        g.f64_lgr = t->f64_lgr;
+        g.band = t->plane_band;
         if (!valid_tuning(0, g) || !valid_tuning(1, g))
             throw Fail{SMPQ_EINVAL, "unsupported stencil variant for this lattice"};
-        c->f32_kind = f32_kind;
-        c->f32_nr = f32_nr;
-        c->f64_lgr = f64_lgr;
+        c->f32_kind = t->f32_kind;
+        c->f32_nr = t->f32_nr;
+        c->f64_lgr = t->f64_lgr;
+        c->band = t->plane_band;
         c->gen++;
     });
 }
 
-smpq_status smpq_autotune(smpq_ctx *c, int n_rhs, int *f32_kind, int *f32_nr, int *f64_lgr) {
+smpq_status smpq_get_tuning(smpq_ctx *c, smpq_tuning *t) {
+    return guarded(c, [&] {
+        if (!t) throw Fail{SMPQ_EINVAL, "null tuning"};
+        *t = smpq_tuning{c->f32_kind, c->f32_nr, c->f64_lgr, c->band};
+    });
+}
+
+smpq_status smpq_autotune(smpq_ctx *c, int n_rhs, smpq_tuning *chosen) {
     return guarded(c, [&] {
         if (n_rhs < 1) throw Fail{SMPQ_EINVAL, "n_rhs must be >= 1"};
         need_device(c);
         if (!c->have_gauge) throw Fail{SMPQ_ESTATE, "no gauge field loaded"};
         double by;
-        std::vector<std::pair<int, int>> cand = {{0, 2}, {0, 4}, {0, 8}};
-        if (plane_tileable(c->geom())) cand.insert(cand.end(), {{1, 4}, {1, 8}, {1, 16}});
+        struct Cand {
+            int kind, nr, band;
+        };
+        std::vector<Cand> cand = {{0, 2, 1}, {0, 4, 1}, {0, 8, 1}};
+        const Geom g0 = c->geom();
+        for (int kind = 1; kind <= 2; ++kind) {
+            if (kind == 1 ? !plane_tileable(g0) : g0.tile_y == 0) continue;
+            for (int nr : {4, 8, 16})
+                for (int band : {1, 2, 4})
+                    if (c->dims[2] % band == 0) cand.push_back({kind, nr, band});
+        }
+        const smpq_tuning keep{c->f32_kind, c->f32_nr, c->f64_lgr, c->band};
         double best = INFINITY;
-        std::pair<int, int> pick = {c->f32_kind, c->f32_nr};
-        for (auto kn : cand) {
-            c->f32_kind = kn.first;
-            c->f32_nr = kn.second;
-            const double t = time_dslash(c, 1, n_rhs, 2, 10, &by);
-            if (t < best) {
-                best = t;
-                pick = kn;
+        Cand pick{keep.f32_kind, keep.f32_nr, keep.plane_band};
+        try {
+            for (const Cand &k : cand) {
+                c->f32_kind = k.kind;
+                c->f32_nr = k.nr;
+                c->band = k.band;
+                const double t = time_dslash(c, 1, n_rhs, 2, 10, &by);
+                if (t < best) {
+                    best = t;
+                    pick = k;
+                }
             }
-        }
-        c->f32_kind = pick.first;
-        c->f32_nr = pick.second;
-        best = INFINITY;
-        int lpick = c->f64_lgr;
-        for (int l = 0; l <= 2; ++l) {
-            c->f64_lgr = l;
-            const double t = time_dslash(c, 0, n_rhs, 2, 10, &by);
-            if (t < best) {
-                best = t;
-                lpick = l;
+            c->f32_kind = pick.kind;
+            c->f32_nr = pick.nr;
+            c->band = pick.band;
+            best = INFINITY;
+            int lpick = keep.f64_lgr;
+            for (int l = 0; l <= 2; ++l) {
+                c->f64_lgr = l;
+                const double t = time_dslash(c, 0, n_rhs, 2, 10, &by);
+                if (t < best) {
+                    best = t;
+                    lpick = l;
+                }
             }
+            c->f64_lgr = lpick;
+        } catch (...) {
+            c->f32_kind = keep.f32_kind;
+            c->f32_nr = keep.f32_nr;
+            c->f64_lgr = keep.f64_lgr;
+            c->band = keep.plane_band;
+            throw;
         }
-        c->f64_lgr = lpick;
         c->gen++;   // captured graphs used the previous variants
-        if (f32_kind) *f32_kind = c->f32_kind;
-        if (f32_nr) *f32_nr = c->f32_nr;
-        if (f64_lgr) *f64_lgr = c->f64_lgr;
+        if (chosen) *chosen = smpq_tuning{c->f32_kind, c->f32_nr, c->f64_lgr, c->band};
     });
 }
 

@@ -18,9 +18,11 @@ struct Geom {
     int nx, ny, nz, nt, V;
     size_t vs;
     // stencil tuning (chosen per lattice, see smpq_autotune): FP32 kernel kind (0: one site per
-    // thread, 1: 16x16 xy-plane per block in LDS), FP32 right-hand sides per thread, and log2 of
-    // the right-hand sides interleaved over the lanes of an FP64 block
-    int f32_kind, f32_nr, f64_lgr;
+    // thread, 1: 16x16 xy-plane per block in LDS, 2: xy-tile of tile_y rows with y-halos in
+    // LDS), FP32 right-hand sides per thread, log2 of the right-hand sides interleaved over the
+    // lanes of an FP64 block, and the z-band of the plane order of kinds 1 and 2;
+    // tile_y = tile_rows(nx, ny) (0 when no tile fits)
+    int f32_kind, f32_nr, f64_lgr, band, tile_y;
 };
 
 // Right-hand-side addressing: slot k of a launch uses offset (slot * slot_stride + extra)
@@ -69,7 +71,10 @@ void launch_dslash(int prec, bool dag, int epi, const void *U, const void *in, s
                    double *partial, hipStream_t st);
 __host__ __device__ int site_blocks(const Geom &g);   // blocks of 256 sites
 int dslash_partials(int prec, const Geom &g);         // partials per slot of the stencil epilogue
-bool plane_tileable(const Geom &g);                    // the xy-plane has exactly 256 sites
+bool plane_tileable(const Geom &g);
+// Rows per xy-tile: the largest divisor ty >= 2 of ny with nx * ty <= 256 and a multiple of 64
+// (nx <= 64); 0 when there is none.
+int tile_rows(int nx, int ny);                    // the xy-plane has exactly 256 sites
 bool valid_tuning(int prec, const Geom &g);            // g's tuning names an instantiated variant
 int unit_parts(int prec, const Geom &g);        // partials per slot written by element-wise kernels
 size_t partial_stride(const Geom &g);           // slot stride of the partial buffer (>= both)

@@ -107,6 +107,15 @@ __device__ __forceinline__ int xcd_swizzle(int b, int nb) {
     return xcd * q + (xcd < r ? xcd : r) + k;
 }
 
+// Plane p of the block order -> (z, t) plane index z + nz t.  The planes are taken in bands of
+// g.band consecutive z: t runs over the whole extent inside a band, so that the +-t
+// neighbours of a plane were staged g.band blocks earlier (still in L2) rather than nz.
+__device__ __forceinline__ int plane_order(int p, const Geom &g) {
+    if (g.band == 1) return p;
+    const int per = g.band * g.nt, b = p / per, i = p % per;
+    return b * g.band + i % g.band + g.nz * (i / g.band);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -306,6 +315,141 @@ __global__ __launch_bounds__(kBlock) void k_dslash_f32(const float4 *__restrict_
     }
 }
 
+// FP32 stencil on xy-tiles: a block of nx * ty threads (ty = g.tile_y rows, a divisor of ny)
+// covers rows y0 .. y0 + ty - 1 of one (z, t) plane, one site per thread.  For each
+// right-hand side the block stages those rows plus one halo row on each side (periodic in y)
+// in LDS, so the +-x and +-y neighbours come from LDS and only +-z and +-t from global memory
+// (their rows are the tiles of the neighbouring planes).  Links as in k_dslash_f32.
+template <int NR, bool DAG, int EPI>
+__global__ __launch_bounds__(kBlock) void k_dslash_f32_tile(const float4 *__restrict__ U, const float4 *__restrict__ in,
+                                                            size_t in_stride, size_t in_extra,
+                                                            float4 *__restrict__ out, size_t out_stride,
+                                                            const float4 *__restrict__ aux, size_t aux_stride,
+                                                            size_t aux_extra, Geom g, float kappa, float sigma,
+                                                            Slots sl, int nsb, double *__restrict__ partial,
+                                                            size_t pstride) {
+    constexpr int SF = DAG ? -1 : 1;
+    constexpr int kTileSites = kBlock + 2 * 64;
+    __shared__ float4 tile[6][kTileSites];
+    const int L = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int sb = L % nsb, rg = L / nsb;
+    const int cnt = slot_count(sl);
+    const int k0 = rg * NR;
+    if (k0 >= cnt) return;  // uniform over the block
+    const int nx = g.nx, ny = g.ny, ty = g.tile_y;
+    const int tiles_per_plane = ny / ty;
+    const int pl = plane_order(sb / tiles_per_plane, g), y0 = (sb % tiles_per_plane) * ty;
+    const int x = threadIdx.x % nx, yl = threadIdx.x / nx;
+    const int plane0 = pl * nx * ny;
+    const int s = plane0 + (y0 + yl) * nx + x;   // every site is valid: V is a multiple of the tile
+    const Nbr nb = neighbours(s, nx, ny, g.nz, g.nt);
+    // halo loads: threads 0 .. 2nx-1 also fetch row y0 - 1 (first nx) or y0 + ty (next nx)
+    const bool halo = (int)threadIdx.x < 2 * nx;
+    const int hrow = threadIdx.x < (unsigned)nx ? 0 : ty + 1;
+    const int hy = threadIdx.x < (unsigned)nx ? (y0 + ny - 1) % ny : (y0 + ty) % ny;
+    const int hsite = plane0 + hy * nx + x;
+    const int hl = hrow * nx + x;
+    float4 lf[4][3], lb[4][3];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            lf[mu][j] = U[(size_t)(mu * 3 + j) * g.V + s];
+            lb[mu][j] = U[(size_t)(mu * 3 + j) * g.V + nb.bwd[mu]];
+        }
+    const int me = (yl + 1) * nx + x;
+    const int xf = (yl + 1) * nx + (x == nx - 1 ? 0 : x + 1);
+    const int xb = (yl + 1) * nx + (x == 0 ? nx - 1 : x - 1);
+    const int yf = me + nx, yb = me - nx;
+    double dot[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) dot[r] = 0.0;
+#pragma unroll 1
+    for (int r = 0; r < NR; ++r) {
+        const int k = k0 + r;
+        if (k >= cnt) break;  // uniform over the block
+        const int slot = slot_of(sl, k);
+        const float4 *src = in + slot * in_stride + in_extra;
+        __syncthreads();  // the previous right-hand side is done with the tile
+#pragma unroll
+        for (int j = 0; j < 6; ++j) tile[j][me] = src[j * g.vs + s];
+        if (halo) {
+#pragma unroll
+            for (int j = 0; j < 6; ++j) tile[j][hl] = src[j * g.vs + hsite];
+        }
+        cpx<float> acc[12], u[9], p[12], h[6], w[6];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[c] = {0.f, 0.f};
+#define SMPQ_GLOBAL_HOP(MU)                                                          \
+        unpack_rows(lf[MU][0], lf[MU][1], lf[MU][2], u);                             \
+        Store<float>::load(src, g.vs, nb.fwd[MU], p);                                \
+        project<MU, SF>(p, h);                                                       \
+        su3_mul(u, h, w);                                                            \
+        accumulate<MU, SF>(acc, w);                                                  \
+        unpack_rows(lb[MU][0], lb[MU][1], lb[MU][2], u);                             \
+        Store<float>::load(src, g.vs, nb.bwd[MU], p);                                \
+        project<MU, -SF>(p, h);                                                      \
+        su3_dag_mul(u, h, w);                                                        \
+        accumulate<MU, -SF>(acc, w);
+        SMPQ_GLOBAL_HOP(2)
+        SMPQ_GLOBAL_HOP(3)
+#undef SMPQ_GLOBAL_HOP
+        __syncthreads();  // the tile is complete
+#define SMPQ_TILE_LOAD(L, P)                                                         \
+        _Pragma("unroll") for (int j = 0; j < 6; ++j) {                              \
+            const float4 t_ = tile[j][L];                                            \
+            P[2 * j] = {t_.x, t_.y};                                                 \
+            P[2 * j + 1] = {t_.z, t_.w};                                             \
+        }
+#define SMPQ_TILE_HOP(MU, LF, LB)                                                    \
+        unpack_rows(lf[MU][0], lf[MU][1], lf[MU][2], u);                             \
+        SMPQ_TILE_LOAD(LF, p)                                                        \
+        project<MU, SF>(p, h);                                                       \
+        su3_mul(u, h, w);                                                            \
+        accumulate<MU, SF>(acc, w);                                                  \
+        unpack_rows(lb[MU][0], lb[MU][1], lb[MU][2], u);                             \
+        SMPQ_TILE_LOAD(LB, p)                                                        \
+        project<MU, -SF>(p, h);                                                      \
+        su3_dag_mul(u, h, w);                                                        \
+        accumulate<MU, -SF>(acc, w);
+        SMPQ_TILE_HOP(0, xf, xb)
+        SMPQ_TILE_HOP(1, yf, yb)
+#undef SMPQ_TILE_HOP
+        cpx<float> v[12];
+        SMPQ_TILE_LOAD(me, v)
+#undef SMPQ_TILE_LOAD
+#pragma unroll
+        for (int c = 0; c < 12; ++c) v[c] = v[c] - kappa * acc[c];
+        if constexpr (EPI == 1) {
+            Store<float>::load(aux + slot * aux_stride + aux_extra, g.vs, s, p);
+            double d = 0.0;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                v[c] = v[c] + sigma * p[c];
+                d += (double)p[c].re * (double)v[c].re + (double)p[c].im * (double)v[c].im;
+            }
+            dot[r] = d;
+        }
+        Store<float>::store(out + slot * out_stride, g.vs, s, v);
+    }
+    if constexpr (EPI == 1) {
+        __shared__ double lds[NR][kBlock / 64];
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const int nw = blockDim.x >> 6;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const double t = wave_sum(dot[r]);
+            if (lane == 0) lds[r][wv] = t;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < NR && k0 + (int)threadIdx.x < cnt) {
+            double t = 0.0;
+            for (int i = 0; i < nw; ++i) t += lds[threadIdx.x][i];
+            partial[(size_t)slot_of(sl, k0 + threadIdx.x) * pstride + sb] = t;
+        }
+    }
+}
+
 template <int NR, bool DAG, int EPI>
 __global__ __launch_bounds__(kBlock) void k_dslash_f32_plane(const float4 *__restrict__ U, const float4 *__restrict__ in,
                                                              size_t in_stride, size_t in_extra,
@@ -321,7 +465,7 @@ __global__ __launch_bounds__(kBlock) void k_dslash_f32_plane(const float4 *__res
     const int cnt = slot_count(sl);
     const int k0 = rg * NR;
     if (k0 >= cnt) return;  // uniform over the block
-    const int base = sb * kBlock;
+    const int base = plane_order(sb, g) * kBlock;
     const int s = base + threadIdx.x;  // every site is valid: V is a multiple of the plane
     const Nbr nb = neighbours(s, g.nx, g.ny, g.nz, g.nt);
     float4 lf[4][3], lb[4][3];
@@ -422,11 +566,28 @@ __host__ __device__ int site_blocks(const Geom &g) { return (g.V + kBlock - 1) /
 static int fp64_parts(const Geom &g) { return (g.V + (kBlock >> g.f64_lgr) - 1) / (kBlock >> g.f64_lgr); }
 size_t partial_stride(const Geom &g) { return (size_t)12 * site_blocks(g); }
 bool plane_tileable(const Geom &g) { return g.nx * g.ny == kBlock; }
-int dslash_partials(int prec, const Geom &g) { return prec == 0 ? fp64_parts(g) : site_blocks(g); }
+
+int tile_rows(int nx, int ny) {
+    if (nx > 64) return 0;
+    for (int ty = kBlock / nx; ty >= 2; --ty)
+        if (ny % ty == 0 && (nx * ty) % 64 == 0) return ty;
+    return 0;
+}
+
+static int tile_blocks(const Geom &g) { return g.V / (g.nx * g.tile_y); }
+
+int dslash_partials(int prec, const Geom &g) {
+    if (prec == 0) return fp64_parts(g);
+    return g.f32_kind >= 2 ? tile_blocks(g) : site_blocks(g);
+}
 
 bool valid_tuning(int prec, const Geom &g) {
     if (prec == 0) return g.f64_lgr >= 0 && g.f64_lgr <= 2;
-    if (g.f32_kind == 1) return plane_tileable(g) && (g.f32_nr == 4 || g.f32_nr == 8 || g.f32_nr == 16);
+    const bool nr_tile = g.f32_nr == 4 || g.f32_nr == 8 || g.f32_nr == 16;
+    if (g.f32_kind == 1) return plane_tileable(g) && nr_tile && g.band >= 1 && g.nz % g.band == 0;
+    const bool tiled = g.tile_y > 0 && g.tile_y == tile_rows(g.nx, g.ny);
+    const bool band_ok = g.band >= 1 && g.nz % g.band == 0;
+    if (g.f32_kind == 2) return tiled && nr_tile && band_ok;
     return g.f32_kind == 0 && (g.f32_nr == 2 || g.f32_nr == 4 || g.f32_nr == 8);
 }
 
@@ -445,13 +606,18 @@ static void launch_dslash_t(const void *U, const void *in, size_t in_stride, siz
                        aux_extra, g, (T)kappa, (T)sigma, sl, lgR, nsb, partial, partial_stride(g));
 }
 
-template <int NR, bool DAG, int EPI, bool PLANE>
+template <int NR, bool DAG, int EPI, int KIND>
 static void launch_f32(const void *U, const void *in, size_t in_stride, size_t in_extra, void *out, size_t out_stride,
                        const void *aux, size_t aux_stride, size_t aux_extra, const Geom &g, double kappa, double sigma,
                        Slots sl, int max_slots, double *partial, hipStream_t st) {
-    const int nsb = site_blocks(g);
+    const int nsb = KIND >= 2 ? tile_blocks(g) : site_blocks(g);
     const int ngr = (max_slots + NR - 1) / NR;
-    if constexpr (PLANE)
+    if constexpr (KIND == 2)
+        hipLaunchKernelGGL((k_dslash_f32_tile<NR, DAG, EPI>), dim3(nsb * ngr), dim3(g.nx * g.tile_y), 0, st,
+                           (const float4 *)U, (const float4 *)in, in_stride, in_extra, (float4 *)out, out_stride,
+                           (const float4 *)aux, aux_stride, aux_extra, g, (float)kappa, (float)sigma, sl, nsb, partial,
+                           partial_stride(g));
+    else if constexpr (KIND == 1)
         hipLaunchKernelGGL((k_dslash_f32_plane<NR, DAG, EPI>), dim3(nsb * ngr), dim3(kBlock), 0, st,
                            (const float4 *)U, (const float4 *)in, in_stride, in_extra, (float4 *)out, out_stride,
                            (const float4 *)aux, aux_stride, aux_extra, g, (float)kappa, (float)sigma, sl, nsb, partial,
@@ -469,14 +635,18 @@ static void launch_f32_tuned(const void *U, const void *in, size_t in_stride, si
 #define SMPQ_F32(NR, PL)                                                                                       \
     launch_f32<NR, DAG, EPI, PL>(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra, g, kappa, \
                                  sigma, sl, max_slots, partial, st)
-    if (g.f32_kind == 1) {
-        if (g.f32_nr == 4) SMPQ_F32(4, true);
-        else if (g.f32_nr == 16) SMPQ_F32(16, true);
-        else SMPQ_F32(8, true);
+    if (g.f32_kind == 2) {
+        if (g.f32_nr == 4) SMPQ_F32(4, 2);
+        else if (g.f32_nr == 16) SMPQ_F32(16, 2);
+        else SMPQ_F32(8, 2);
+    } else if (g.f32_kind == 1) {
+        if (g.f32_nr == 4) SMPQ_F32(4, 1);
+        else if (g.f32_nr == 16) SMPQ_F32(16, 1);
+        else SMPQ_F32(8, 1);
     } else {
-        if (g.f32_nr == 2) SMPQ_F32(2, false);
-        else if (g.f32_nr == 8) SMPQ_F32(8, false);
-        else SMPQ_F32(4, false);
+        if (g.f32_nr == 2) SMPQ_F32(2, 0);
+        else if (g.f32_nr == 8) SMPQ_F32(8, 0);
+        else SMPQ_F32(4, 0);
     }
 #undef SMPQ_F32
 }

@@ -35,6 +35,7 @@ def _zolo_interval(U, lat):
 
 SITE_VARIANTS = [(0, nr, lgr) for nr, lgr in ((2, 0), (4, 1), (8, 2))]
 PLANE_VARIANTS = [(1, nr, lgr) for nr, lgr in ((4, 0), (8, 1), (16, 2))]
+TILE_VARIANTS = [(2, nr, lgr) for nr, lgr in ((4, 0), (8, 1), (16, 2))]
 
 
 @pytest.mark.parametrize("dims", [(6, 4, 4, 6), (5, 3, 4, 7), (4, 4, 4, 4)])
@@ -61,7 +62,7 @@ def test_dslash_parity(dims, nrhs):
         smpq.smpq_set_tuning(c, 1, 8, 1)
 
 
-@pytest.mark.parametrize("dims", [(16, 16, 2, 2), (16, 16, 3, 2)])
+@pytest.mark.parametrize("dims", [(16, 16, 2, 2), (16, 16, 3, 2), (16, 16, 4, 3)])
 @pytest.mark.parametrize("nrhs", [1, 9, 17])
 def test_dslash_parity_plane_tiled(dims, nrhs):
     """16x16 xy-planes: the FP32 kernel that stages one plane per block in LDS, with 4, 8 and
@@ -73,10 +74,13 @@ def test_dslash_parity_plane_tiled(dims, nrhs):
     c = _ctx(dims, U)
     for dag in (False, True):
         ref = np.stack([apply_dw(U, lat, KAPPA, p, dagger=dag) for p in psi])
-        for tune in PLANE_VARIANTS:
-            smpq.smpq_set_tuning(c, *tune)
-            out32 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_MIXED_FP32)
-            assert np.abs(out32 - ref).max() <= 2e-6 * np.abs(ref).max(), tune
+        for tune in PLANE_VARIANTS + TILE_VARIANTS:
+            for band in (1, 2, 4):
+                if dims[2] % band:
+                    continue
+                smpq.smpq_set_tuning(c, *tune, band)
+                out32 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_MIXED_FP32)
+                assert np.abs(out32 - ref).max() <= 2e-6 * np.abs(ref).max(), (tune, band)
             out64 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_FP64)
             assert np.abs(out64 - ref).max() <= 1e-13 * np.abs(ref).max(), tune
 
@@ -88,8 +92,10 @@ def test_autotune_picks_a_valid_variant_and_keeps_parity():
     U = si.near_identity_su3(dims, 0.5, 13)
     psi = si.random_spinors(dims, 3, 14)
     c = _ctx(dims, U)
-    kind, nr, lgr = smpq.smpq_autotune(c, 8)
-    assert (kind, nr, lgr) in [(k, n, l) for k, n, _ in SITE_VARIANTS + PLANE_VARIANTS for l in range(3)]
+    t = smpq.smpq_autotune(c, 8)
+    assert smpq.smpq_get_tuning(c) == t
+    assert (t["f32_kind"], t["f32_nr"]) in [(k, n) for k, n, _ in SITE_VARIANTS + PLANE_VARIANTS + TILE_VARIANTS]
+    assert t["f64_lgr"] in (0, 1, 2) and t["plane_band"] in (1, 2)
     ref = np.stack([apply_dw(U, lat, KAPPA, p) for p in psi])
     out32 = smpq.smpq_apply_dw(c, psi, precision=smpq.SMPQ_MIXED_FP32)
     assert np.abs(out32 - ref).max() <= 2e-6 * np.abs(ref).max()
@@ -97,8 +103,33 @@ def test_autotune_picks_a_valid_variant_and_keeps_parity():
     assert np.abs(out64 - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
-def test_qx_plane_tiled_mixed():
-    dims = (16, 16, 2, 2)
+@pytest.mark.parametrize("dims", [(24, 16, 2, 2), (32, 16, 4, 3), (8, 64, 2, 2)])
+@pytest.mark.parametrize("nrhs", [1, 9, 17])
+def test_dslash_parity_xy_tiles(dims, nrhs):
+    """xy-tiles of ty < ny rows with halo rows staged in LDS (ty = 8, 8, 32), 4, 8 and 16
+    right-hand sides per thread, against the oracle."""
+    print(f"xy-tile dslash parity dims={dims} nrhs={nrhs}", flush=True)
+    lat = Lattice(dims)
+    U = si.near_identity_su3(dims, 0.5, 15)
+    psi = si.random_spinors(dims, nrhs, 16)
+    c = _ctx(dims, U)
+    with pytest.raises(smpq.SmpqError):
+        smpq.smpq_set_tuning(c, 1, 8, 1)
+    for dag in (False, True):
+        ref = np.stack([apply_dw(U, lat, KAPPA, p, dagger=dag) for p in psi])
+        for tune in TILE_VARIANTS:
+            for band in (1, 2, 4):
+                if dims[2] % band:
+                    continue
+                smpq.smpq_set_tuning(c, *tune, band)
+                out32 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_MIXED_FP32)
+                assert np.abs(out32 - ref).max() <= 2e-6 * np.abs(ref).max(), (tune, band)
+    with pytest.raises(smpq.SmpqError):           # the band must divide nz
+        smpq.smpq_set_tuning(c, 2, 8, 1, 3)
+
+
+@pytest.mark.parametrize("dims,kind,band", [((16, 16, 2, 2), 1, 1), ((16, 16, 2, 2), 2, 2), ((24, 16, 2, 2), 2, 2)])
+def test_qx_plane_tiled_mixed(dims, kind, band):
     lat = Lattice(dims)
     U = si.near_identity_su3(dims, 0.3, 13)
     lo, hi = _zolo_interval(U, lat)
@@ -106,6 +137,7 @@ def test_qx_plane_tiled_mixed():
     col, ncls = colouring(lat, (2, 2, 2, 2), 0)
     ref = qx_probing(U, lat, KAPPA, zo, col, [5], TOL, 5000)
     c = _ctx(dims, U)
+    smpq.smpq_set_tuning(c, kind, 8, 1, band)
     smpq.smpq_set_scheme(c, (2, 2, 2, 2), 0)
     smpq.smpq_set_zolotarev(c, 14, lo, hi)
     smpq.smpq_set_solver(c, smpq.SMPQ_MIXED_FP32, TOL, 5000, 50)
