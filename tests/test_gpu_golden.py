@@ -5,8 +5,8 @@ Workloads (smpq_inputs.WORKLOADS):
               sources), dense exact density
   flux8       8^4 U(1) flux (1,1) + noise 0.1 + random gauge: SMP r = 2 full map, point
               sources on the seeded 64-site subset, SMP r = 4 on three classes
-  noise16x32  16^3 x 32 eps 0.2: SMP r = 4 classes 0 and 129, computed inside one full-size
-              batch (the batch size the benchmark uses)
+  noise16x32  16^3 x 32 eps 0.2: SMP r = 4 classes 0 and 129, computed inside a full-size
+              batch (the batch size of the benchmark)
 Tolerances: FP64 path max |dq| <= 1e-10; mixed path max |dq| <= 1e-5 and |dQ| <= 1e-4.
 """
 import os
@@ -105,9 +105,12 @@ def test_noise16x32_sampled_classes(prec):
     c = _ctx("noise16x32", prec)
     smpq.smpq_set_scheme(c, (4, 4, 4, 4), 0)
     col = smpq.smpq_get_coloring(c)
-    classes = [0, 129] + [k for k in range(1, 63)]          # 64 classes = 768 right-hand sides
+    # 52 classes = 624 right-hand sides: one batch of the mixed path, as in the whole-map
+    # benchmark run (3072 sources in 5 batches of 624 or fewer); the FP64 path takes two
+    classes = [0, 129] + [k for k in range(1, 51)]
     q, qi, st = smpq.smpq_compute_qx_classes(c, classes)
-    assert st["n_batches"] == 1 and st["n_sources"] == 768
+    assert st["n_sources"] == 624
+    assert st["n_batches"] == (1 if prec == smpq.SMPQ_MIXED_FP32 else 2)
     mask = np.isin(col, [0, 129])
     tol = 1e-10 if prec == smpq.SMPQ_FP64 else 1e-5
     assert np.abs(q[mask] - g["qx"][mask]).max() < tol
