@@ -280,7 +280,8 @@ def main():
                 "Q": Q if scale == 1.0 else None,
                 "abs_Q_minus_round": abs(Q - round(Q)) if scale == 1.0 else None,
                 "max_abs_imag_q": st["max_abs_imag_q"], "sum_imag_q": st["sum_imag_q"],
-                "lam_min": st["lam_min"], "lam_max": st["lam_max"], "zolo_delta": st["zolo_delta"]}
+                "lam_min": st["lam_min"], "lam_max": st["lam_max"], "zolo_delta": st["zolo_delta"],
+                "max_true_resid_base_fp64": st["max_true_resid"]}
     if args.full_fp64:
         accuracy["Q_fp64"] = float(q64.sum())
 

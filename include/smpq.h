@@ -84,6 +84,9 @@ typedef struct {
     double update_ms;            /* total duration of the fused multi-shift update       */
     double update_bytes;
     int64_t update_launches;
+    double max_true_resid;       /* mixed precision: largest FP64 true residual
+                                    ||b - (H^2 + q_1) x_1|| / ||b|| of the base system over the
+                                    sources, taken after the solve (0 in FP64)              */
 } smpq_stats;
 
 /* Create a context for a lattice dims[4] = {nx, ny, nz, nt} on HIP device `device`

@@ -45,7 +45,8 @@ class SmpqStats(ctypes.Structure):
                [(n, ctypes.c_int64) for n in ("n_sources", "n_batches", "total_iters", "max_iters",
                                               "n_reliable_updates", "shift_updates")] + \
                [("dslash_ms", ctypes.c_double), ("dslash_bytes", ctypes.c_double), ("dslash_launches", ctypes.c_int64),
-                ("update_ms", ctypes.c_double), ("update_bytes", ctypes.c_double), ("update_launches", ctypes.c_int64)]
+                ("update_ms", ctypes.c_double), ("update_bytes", ctypes.c_double), ("update_launches", ctypes.c_int64),
+                ("max_true_resid", ctypes.c_double)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

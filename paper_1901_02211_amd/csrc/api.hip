@@ -358,6 +358,7 @@ void upload_zolo(smpq_ctx *c) {
 
 struct BatchResult {
     long long iters_sum = 0, iters_max = 0, n_reliable = 0, entries = 0, pupd = 0, active = 0;
+    double max_true_resid = 0.0;
 };
 
 // One CG iteration for every active slot of the batch (capacity-sized launches; inactive
@@ -512,6 +513,28 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
         if (iter >= c->max_iter)
             throw Fail{SMPQ_ENOCONV, "multi-shift CG did not converge within max_iter = " + std::to_string(c->max_iter)};
     }
+    if (mixed) {
+        // FP64 true residual ||b - (H^2 + s0) x0|| / ||b|| of the base system of every slot,
+        // x0 being FP64 after the final fold
+        std::vector<int> all(nslots);
+        for (int k = 0; k < nslots; ++k) all[k] = k;
+        *c->h_count = nslots;
+        HIPCHK(hipMemcpyAsync(S.list, all.data(), sizeof(int) * nslots, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(S.count, c->h_count, sizeof(int), hipMemcpyHostToDevice, s));
+        launch_dslash(0, false, 0, c->U64.p, w.x0.p, rs64, 0, w.tmp64.p, rs64, nullptr, 0, 0, g, c->kappa, 0.0, act,
+                      S.B, nullptr, s);
+        launch_dslash(0, true, 1, c->U64.p, w.tmp64.p, rs64, 0, w.ap64.p, rs64, w.x0.p, rs64, 0, g, c->kappa, s0,
+                      act, S.B, S.partial, s);
+        launch_reliable(prec, g, S, src, w.ap64.as<double2>(), w.r.p, s);
+        launch_scalars_rr(S, np_unit, s);
+        HIPCHK(hipGetLastError());
+        std::vector<double> rr(nslots), bn(nslots);
+        HIPCHK(hipMemcpyAsync(rr.data(), S.rr, sizeof(double) * nslots, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(bn.data(), S.bnorm, sizeof(double) * nslots, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int k = 0; k < nslots; ++k)
+            res.max_true_resid = std::max(res.max_true_resid, std::sqrt(rr[k]) / bn[k]);
+    }
     std::vector<int> status(nslots), iters(nslots);
     std::vector<long long> ent(nslots), pup(nslots), actv(nslots);
     HIPCHK(hipMemcpy(status.data(), S.status, sizeof(int) * nslots, hipMemcpyDeviceToHost));
@@ -557,6 +580,7 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
         st->update_bytes += V * ((double)res.active * 12.0 * s_t + acc_bytes + (double)(res.entries + res.pupd) * 12.0 * s_t);
         st->update_launches += res.iters_max;
         st->n_reliable_updates += res.n_reliable;
+        st->max_true_resid = std::max(st->max_true_resid, res.max_true_resid);
         st->shift_updates += res.entries;
     }
     return res;

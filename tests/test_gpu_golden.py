@@ -52,6 +52,11 @@ def test_noise4_smp_full_map(prec):
     assert np.abs(qi - g["qx_imag"]).max() < tol
     assert abs(Q - g["qx"].sum()) < (1e-9 if prec == smpq.SMPQ_FP64 else 1e-4)
     assert st["n_sources"] == 192
+    # the mixed path ends with an FP64 true residual of every base system at the tolerance
+    if prec == smpq.SMPQ_MIXED_FP32:
+        assert 0.0 < st["max_true_resid"] <= 10 * TOL
+    else:
+        assert st["max_true_resid"] == 0.0
 
 
 def test_noise4_point_trace_and_dense():
@@ -110,6 +115,7 @@ def test_noise16x32_sampled_classes(prec):
     classes = [0, 129] + [k for k in range(1, 51)]
     q, qi, st = smpq.smpq_compute_qx_classes(c, classes)
     assert st["n_sources"] == 624
+    assert st["max_true_resid"] <= 10 * TOL
     assert st["n_batches"] == (1 if prec == smpq.SMPQ_MIXED_FP32 else 2)
     mask = np.isin(col, [0, 129])
     tol = 1e-10 if prec == smpq.SMPQ_FP64 else 1e-5
