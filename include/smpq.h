@@ -154,6 +154,12 @@ smpq_status smpq_set_batch(smpq_ctx *ctx, int max_rhs);
 smpq_status smpq_set_scheme(smpq_ctx *ctx, const int r[4], int mode, int *n_classes,
                             int *n_sources);
 
+/* Minimal Euclidean distance between two sites of one class of the current scheme (Eq. 18;
+ * minimum image on the torus) and the number of same-class sites at that distance from a
+ * site (section 3).  Every class of the three modes is a translate of one sublattice, so
+ * both are the same for all classes.  Host only.  0 and 0 when classes hold one site. */
+smpq_status smpq_get_scheme_rmin(const smpq_ctx *ctx, double *r_min, int *nearest);
+
 /* Point sources (section 2.1, Eq. 5): every site is its own class (V classes). */
 smpq_status smpq_set_point_scheme(smpq_ctx *ctx, int *n_classes, int *n_sources);
 

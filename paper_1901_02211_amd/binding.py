@@ -19,7 +19,7 @@ __all__ = [
     "smpq_create", "smpq_destroy", "smpq_strerror", "smpq_last_error", "smpq_load_gauge",
     "smpq_set_kappa", "smpq_lanczos", "smpq_estimate_bounds", "smpq_set_zolotarev",
     "smpq_get_zolotarev", "smpq_set_solver", "smpq_set_batch", "smpq_set_scheme",
-    "smpq_set_point_scheme", "smpq_get_coloring", "smpq_apply_dw", "smpq_apply_dov",
+    "smpq_set_point_scheme", "smpq_get_coloring", "smpq_get_scheme_rmin", "smpq_apply_dw", "smpq_apply_dov",
     "smpq_compute_qx", "smpq_compute_qx_classes", "smpq_compute_qx_points", "smpq_prepare", "smpq_set_stream",
     "smpq_set_timing", "smpq_set_graphs", "smpq_bench_dslash", "smpq_autotune",
     "smpq_set_tuning", "smpq_get_tuning", "smpq_set_memory_limit", "smpq_compute_qx_multi",
@@ -68,6 +68,7 @@ _SIG = {
     "smpq_set_scheme": (ctypes.c_int, [_vp, _c_int_p, ctypes.c_int, _c_int_p, _c_int_p]),
     "smpq_set_point_scheme": (ctypes.c_int, [_vp, _c_int_p, _c_int_p]),
     "smpq_get_coloring": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32)]),
+    "smpq_get_scheme_rmin": (ctypes.c_int, [_vp, _c_double_p, _c_int_p]),
     "smpq_apply_dw": (ctypes.c_int, [_vp, _c_double_p, _c_double_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "smpq_apply_dov": (ctypes.c_int, [_vp, _c_double_p, _c_double_p, ctypes.c_int]),
     "smpq_compute_qx": (ctypes.c_int, [_vp, _c_double_p, _c_double_p, _c_double_p, ctypes.POINTER(SmpqStats)]),
@@ -217,6 +218,13 @@ def smpq_get_coloring(ctx):
     out = np.zeros(ctx.volume, dtype=np.int32)
     _check(ctx, _lib.smpq_get_coloring(ctx.ptr, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
     return out
+
+
+def smpq_get_scheme_rmin(ctx):
+    """(r_min, number of same-class sites at r_min) of the current scheme."""
+    r, n = ctypes.c_double(), ctypes.c_int()
+    _check(ctx, _lib.smpq_get_scheme_rmin(ctx.ptr, ctypes.byref(r), ctypes.byref(n)))
+    return r.value, n.value
 
 
 def _spinors(ctx, psi):

@@ -1084,6 +1084,36 @@ smpq_status smpq_get_coloring(const smpq_ctx *cc, int32_t *colour) {
     });
 }
 
+smpq_status smpq_get_scheme_rmin(const smpq_ctx *cc, double *r_min, int *nearest) {
+    smpq_ctx *c = const_cast<smpq_ctx *>(cc);
+    return guarded(c, [&] {
+        if (!c->have_scheme) throw Fail{SMPQ_ESTATE, "no scheme set"};
+        // every class of the three modes is a coset of one sublattice, so the distances
+        // from site 0 to the other sites of its class are those of any class
+        long long best = -1;
+        int cnt = 0;
+        for (int s = 1; s < c->V; ++s) {
+            if (c->colour[s] != c->colour[0]) continue;
+            long long d2 = 0;
+            int t = s;
+            for (int mu = 0; mu < 4; ++mu) {
+                const int x = t % c->dims[mu];
+                t /= c->dims[mu];
+                const int d = std::min(x, c->dims[mu] - x);
+                d2 += (long long)d * d;
+            }
+            if (best < 0 || d2 < best) {
+                best = d2;
+                cnt = 1;
+            } else if (d2 == best) {
+                ++cnt;
+            }
+        }
+        if (r_min) *r_min = best < 0 ? 0.0 : std::sqrt((double)best);
+        if (nearest) *nearest = best < 0 ? 0 : cnt;
+    });
+}
+
 smpq_status smpq_apply_dw(smpq_ctx *c, const double *in, double *out, int n, int dagger, smpq_precision prec) {
     return guarded(c, [&] {
         if (!in || !out || n < 1) throw Fail{SMPQ_EINVAL, "need input, output and n_rhs >= 1"};

@@ -139,6 +139,8 @@ def random_spinors(dims, n: int, seed: int) -> np.ndarray:
 WORKLOADS = {
     # 4^4, near-identity noise eps=0.3, seed 0; SMP r=2 plus a full point-source trace.
     "noise4": dict(dims=(4, 4, 4, 4), kind="noise", eps=0.3, seed=0, r=2),
+    # 8^4, near-identity noise eps=0.3, seed 10 (scheme scans; Haar gauge transform seed 11 on request)
+    "noise8": dict(dims=(8, 8, 8, 8), kind="noise", eps=0.3, seed=10, r=(2, 4)),
     # 8^4, U(1) flux (1,1) (Q = 2), noise eps=0.1 seed 1, Haar gauge transform seed 2;
     # SMP r in {2, 4}; point sources on 64 sites drawn with seed 3.
     "flux8": dict(dims=(8, 8, 8, 8), kind="flux", flux=(1, 1), eps=0.1, seed=1, gauge_seed=2,
@@ -154,16 +156,20 @@ WORKLOADS = {
 }
 
 
-def workload(name: str) -> np.ndarray:
-    """Build the gauge field of a named workload (deterministic)."""
+def workload(name: str, gauge=True, gauge_seed=None) -> np.ndarray:
+    """Build the gauge field of a named workload (deterministic).  gauge=False leaves out the
+    workload's random gauge transform; gauge_seed applies a Haar transform with that seed
+    (in place of the workload's own, if it has one)."""
     w = WORKLOADS[name]
     dims = w["dims"]
     if w["kind"] == "noise":
-        return near_identity_su3(dims, w["eps"], w["seed"])
-    U = u1_flux(dims, *w["flux"])
-    U = left_multiply(near_identity_su3(dims, w["eps"], w["seed"]), U)
-    if "gauge_seed" in w:
-        U = gauge_transform(U, dims, haar_su3(volume(dims), w["gauge_seed"]))
+        U = near_identity_su3(dims, w["eps"], w["seed"])
+    else:
+        U = u1_flux(dims, *w["flux"])
+        U = left_multiply(near_identity_su3(dims, w["eps"], w["seed"]), U)
+    seed = gauge_seed if gauge_seed is not None else w.get("gauge_seed")
+    if gauge and seed is not None:
+        U = gauge_transform(U, dims, haar_su3(volume(dims), seed))
     return U
 
 

@@ -45,6 +45,22 @@ def test_table2_counts_from_library(row):
     assert smpq.smpq_set_scheme(c, r, mode)[1] == nsmp
 
 
+@pytest.mark.parametrize("row", [r for r in load_table("table1_rmin.txt") if r[0] <= 16])
+def test_table1_rmin_from_library(row):
+    """The library's r_min of each scheme equals the paper's Table 1; the number of nearest
+    same-class sites is 8 in normal mode and 24 in the split and combine modes (section 3),
+    4 when a class has two sites per direction (m = 2: +r and -r are one image)."""
+    n, m, mode, a, b = row
+    c = smpq.smpq_create((n,) * 4, -1)
+    smpq.smpq_set_scheme(c, gaps_from_m((n,) * 4, (m,) * 4), mode)
+    rmin, nearest = smpq.smpq_get_scheme_rmin(c)
+    assert abs(rmin - a * np.sqrt(b)) < 1e-12
+    if m == 2 and mode == 0:
+        assert nearest == 4
+    else:
+        assert nearest == (8 if mode == 0 else 24)
+
+
 ZOLO_CASES = [(14, 0.13, 2.62), (14, 0.05, 2.7), (14, 0.15, 2.7), (6, 0.3, 1.0), (20, 0.02, 3.0)] + \
     [(n, lo, 2.7) for n in (4, 14, 24) for lo in np.linspace(0.01, 1.5, 23)]
 

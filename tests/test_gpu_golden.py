@@ -193,3 +193,19 @@ def test_noise32x64_dov_sampled_sites():
     sites = g["sites"]
     assert np.abs(out[sites] - g["dov"]).max() < 1e-10 * np.abs(g["dov"]).max()
     assert w["dims"] == (32, 32, 32, 64)
+
+
+def test_scheme_scan_special_cases():
+    """The scan on 4^4: its exact density is the stored point-source trace, the r = 4 = n row
+    (one site per class) equals it, and the r = 2 normal-mode row is the stored SMP map."""
+    from paper_1901_02211_amd.scan import scan
+    print("scheme scan on noise4", flush=True)
+    res = scan(si.workload("noise4"), (4, 4, 4, 4), gaps=(2, 4), precision=smpq.SMPQ_FP64)
+    assert res["n_point_sources"] == 3072
+    assert abs(res["Q_exact"] - _golden("noise4_point")["qx"].sum()) < 1e-9
+    rows = {(w["r"], w["mode"]): w for w in res["rows"]}
+    assert set(rows) == {(2, 0), (2, 1), (2, 2), (4, 0), (4, 2)}     # (4, 1): m = 1 is odd
+    assert rows[(4, 0)]["max_abs_dq"] < 1e-13 and rows[(4, 0)]["n_sources"] == 3072
+    assert abs(rows[(2, 0)]["Q"] - _golden("noise4_smp")["qx"].sum()) < 1e-9
+    assert (rows[(2, 0)]["r_min"], rows[(2, 0)]["nearest"]) == (2.0, 4)
+    assert [w["n_sources"] for w in res["rows"]] == sorted(w["n_sources"] for w in res["rows"])
