@@ -17,6 +17,7 @@ with symmetric multi-probing method", arXiv:1901.02211):
   mscg      multi-shift CG for (D_W^dag D_W + q_i) x_i = b          (section 2.1, Eqs. 6-8)
   probing   symmetric multi-probing colourings, modes 0/1/2       (section 2.2, Eqs. 15-19)
   charge    q(x) from point sources, SMP sources and dense eps    (Eqs. 5, 16)
+  trinv     probing estimate of Tr D_W^-1, the proposed application (Conclusion)
 
 Every function names the passage it follows.  No function here is "parity
 unpinned": each is checked in tests/test_oracle_*.py against closed forms,

@@ -1,8 +1,13 @@
 import os
 import sys
 
-import numpy as np
-import pytest
+# dense oracle checks (inverses, eigendecompositions of a few thousand rows) run faster on a
+# few BLAS threads than on every core when other work shares the machine
+for _v in ("OPENBLAS_NUM_THREADS", "OMP_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ.setdefault(_v, "4")
+
+import numpy as np  # noqa: E402
+import pytest  # noqa: E402
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
