@@ -189,6 +189,19 @@ smpq_status smpq_compute_qx(smpq_ctx *ctx, double *qx, double *qx_imag, double *
 smpq_status smpq_compute_qx_classes(smpq_ctx *ctx, const int32_t *classes, int n_classes,
                                     double *qx, double *qx_imag, smpq_stats *st);
 
+/* Probing estimate of the trace of D_W^-1, the application the Conclusion proposes for the
+ * same probing vectors (Eqs. 15-16): for x in the listed classes of the current scheme,
+ *   t(x) = sum_{alpha,a} [D_W^-1 phi_{c,alpha,a}](x, alpha, a)
+ *        = tr_sc D_W^-1(x, x) + sum_{y in S_c, y != x} sum_j D_W^-1(x j; y j),
+ * exact with the point scheme (then sum_x t(x) = Tr D_W^-1, and t(x) is real).  Each source
+ * is one CG solve of D_W^dag D_W y = phi (multi-shift machinery with the single shift 0, the
+ * context's precision, tolerance and reliable updates), and D_W^-1 phi = g gamma5 D_W y with
+ * g = gamma5 of the source's spin.  Needs no Zolotarev coefficients.
+ *   classes   NULL: every class; else n distinct class indices
+ *   t_re      V doubles, Re t(x) (0 outside the listed classes); t_im NULL or V doubles */
+smpq_status smpq_compute_trinv(smpq_ctx *ctx, const int32_t *classes, int n, double *t_re, double *t_im,
+                               smpq_stats *st);
+
 /* Exact point-source density (Eq. 5) on n listed sites: qx[i] = q(sites[i]).  Does not
  * change the scheme set with smpq_set_scheme. */
 smpq_status smpq_compute_qx_points(smpq_ctx *ctx, const int64_t *sites, int n, double *qx,

@@ -129,6 +129,17 @@ struct smpq_ctx {
     bool have_zolo = false;
     Zolo zolo;
     DevMem zc, zdelta;   // device copies of c_i and q_i - q_min
+    // coefficients of the current multi-shift solve: the Zolotarev set, or the single
+    // unshifted system of D_W^dag D_W (c0 = 0, c = 1, q = 0) for the trace of D_W^-1
+    struct Coef {
+        int n = 0;
+        double c0 = 0.0, s0 = 0.0;
+        const double *c = nullptr, *delta = nullptr;
+    };
+    Coef coef_eps, coef_inv;
+    const Coef *coef = &coef_eps;
+    const Coef *graph_coef = nullptr;   // the set the captured graphs were built with
+    DevMem inv_cd;                      // {1, 0}: c and delta of the unshifted system
     smpq_precision prec = SMPQ_FP64;
     double tol = 1e-12;
     int max_iter = 10000;
@@ -354,6 +365,18 @@ void upload_zolo(smpq_ctx *c) {
     c->zdelta.ensure(sizeof(double) * n);
     HIPCHK(hipMemcpy(c->zc.p, c->zolo.c.data(), sizeof(double) * n, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->zdelta.p, dl.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    c->coef_eps = smpq_ctx::Coef{n, c->zolo.c0, c->zolo.q[0], c->zc.as<double>(), c->zdelta.as<double>()};
+}
+
+// Select the coefficient set of the next solves (Zolotarev or the unshifted inverse).
+void use_coef(smpq_ctx *c, bool inverse) {
+    if (inverse && !c->inv_cd.p) {
+        const double cd[2] = {1.0, 0.0};
+        c->inv_cd.ensure(sizeof(cd));
+        HIPCHK(hipMemcpy(c->inv_cd.p, cd, sizeof(cd), hipMemcpyHostToDevice));
+        c->coef_inv = smpq_ctx::Coef{1, 0.0, 0.0, c->inv_cd.as<double>(), c->inv_cd.as<double>() + 1};
+    }
+    c->coef = inverse ? &c->coef_inv : &c->coef_eps;
 }
 
 struct BatchResult {
@@ -383,7 +406,7 @@ void enqueue_iteration(smpq_ctx *c, int prec, const MSState &S, bool y64, bool x
         tm->dslash.record(s, captured);
     }
     launch_dslash(prec, true, 1, U, w.tmp.p, rs, 0, w.ap.p, rs, w.p.p, NS * rs, S.i0 * rs, g, c->kappa,
-                  c->zolo.q[0], act, B, S.partial, s);
+                  c->coef->s0, act, B, S.partial, s);
     if (tm) tm->dslash.record(s, captured);
     launch_scalars_alpha(S, np_ds, s);
     launch_r_update(prec, g, S, w.r.p, w.ap.p, s);
@@ -428,6 +451,10 @@ GroupTimers *launch_group(smpq_ctx *c, int prec, const MSState &S, int it0) {
         enqueue_group(c, prec, S, it0, tm, false);
         return tm;
     }
+    if (c->graph_coef != c->coef) {   // the graphs hold the coefficients of the other set
+        c->gen++;
+        c->graph_coef = c->coef;
+    }
     const int t = timed ? 1 : 0;
     GroupTimers *tm = timed ? &c->graph_timers[v] : nullptr;
     if (!c->graphs[t][v] || c->graph_gen[t][v] != c->gen) {
@@ -464,18 +491,18 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
     S.B = w.B;           // launches are sized for the workspace capacity; slots >= nslots start done
     S.i0 = 0;            // q ascending: the smallest shift is the base system
     S.tol = c->tol;
-    S.c = c->zc.as<double>();
-    S.delta = c->zdelta.as<double>();
+    S.c = c->coef->c;
+    S.delta = c->coef->delta;
     const int NS = S.NS;
     const Geom g = c->geom();
     hipStream_t s = c->stream;
-    const double s0 = c->zolo.q[0];
+    const double s0 = c->coef->s0;
     const size_t rs64 = 12 * c->vs;
     const int np_unit = unit_parts(prec, g);
     const Slots act{S.list, S.count, 0};
     const bool mixed = prec == 1;
 
-    launch_cg_init(prec, g, src, nslots, NS, c->zolo.c0, w.r.p, w.p.p, w.y.as<double2>(), mixed ? w.yacc.p : nullptr,
+    launch_cg_init(prec, g, src, nslots, NS, c->coef->c0, w.r.p, w.p.p, w.y.as<double2>(), mixed ? w.yacc.p : nullptr,
                    mixed ? w.x0.as<double2>() : nullptr, mixed ? w.x0acc.p : nullptr, S.partial, s);
     launch_scalars_init(S, np_unit, nslots, s);
     launch_compact(S, s);
@@ -679,9 +706,10 @@ void auto_zolo(smpq_ctx *c, smpq_stats *st) {
 
 // q(x) for the listed classes of a colouring (scheme or point), written into the
 // device arrays qx/qxi (which the caller zeroes).
-void qx_classes(smpq_ctx *c, const std::vector<int> &classes, bool point, smpq_stats *st) {
+void qx_classes(smpq_ctx *c, const std::vector<int> &classes, bool point, smpq_stats *st, bool inverse = false) {
     const int prec = c->prec == SMPQ_FP64 ? 0 : 1;
-    const int NS = c->zolo.n;
+    use_coef(c, inverse);
+    const int NS = c->coef->n;
     const int total = (int)classes.size() * 12;
     if (total == 0) return;
     const int B = choose_batch(c, prec, NS, total, true);
@@ -712,7 +740,7 @@ void qx_classes(smpq_ctx *c, const std::vector<int> &classes, bool point, smpq_s
         BatchResult r = run_batch(c, prec, 12 * nc, src, st);
         const double t1 = now_s();
         launch_contract(c->geom(), c->U64.as<double2>(), w.y.as<double2>(), c->kappa, w.batch_classes.as<int>(), nc,
-                        maxsize, cptr, csites, c->qx.as<double>(), c->qxi.as<double>(), c->stream);
+                        maxsize, cptr, csites, c->qx.as<double>(), c->qxi.as<double>(), inverse, c->stream);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(c->stream));
         if (st) {
@@ -1153,6 +1181,7 @@ smpq_status smpq_apply_dov(smpq_ctx *c, const double *in, double *out, int n) {
         need_device(c);
         require_gauge_zolo(c);
         const int prec = c->prec == SMPQ_FP64 ? 0 : 1;
+        use_coef(c, false);
         const int NS = c->zolo.n;
         const Geom g = c->geom();
         const size_t v64 = 12 * 16 * c->vs;
@@ -1354,6 +1383,24 @@ smpq_status smpq_compute_qx_multi(smpq_ctx *const *ctxs, int n_ctx, const int32_
             return res[k];
         }
     return SMPQ_OK;
+}
+
+smpq_status smpq_compute_trinv(smpq_ctx *c, const int32_t *classes, int n, double *t_re, double *t_im,
+                               smpq_stats *st) {
+    return guarded(c, [&] {
+        if (!t_re) throw Fail{SMPQ_EINVAL, "null output"};
+        const std::vector<int> cls = class_list(c, classes, classes ? n : -1);
+        if (st) std::memset(st, 0, sizeof(*st));
+        need_device(c);
+        if (!c->have_gauge) throw Fail{SMPQ_ESTATE, "no gauge field loaded"};
+        c->qx.ensure(sizeof(double) * c->V);
+        c->qxi.ensure(sizeof(double) * c->V);
+        HIPCHK(hipMemsetAsync(c->qx.p, 0, sizeof(double) * c->V, c->stream));
+        HIPCHK(hipMemsetAsync(c->qxi.p, 0, sizeof(double) * c->V, c->stream));
+        ensure_scheme_device(c);
+        qx_classes(c, cls, false, st, true);
+        finish_q(c, t_re, t_im, st);
+    });
 }
 
 smpq_status smpq_compute_qx_points(smpq_ctx *c, const int64_t *sites, int n, double *qx, smpq_stats *st) {

@@ -100,9 +100,10 @@ void launch_reliable(int prec, const Geom &g, const MSState &s, const Source &sr
 void launch_scalars_rr(const MSState &s, int npart, hipStream_t st);
 
 // q(x) contraction (Eq. 16) for the classes of one batch; slot = 12*class_pos + comp.
+// inverse: the trace density of D_W^-1 from y = (D_W^dag D_W)^-1 phi instead.
 void launch_contract(const Geom &g, const double2 *U64, const double2 *y, double kappa, const int *batch_classes,
                      int n_classes, int max_class_size, const int *class_ptr, const int *class_sites, double *qx,
-                     double *qxi, hipStream_t st);
+                     double *qxi, bool inverse, hipStream_t st);
 
 // Lanczos helpers (single FP64 vector); the update writes unit_parts(0, g) partials
 void launch_lanczos_update(const Geom &g, double2 *w, const double2 *v, const double2 *vprev, double alpha,

@@ -10,7 +10,8 @@
 //                  update, fused update of every active shift's search direction plus the
 //                  running rational sum y = c_0 b + sum_i c_i x_i, scalar recurrences on the
 //                  device (one wave per right-hand side), FP64 residual replacement.
-//  k_contract      q(x) += 1/2 [gamma5 D_ov phi](x, alpha, a) on the probed sites (Eq. 16).
+//  k_contract      q(x) += 1/2 [gamma5 D_ov phi](x, alpha, a) on the probed sites (Eq. 16), or
+//                  the probing estimate of tr D_W^-1 (x, x) from the unshifted solve.
 //
 // Reductions are two-pass and fixed-order (per-block partials, then one wave per
 // right-hand side), so every FP64 result is bitwise reproducible from run to run.
@@ -1136,6 +1137,11 @@ void launch_scalars_rr(const MSState &s, int npart, hipStream_t st) {
 // For each probed site x of class position ci and each component j (slot 12 ci + j):
 //   q(x)  += 1/2 gamma5_jj (1 + Re[D_W y_slot](x, j)),   qi(x) += 1/2 gamma5_jj Im[D_W y_slot](x, j),
 // since gamma5 D_ov phi = gamma5 (phi + D_W y) with eps phi = gamma5 D_W y.
+// INV (trace of D_W^-1): y_slot = (D_W^dag D_W)^-1 phi and D_W^-1 phi = g_j gamma5 D_W y_slot
+// (from D_W^-1 = D_W^dag (D_W D_W^dag)^-1, D_W D_W^dag = gamma5 D_W^dag D_W gamma5 and
+// gamma5 phi = g_j phi), so component j of D_W^-1 phi at x is [D_W y_slot](x, j):
+//   t(x) += [D_W y_slot](x, j)  (real part into qx, imaginary part into qxi).
+template <bool INV>
 __global__ __launch_bounds__(kBlock) void k_contract(Geom g, const double2 *U64, const double2 *y, double kappa,
                                                      const int *batch_classes, const int *class_ptr,
                                                      const int *class_sites, double *qx, double *qxi) {
@@ -1154,9 +1160,14 @@ __global__ __launch_bounds__(kBlock) void k_contract(Geom g, const double2 *U64,
         const cpx<double> self = ld64(yv, g.vs, j, x);
         const double dre = self.re - kappa * acc[j].re;
         const double dim = self.im - kappa * acc[j].im;
-        const double g5 = (j < 6) ? 0.5 : -0.5;
-        q += g5 * (1.0 + dre);
-        qi += g5 * dim;
+        if constexpr (INV) {
+            q += dre;
+            qi += dim;
+        } else {
+            const double g5 = (j < 6) ? 0.5 : -0.5;
+            q += g5 * (1.0 + dre);
+            qi += g5 * dim;
+        }
     }
     qx[x] = q;
     qxi[x] = qi;
@@ -1164,10 +1175,14 @@ __global__ __launch_bounds__(kBlock) void k_contract(Geom g, const double2 *U64,
 
 void launch_contract(const Geom &g, const double2 *U64, const double2 *y, double kappa, const int *batch_classes,
                      int n_classes, int max_class_size, const int *class_ptr, const int *class_sites, double *qx,
-                     double *qxi, hipStream_t st) {
+                     double *qxi, bool inverse, hipStream_t st) {
     dim3 grid((max_class_size + kBlock - 1) / kBlock, n_classes);
-    hipLaunchKernelGGL(k_contract, grid, dim3(kBlock), 0, st, g, U64, y, kappa, batch_classes, class_ptr,
-                       class_sites, qx, qxi);
+    if (inverse)
+        hipLaunchKernelGGL(k_contract<true>, grid, dim3(kBlock), 0, st, g, U64, y, kappa, batch_classes, class_ptr,
+                           class_sites, qx, qxi);
+    else
+        hipLaunchKernelGGL(k_contract<false>, grid, dim3(kBlock), 0, st, g, U64, y, kappa, batch_classes, class_ptr,
+                           class_sites, qx, qxi);
 }
 
 // ------------------------------------------------------------------ Lanczos helpers (FP64, one vector)
