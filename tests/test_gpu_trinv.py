@@ -101,3 +101,16 @@ def test_trinv_then_qx_on_one_context():
     t2, _ = smpq.smpq_compute_trinv(c, [0, 3])
     assert np.array_equal(q1, q2) and np.array_equal(t1, t2)
     assert np.abs(t1).max() > 1.0 and np.abs(q1).max() > 0.0
+
+
+def test_trinv_scan_point_row_is_exact():
+    """The scan of the trace of D_W^-1 on 4^4: the exact trace is the dense one, and the
+    single-site scheme r = 4 reproduces it."""
+    from paper_1901_02211_amd.scan import scan
+    dims = (4, 4, 4, 4)
+    print("trinv scheme scan on noise4", flush=True)
+    U = si.workload("noise4")
+    res = scan(U, dims, gaps=(2, 4), precision=smpq.SMPQ_FP64, quantity="trinv")
+    assert abs(res["Q_exact"] - trinv_dense(U, Lattice(dims), KAPPA).sum().real) < 1e-8
+    rows = {(w["r"], w["mode"]): w for w in res["rows"]}
+    assert rows[(4, 0)]["max_abs_dq"] < 1e-13
