@@ -202,6 +202,14 @@ smpq_status smpq_compute_qx_classes(smpq_ctx *ctx, const int32_t *classes, int n
 smpq_status smpq_compute_trinv(smpq_ctx *ctx, const int32_t *classes, int n, double *t_re, double *t_im,
                                smpq_stats *st);
 
+/* Locality of the overlap operator (section 2.2, Eq. 12 and Fig. 1): the twelve columns
+ * D_ov e_{site,beta,b} of the point source at `site` (one batch of 12 solves with the current
+ * coefficients and precision), reduced at every x to
+ *   mean_abs[x] = (1/144) sum_{alpha,a,beta,b} |D_ov(x alpha a; site beta b)|   (V doubles).
+ * Averaging over the sites at one distance and fitting the logarithm gives the decay rate
+ * gamma of Eq. 12. */
+smpq_status smpq_dov_locality(smpq_ctx *ctx, int64_t site, double *mean_abs, smpq_stats *st);
+
 /* Exact point-source density (Eq. 5) on n listed sites: qx[i] = q(sites[i]).  Does not
  * change the scheme set with smpq_set_scheme. */
 smpq_status smpq_compute_qx_points(smpq_ctx *ctx, const int64_t *sites, int n, double *qx,

@@ -1403,6 +1403,46 @@ smpq_status smpq_compute_trinv(smpq_ctx *c, const int32_t *classes, int n, doubl
     });
 }
 
+smpq_status smpq_dov_locality(smpq_ctx *c, int64_t site, double *mean_abs, smpq_stats *st) {
+    return guarded(c, [&] {
+        if (!mean_abs) throw Fail{SMPQ_EINVAL, "null output"};
+        if (site < 0 || site >= c->V) throw Fail{SMPQ_EINVAL, "site index out of range"};
+        if (st) std::memset(st, 0, sizeof(*st));
+        need_device(c);
+        require_gauge_zolo(c);
+        const int prec = c->prec == SMPQ_FP64 ? 0 : 1;
+        use_coef(c, false);
+        ensure_point_device(c);
+        ensure_workspace(c, prec, c->zolo.n, std::max(12, c->ws.prec == prec && c->ws.NS == c->zolo.n ? c->ws.B : 12));
+        Workspace &w = c->ws;
+        std::vector<int> sc(12, (int)site), sp(12);
+        for (int j = 0; j < 12; ++j) sp[j] = j;
+        HIPCHK(hipMemcpyAsync(w.slot_class.p, sc.data(), sizeof(int) * 12, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(w.slot_comp.p, sp.data(), sizeof(int) * 12, hipMemcpyHostToDevice, c->stream));
+        Source src{c->d_pcolour.as<int>(), w.slot_class.as<int>(), w.slot_comp.as<int>(), nullptr};
+        const double t0 = now_s();
+        BatchResult r = run_batch(c, prec, 12, src, st);
+        // columns of D_ov: e_j + D_W y_j (gamma5 eps e_j = D_W y_j)
+        const Geom g = c->geom();
+        DevMem d, m;
+        d.ensure((size_t)12 * 12 * 16 * c->vs);
+        m.ensure(sizeof(double) * c->V);
+        launch_dslash(0, false, 0, c->U64.p, w.y.p, 12 * c->vs, 0, d.p, 12 * c->vs, nullptr, 0, 0, g, c->kappa, 0.0,
+                      Slots{nullptr, nullptr, 12}, 12, nullptr, c->stream);
+        launch_block_mean_abs(g, d.as<double2>(), (int)site, m.as<double>(), c->stream);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(mean_abs, m.p, sizeof(double) * c->V, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (st) {
+            st->t_solve_s = now_s() - t0;
+            st->n_sources = 12;
+            st->n_batches = 1;
+            st->total_iters = r.iters_sum;
+            st->max_iters = r.iters_max;
+        }
+    });
+}
+
 smpq_status smpq_compute_qx_points(smpq_ctx *c, const int64_t *sites, int n, double *qx, smpq_stats *st) {
     return guarded(c, [&] {
         if ((!sites && n > 0) || !qx || n < 0) throw Fail{SMPQ_EINVAL, "bad site list or output"};

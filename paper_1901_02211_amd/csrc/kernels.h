@@ -99,6 +99,10 @@ void launch_reliable(int prec, const Geom &g, const MSState &s, const Source &sr
                      void *r, hipStream_t st);
 void launch_scalars_rr(const MSState &s, int npart, hipStream_t st);
 
+// m(x) = mean |D_ov(x i; site j)| over the 144 entries, from d_j = D_W y_j of the twelve
+// point-source columns of `site` (Eq. 12).
+void launch_block_mean_abs(const Geom &g, const double2 *d, int site, double *m, hipStream_t st);
+
 // q(x) contraction (Eq. 16) for the classes of one batch; slot = 12*class_pos + comp.
 // inverse: the trace density of D_W^-1 from y = (D_W^dag D_W)^-1 phi instead.
 void launch_contract(const Geom &g, const double2 *U64, const double2 *y, double kappa, const int *batch_classes,

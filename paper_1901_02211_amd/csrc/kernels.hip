@@ -1185,6 +1185,30 @@ void launch_contract(const Geom &g, const double2 *U64, const double2 *y, double
                            class_sites, qx, qxi);
 }
 
+// ------------------------------------------------------------------ locality of D_ov (Eq. 12)
+// d holds D_W y_j for the twelve point-source columns j of site `site` (slot stride 12 vs);
+// column j of D_ov is e_{site,j} + d_j.  m(x) = (1/144) sum_{i,j} |D_ov(x i; site j)|.
+__global__ __launch_bounds__(kBlock) void k_block_mean_abs(Geom g, const double2 *d, int site, double *m) {
+    const int x = blockIdx.x * kBlock + threadIdx.x;
+    if (x >= g.V) return;
+    double acc = 0.0;
+#pragma unroll 1
+    for (int j = 0; j < 12; ++j) {
+        const double2 *col = d + (size_t)j * 12 * g.vs;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            cpx<double> v = ld64(col, g.vs, i, x);
+            if (x == site && i == j) v.re += 1.0;
+            acc += sqrt(v.re * v.re + v.im * v.im);
+        }
+    }
+    m[x] = acc / 144.0;
+}
+
+void launch_block_mean_abs(const Geom &g, const double2 *d, int site, double *m, hipStream_t st) {
+    hipLaunchKernelGGL(k_block_mean_abs, dim3((g.V + kBlock - 1) / kBlock), dim3(kBlock), 0, st, g, d, site, m);
+}
+
 // ------------------------------------------------------------------ Lanczos helpers (FP64, one vector)
 __global__ __launch_bounds__(kBlock) void k_lanczos_update(Geom g, double2 *w, const double2 *v, const double2 *vprev,
                                                            double alpha, double beta, double *partial) {

@@ -313,3 +313,25 @@ def test_graphs_match_eager_and_timed(prec):
     smpq.smpq_set_batch(c, 12)
     q2 = smpq.smpq_compute_qx_classes(c, [1, 6, 9])[0]
     assert np.abs(q2 - out[0]).max() < (1e-13 if prec == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("prec", [smpq.SMPQ_FP64, smpq.SMPQ_MIXED_FP32])
+def test_dov_locality_matches_oracle(prec):
+    """Mean absolute block entries of D_ov around one site (Eq. 12) against the oracle's twelve
+    point-source columns; FP64 1e-10, mixed 2e-6 (entries are at most ~1)."""
+    from oracle.locality import block_mean_abs
+    dims = (4, 4, 4, 4)
+    print(f"D_ov locality on noise4, precision {prec}", flush=True)
+    lat = Lattice(dims)
+    U = si.workload("noise4")
+    lo, hi = 0.13, 2.62
+    zo = zolotarev(14, lo, hi)
+    site = 37
+    ref = block_mean_abs(U, lat, KAPPA, zo[:3], site, TOL, 5000)
+    c = _ctx(dims, U)
+    smpq.smpq_set_zolotarev(c, 14, lo, hi)
+    smpq.smpq_set_solver(c, prec, TOL, 5000, 50 if prec == smpq.SMPQ_MIXED_FP32 else 0)
+    m, st = smpq.smpq_dov_locality(c, site)
+    assert st["n_sources"] == 12
+    assert np.abs(m - ref).max() < (1e-10 if prec == smpq.SMPQ_FP64 else 2e-6)
+    assert m[site] == m.max()
