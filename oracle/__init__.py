@@ -18,6 +18,8 @@ with symmetric multi-probing method", arXiv:1901.02211):
   probing   symmetric multi-probing colourings, modes 0/1/2       (section 2.2, Eqs. 15-19)
   charge    q(x) from point sources, SMP sources and dense eps    (Eqs. 5, 16)
   trinv     probing estimate of Tr D_W^-1, the proposed application (Conclusion)
+  locality  mean block entries of D_ov against distance            (Eq. 12, Fig. 1)
+  deflation exact sign on the lowest modes of H_W^2, Zolotarev on the rest
 
 Every function names the passage it follows.  No function here is "parity
 unpinned": each is checked in tests/test_oracle_*.py against closed forms,

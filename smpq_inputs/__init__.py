@@ -113,6 +113,22 @@ def haar_su3(n: int, seed: int) -> np.ndarray:
     return Q / (det ** (1.0 / 3.0))[..., None, None]
 
 
+def rough_block(dims, eps: float, seed: int, block: int) -> np.ndarray:
+    """Near-identity links (eps, seed) with the links of the sites whose four coordinates are
+    all < block replaced by Haar-random SU(3) (seed + 100): a smooth field with one rough
+    spot, which pulls a few eigenvalues of H_W below the rest of its spectrum."""
+    U = near_identity_su3(dims, eps, seed)
+    V = volume(dims)
+    H = haar_su3(4 * V, seed + 100).reshape(V, 4, 3, 3)
+    idx = np.arange(V)
+    inside = np.ones(V, dtype=bool)
+    for n in dims:
+        inside &= (idx % n) < block
+        idx = idx // n
+    U[inside] = H[inside]
+    return U
+
+
 def left_multiply(N: np.ndarray, U: np.ndarray) -> np.ndarray:
     """U_mu(x) <- N_mu(x) U_mu(x) (noise applied on the left)."""
     return N @ U
@@ -139,6 +155,9 @@ def random_spinors(dims, n: int, seed: int) -> np.ndarray:
 WORKLOADS = {
     # 4^4, near-identity noise eps=0.3, seed 0; SMP r=2 plus a full point-source trace.
     "noise4": dict(dims=(4, 4, 4, 4), kind="noise", eps=0.3, seed=0, r=2),
+    # 4^4 and 8^4 near-identity (eps 0.3) with a Haar-random 2^4 / 3^4 block: isolated low modes
+    "rough4": dict(dims=(4, 4, 4, 4), kind="rough", eps=0.3, seed=50, block=2, r=2),
+    "rough8": dict(dims=(8, 8, 8, 8), kind="rough", eps=0.3, seed=60, block=3, r=(2, 4)),
     # 8^4, near-identity noise eps=0.3, seed 10 (scheme scans; Haar gauge transform seed 11 on request)
     "noise8": dict(dims=(8, 8, 8, 8), kind="noise", eps=0.3, seed=10, r=(2, 4)),
     # 8^4, U(1) flux (1,1) (Q = 2), noise eps=0.1 seed 1, Haar gauge transform seed 2;
@@ -164,6 +183,8 @@ def workload(name: str, gauge=True, gauge_seed=None) -> np.ndarray:
     dims = w["dims"]
     if w["kind"] == "noise":
         U = near_identity_su3(dims, w["eps"], w["seed"])
+    elif w["kind"] == "rough":
+        U = rough_block(dims, w["eps"], w["seed"], w["block"])
     else:
         U = u1_flux(dims, *w["flux"])
         U = left_multiply(near_identity_su3(dims, w["eps"], w["seed"]), U)
