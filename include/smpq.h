@@ -41,6 +41,7 @@ extern "C" {
 #endif
 
 #define SMPQ_MAX_POLES 32
+#define SMPQ_MAX_DEFLATED 256
 
 typedef struct smpq_ctx smpq_ctx;
 
@@ -209,6 +210,27 @@ smpq_status smpq_compute_trinv(smpq_ctx *ctx, const int32_t *classes, int n, dou
  * Averaging over the sites at one distance and fitting the logarithm gives the decay rate
  * gamma of Eq. 12. */
 smpq_status smpq_dov_locality(smpq_ctx *ctx, int64_t site, double *mean_abs, smpq_stats *st);
+
+/* Low-mode deflation of eps(H_W) (the exact sign on the lowest modes, the Zolotarev function
+ * on the rest; the usual companion of the Zolotarev approximation of Eq. 4 when a few
+ * eigenvalues of |H_W| lie far below the others).  Computes the n_modes lowest eigenpairs
+ * (theta_i, u_i) of H_W^2 = D_W^dag D_W by `steps` steps of shift-and-invert Lanczos: Lanczos
+ * with full reorthogonalisation on (H_W^2)^-1, each application an FP64 CG solve to relative
+ * residual 1e-14 (start vector from the SplitMix64 stream 1; every Lanczos vector, 192 V_pad
+ * bytes, is held on the device during the call); theta_i = <u_i, H^2 u_i> of the Ritz vectors.
+ * It keeps u_i and w_i = H_W u_i / sqrt(theta_i).  From then on smpq_compute_qx, _classes, _points, _multi and
+ * smpq_apply_dov use
+ *     eps b = sum_i w_i <u_i, b> + eps_Z(H_W) (b - sum_i u_i <u_i, b>)
+ * (eps(H) = H (H^2)^(-1/2) maps u_i to w_i exactly); smpq_compute_trinv is unaffected.
+ * n_modes = 0 removes the deflation.  Outputs (nullable): theta[n_modes + 1] = the deflated
+ * values of H^2 ascending followed by the next Ritz value (the bottom of what the Zolotarev
+ * function must cover); theta_max = the largest eigenvalue of H^2 (300 plain Lanczos steps);
+ * max_resid = max_i ||H^2 u_i - theta_i u_i|| / theta_max.  With no Zolotarev coefficients set, the next q(x)
+ * computation takes the interval [0.9 sqrt(theta[n_modes]), 1.02 sqrt(theta_max)].
+ * Errors: EINVAL (n_modes outside 0..SMPQ_MAX_DEFLATED, steps <= n_modes), ENUMERIC (the
+ * Lanczos process ended before n_modes + 1 steps). */
+smpq_status smpq_deflate(smpq_ctx *ctx, int n_modes, int steps, double *theta, double *theta_max,
+                         double *max_resid);
 
 /* Exact point-source density (Eq. 5) on n listed sites: qx[i] = q(sites[i]).  Does not
  * change the scheme set with smpq_set_scheme. */

@@ -20,7 +20,7 @@ __all__ = [
     "smpq_set_kappa", "smpq_lanczos", "smpq_estimate_bounds", "smpq_set_zolotarev",
     "smpq_get_zolotarev", "smpq_set_solver", "smpq_set_batch", "smpq_set_scheme",
     "smpq_set_point_scheme", "smpq_get_coloring", "smpq_get_scheme_rmin", "smpq_apply_dw", "smpq_apply_dov",
-    "smpq_compute_qx", "smpq_compute_qx_classes", "smpq_compute_trinv", "smpq_dov_locality", "smpq_compute_qx_points", "smpq_prepare", "smpq_set_stream",
+    "smpq_compute_qx", "smpq_compute_qx_classes", "smpq_compute_trinv", "smpq_dov_locality", "smpq_deflate", "smpq_compute_qx_points", "smpq_prepare", "smpq_set_stream",
     "smpq_set_timing", "smpq_set_graphs", "smpq_bench_dslash", "smpq_autotune",
     "smpq_set_tuning", "smpq_get_tuning", "smpq_set_memory_limit", "smpq_compute_qx_multi",
 ]
@@ -76,6 +76,7 @@ _SIG = {
                                                _c_double_p, ctypes.POINTER(SmpqStats)]),
     "smpq_compute_trinv": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int, _c_double_p,
                                           _c_double_p, ctypes.POINTER(SmpqStats)]),
+    "smpq_deflate": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _c_double_p, _c_double_p, _c_double_p]),
     "smpq_dov_locality": (ctypes.c_int, [_vp, ctypes.c_int64, _c_double_p, ctypes.POINTER(SmpqStats)]),
     "smpq_compute_qx_points": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, _c_double_p,
                                               ctypes.POINTER(SmpqStats)]),
@@ -287,6 +288,16 @@ def smpq_compute_trinv(ctx, classes=None):
         cp, n = cl.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(cl)
     _check(ctx, _lib.smpq_compute_trinv(ctx.ptr, cp, n, _dp(t_re), _dp(t_im), ctypes.byref(st)))
     return t_re + 1j * t_im, st.as_dict()
+
+
+def smpq_deflate(ctx, n_modes, steps=80):
+    """Deflate the n_modes lowest modes of H_W^2; returns (theta[n_modes + 1], theta_max,
+    max relative residual)."""
+    th = np.zeros(max(n_modes, 0) + 1)
+    tmax, res = ctypes.c_double(), ctypes.c_double()
+    _check(ctx, _lib.smpq_deflate(ctx.ptr, int(n_modes), int(steps), _dp(th), ctypes.byref(tmax),
+                                  ctypes.byref(res)))
+    return th, tmax.value, res.value
 
 
 def smpq_dov_locality(ctx, site):

@@ -140,6 +140,12 @@ struct smpq_ctx {
     const Coef *coef = &coef_eps;
     const Coef *graph_coef = nullptr;   // the set the captured graphs were built with
     DevMem inv_cd;                      // {1, 0}: c and delta of the unshifted system
+    // low-mode deflation: k eigenvectors u_i of H^2, w_i = H u_i / sqrt(theta_i), and the
+    // per-slot coefficients <u_i, b> of the current batch
+    int defl_k = 0;
+    std::vector<double> defl_theta;
+    double defl_next = 0.0, defl_tmax = 0.0;
+    DevMem defl_u, defl_w, defl_coef;
     smpq_precision prec = SMPQ_FP64;
     double tol = 1e-12;
     int max_iter = 10000;
@@ -681,6 +687,155 @@ void lanczos(smpq_ctx *c, int steps, uint64_t seed, double *tmin, double *tmax) 
     tridiag_extremes(alpha, beta, tmin, tmax);
 }
 
+// Lanczos with full (two-pass classical Gram-Schmidt) reorthogonalisation in FP64 for the
+// hermitian operator `apply` (w = A q), every vector kept in Q; returns the tridiagonal
+// (alpha, beta) of the steps taken (fewer when an invariant subspace is found).
+template <class Apply>
+void lanczos_full(smpq_ctx *c, int steps, uint64_t seed, double2 *Qp, DevMem &w, DevMem &part, DevMem &h,
+                  Apply apply, std::vector<double> &alpha, std::vector<double> &beta) {
+    const Geom g = c->geom();
+    const size_t vl = 12 * c->vs;
+    hipStream_t s = c->stream;
+    std::vector<double> hv((size_t)24 * c->V), stage;
+    double nrm = 0.0;
+    for (size_t i = 0; i < hv.size(); ++i) {
+        hv[i] = 2.0 * splitmix64_uniform(seed, i) - 1.0;
+        nrm += hv[i] * hv[i];
+    }
+    for (double &x : hv) x /= std::sqrt(nrm);
+    spinor_to_device(c, hv.data(), 1, stage);
+    HIPCHK(hipMemcpyAsync(Qp, stage.data(), vl * sizeof(double2), hipMemcpyHostToDevice, s));
+    double2 *wp = w.as<double2>();
+    double2 hw[1];
+    alpha.clear();
+    beta.clear();
+    for (int j = 0; j < steps; ++j) {
+        double2 *qj = Qp + (size_t)j * vl;
+        apply(qj, wp);
+        launch_multi_dot(g, qj, 0, 1, wp, part.as<double>(), h.as<double2>(), s);
+        HIPCHK(hipMemcpyAsync(hw, h.p, sizeof(double2), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double a = hw[0].x;
+        alpha.push_back(a);
+        if (j == steps - 1) break;
+        launch_lanczos_update(g, wp, qj, j > 0 ? qj - vl : qj, a, j > 0 ? beta.back() : 0.0, part.as<double>(), s);
+        for (int pass = 0; pass < 2; ++pass) {
+            launch_multi_dot(g, Qp, vl, j + 1, wp, part.as<double>(), h.as<double2>(), s);
+            launch_multi_axpy(g, Qp, vl, j + 1, h.as<double2>(), wp, false, s);
+        }
+        launch_multi_dot(g, wp, 0, 1, wp, part.as<double>(), h.as<double2>(), s);
+        HIPCHK(hipMemcpyAsync(hw, h.p, sizeof(double2), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double b = std::sqrt(hw[0].x);
+        if (!(b > 1e-14 * (std::fabs(a) + (beta.empty() ? 0.0 : beta.back()))) || !std::isfinite(b)) break;
+        beta.push_back(b);
+        launch_scale(g, Qp + (size_t)(j + 1) * vl, wp, 1.0 / b, s);
+    }
+    HIPCHK(hipGetLastError());
+    beta.resize(alpha.size() - 1);
+}
+
+// The k lowest eigenpairs of H^2 by shift-and-invert Lanczos: Lanczos on (H^2)^-1, applied
+// by an FP64 CG solve to relative residual 1e-14 (the multi-shift solver with the single
+// shift 0), turns the lowest eigenvalues theta of H^2 into the largest, best separated ones,
+// 1/theta; the Ritz vectors u_i of the k largest are refined by their Rayleigh quotients
+// theta_i = <u_i, H^2 u_i>, and w_i = H u_i / sqrt(theta_i) = gamma5 D_W u_i / sqrt(theta_i).
+// theta_max comes from the plain Lanczos bound of the context (300 steps).
+void deflate(smpq_ctx *c, int k, int steps, double *theta_out, double *tmax_out, double *resid_out) {
+    const Geom g = c->geom();
+    const size_t vl = 12 * c->vs;   // double2 per vector
+    const size_t v64 = vl * sizeof(double2);
+    hipStream_t s = c->stream;
+    const Slots one{nullptr, nullptr, 1};
+    steps = std::min(steps, 12 * c->V);
+    DevMem Q, t, w, part, h;
+    Q.ensure(v64 * steps);
+    t.ensure(v64);
+    w.ensure(v64);
+    const int np = unit_parts(0, g);
+    part.ensure(sizeof(double) * std::max<size_t>((size_t)2 * steps * np, partial_stride(g)));
+    h.ensure(sizeof(double2) * (steps + 2));
+    double2 *Qp = Q.as<double2>(), *tp = t.as<double2>(), *wp = w.as<double2>();
+    auto h2 = [&](const double2 *in, double2 *out, double sigma) {   // out = (H^2 + sigma) in
+        launch_dslash(0, false, 0, c->U64.p, in, 0, 0, tp, 0, nullptr, 0, 0, g, c->kappa, 0.0, one, 1, nullptr, s);
+        launch_dslash(0, true, 1, c->U64.p, tp, 0, 0, out, 0, in, 0, 0, g, c->kappa, sigma, one, 1,
+                      part.as<double>(), s);
+    };
+    // the inner solves run in FP64 at tolerance 1e-14 with the unshifted coefficient set
+    struct Keep {
+        smpq_ctx *c;
+        smpq_precision prec;
+        double tol;
+        ~Keep() {
+            c->prec = prec;
+            c->tol = tol;
+            use_coef(c, false);
+        }
+    } keep{c, c->prec, c->tol};
+    c->prec = SMPQ_FP64;
+    c->tol = 1e-14;
+    use_coef(c, true);
+    ensure_workspace(c, 0, 1, c->ws.prec == 0 && c->ws.NS == 1 ? c->ws.B : 1);
+    auto inverse = [&](const double2 *q, double2 *o) {
+        Source src{nullptr, nullptr, nullptr, q};
+        run_batch(c, 0, 1, src, nullptr);
+        HIPCHK(hipMemcpyAsync(o, c->ws.y.p, v64, hipMemcpyDeviceToDevice, s));
+    };
+    std::vector<double> alpha, beta, ev, Z;
+    lanczos_full(c, steps, 1, Qp, w, part, h, inverse, alpha, beta);
+    try {
+        tridiag_eigen(alpha, beta, ev, Z);
+    } catch (const std::exception &e) {
+        throw Fail{SMPQ_ENUMERIC, e.what()};
+    }
+    const int m = (int)ev.size();
+    if (m <= k) throw Fail{SMPQ_ENUMERIC, "Lanczos ended before n_modes + 1 steps"};
+    double tmin_b, tmax_b;
+    lanczos(c, 300, 0, &tmin_b, &tmax_b);
+    c->defl_k = 0;
+    c->defl_u.release();
+    c->defl_w.release();
+    c->defl_u.ensure(v64 * k);
+    c->defl_w.ensure(v64 * k);
+    std::vector<double2> sv(m);
+    std::vector<double> th(k);
+    double2 hw[1];
+    double worst = 0.0;
+    for (int i = 0; i < k; ++i) {
+        const int col = m - 1 - i;   // largest eigenvalues of (H^2)^-1 first
+        for (int j = 0; j < m; ++j) sv[j] = make_double2(Z[(size_t)col * m + j], 0.0);
+        HIPCHK(hipMemcpyAsync(h.p, sv.data(), sizeof(double2) * m, hipMemcpyHostToDevice, s));
+        double2 *ui = c->defl_u.as<double2>() + (size_t)i * vl, *wi = c->defl_w.as<double2>() + (size_t)i * vl;
+        launch_multi_axpy(g, Qp, vl, m, h.as<double2>(), ui, true, s);
+        h2(ui, wp, 0.0);
+        launch_multi_dot(g, ui, 0, 1, wp, part.as<double>(), h.as<double2>() + m, s);
+        HIPCHK(hipMemcpyAsync(hw, h.as<double2>() + m, sizeof(double2), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        th[i] = hw[0].x;
+        if (!(th[i] > 0.0)) throw Fail{SMPQ_ENUMERIC, "non-positive Rayleigh quotient of H^2"};
+        h2(ui, wp, -th[i]);   // residual H^2 u - theta u
+        launch_multi_dot(g, wp, 0, 1, wp, part.as<double>(), h.as<double2>() + m, s);
+        HIPCHK(hipMemcpyAsync(hw, h.as<double2>() + m, sizeof(double2), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        worst = std::max(worst, std::sqrt(hw[0].x) / tmax_b);
+        launch_dslash(0, false, 0, c->U64.p, ui, 0, 0, wi, 0, nullptr, 0, 0, g, c->kappa, 0.0, one, 1, nullptr, s);
+        launch_g5_scale(g, wi, 1.0 / std::sqrt(th[i]), s);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    c->defl_theta = th;
+    c->defl_next = 1.0 / ev[m - 1 - k];
+    c->defl_tmax = tmax_b;
+    c->defl_k = k;
+    c->gen++;
+    if (theta_out) {
+        for (int i = 0; i < k; ++i) theta_out[i] = th[i];
+        theta_out[k] = c->defl_next;
+    }
+    if (tmax_out) *tmax_out = tmax_b;
+    if (resid_out) *resid_out = worst;
+}
+
 void set_zolo(smpq_ctx *c, int n, double lo, double hi) {
     if (n < 1 || n > SMPQ_MAX_POLES) throw Fail{SMPQ_EINVAL, "n_poles must be in 1..SMPQ_MAX_POLES"};
     if (!(lo > 0.0) || !(hi > lo) || !std::isfinite(hi))
@@ -697,6 +852,10 @@ void set_zolo(smpq_ctx *c, int n, double lo, double hi) {
 
 void auto_zolo(smpq_ctx *c, smpq_stats *st) {
     if (c->have_zolo) return;
+    if (c->defl_k > 0) {   // the deflation's Lanczos already bounds the rest of the spectrum
+        set_zolo(c, 14, 0.9 * std::sqrt(c->defl_next), 1.02 * std::sqrt(c->defl_tmax));
+        return;
+    }
     const double t0 = now_s();
     double tmin, tmax;
     lanczos(c, 300, 0, &tmin, &tmax);
@@ -736,11 +895,22 @@ void qx_classes(smpq_ctx *c, const std::vector<int> &classes, bool point, smpq_s
         HIPCHK(hipMemcpyAsync(w.batch_classes.p, classes.data() + k0, sizeof(int) * nc, hipMemcpyHostToDevice,
                               c->stream));
         Source src{colour, w.slot_class.as<int>(), w.slot_comp.as<int>(), nullptr};
+        const int dk = inverse ? 0 : c->defl_k;
+        if (dk > 0) {
+            c->defl_coef.ensure(sizeof(double2) * (size_t)B * dk);
+            launch_defl_coef_probe(c->geom(), c->defl_u.as<double2>(), dk, w.slot_class.as<int>(),
+                                   w.slot_comp.as<int>(), cptr, csites, 12 * nc, c->defl_coef.as<double2>(),
+                                   c->stream);
+            src.du = c->defl_u.as<double2>();
+            src.dcoef = c->defl_coef.as<double2>();
+            src.dk = dk;
+        }
         const double t0 = now_s();
         BatchResult r = run_batch(c, prec, 12 * nc, src, st);
         const double t1 = now_s();
         launch_contract(c->geom(), c->U64.as<double2>(), w.y.as<double2>(), c->kappa, w.batch_classes.as<int>(), nc,
-                        maxsize, cptr, csites, c->qx.as<double>(), c->qxi.as<double>(), inverse, c->stream);
+                        maxsize, cptr, csites, c->qx.as<double>(), c->qxi.as<double>(), inverse,
+                        c->defl_w.as<double2>(), c->defl_coef.as<double2>(), dk, c->stream);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(c->stream));
         if (st) {
@@ -1187,7 +1357,7 @@ smpq_status smpq_apply_dov(smpq_ctx *c, const double *in, double *out, int n) {
         const size_t v64 = 12 * 16 * c->vs;
         std::vector<double> stage;
         spinor_to_device(c, in, n, stage);
-        DevMem bin, bout;
+        DevMem bin, bout, defl_part;
         bin.ensure(v64 * n);
         bout.ensure(v64 * n);
         HIPCHK(hipMemcpyAsync(bin.p, stage.data(), v64 * n, hipMemcpyHostToDevice, c->stream));
@@ -1197,17 +1367,48 @@ smpq_status smpq_apply_dov(smpq_ctx *c, const double *in, double *out, int n) {
             const int nb = std::min(B, n - k0);
             const double2 *bptr = bin.as<double2>() + (size_t)k0 * 12 * c->vs;
             Source src{nullptr, nullptr, nullptr, bptr};
+            const int dk = c->defl_k;
+            if (dk > 0) {   // coefficients <u_i, b> of every right-hand side of the batch
+                c->defl_coef.ensure(sizeof(double2) * (size_t)B * dk);
+                defl_part.ensure(sizeof(double) * 2 * (size_t)dk * unit_parts(0, g));
+                for (int j = 0; j < nb; ++j)
+                    launch_multi_dot(g, c->defl_u.as<double2>(), 12 * c->vs, dk, bptr + (size_t)j * 12 * c->vs,
+                                     defl_part.as<double>(), c->defl_coef.as<double2>() + (size_t)j * dk, c->stream);
+                src.du = c->defl_u.as<double2>();
+                src.dcoef = c->defl_coef.as<double2>();
+                src.dk = dk;
+            }
             run_batch(c, prec, nb, src, nullptr);
             // D_ov b = b + gamma5 eps b = b + D_W y   (eps b = gamma5 D_W y)
             Slots sl{nullptr, nullptr, nb};
             launch_dslash(0, false, 1, c->U64.p, c->ws.y.p, 12 * c->vs, 0,
                           bout.as<double2>() + (size_t)k0 * 12 * c->vs, 12 * c->vs, bptr, 12 * c->vs, 0, g, c->kappa,
                           1.0, sl, nb, c->ws.partial.as<double>(), c->stream);
+            if (dk > 0)
+                launch_add_defl(g, bout.as<double2>() + (size_t)k0 * 12 * c->vs, c->defl_w.as<double2>(), dk,
+                                c->defl_coef.as<double2>(), nb, c->stream);
             HIPCHK(hipGetLastError());
         }
         HIPCHK(hipMemcpyAsync(stage.data(), bout.p, v64 * n, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         spinor_from_device(c, stage, n, out);
+    });
+}
+
+smpq_status smpq_deflate(smpq_ctx *c, int n_modes, int steps, double *theta, double *theta_max, double *max_resid) {
+    return guarded(c, [&] {
+        if (n_modes < 0 || n_modes > SMPQ_MAX_DEFLATED) throw Fail{SMPQ_EINVAL, "n_modes out of range"};
+        if (n_modes == 0) {
+            c->defl_k = 0;
+            c->defl_u.release();
+            c->defl_w.release();
+            c->gen++;
+            return;
+        }
+        if (steps <= n_modes) throw Fail{SMPQ_EINVAL, "need steps > n_modes"};
+        need_device(c);
+        if (!c->have_gauge) throw Fail{SMPQ_ESTATE, "no gauge field loaded"};
+        deflate(c, n_modes, steps, theta, theta_max, max_resid);
     });
 }
 
@@ -1355,6 +1556,8 @@ smpq_status smpq_compute_qx_multi(smpq_ctx *const *ctxs, int n_ctx, const int32_
             smpq_ctx *c = ctxs[k];
             const smpq_status s = guarded(c, [&] {
                 if (planned[k] > 0) ensure_workspace(c, c->prec == SMPQ_FP64 ? 0 : 1, c->zolo.n, planned[k]);
+                if (planned[k] > 0 && c->defl_k > 0)
+                    c->defl_coef.ensure(sizeof(double2) * (size_t)planned[k] * c->defl_k);
             });
             if (s != SMPQ_OK) return give_up(k, s);
         }

@@ -146,6 +146,73 @@ void tridiag_extremes(const std::vector<double> &alpha, const std::vector<double
     *hi = bisect(static_cast<int>(n) - 1);
 }
 
+// All eigenpairs of the symmetric tridiagonal matrix with diagonal d (n) and off-diagonal e
+// (n - 1) by the implicit QL iteration with Wilkinson shifts (Bowdler, Martin, Reinsch and
+// Wilkinson, Numer. Math. 11 (1968)): plane rotations chase the bulge from the bottom of the
+// unreduced block to its top, and their product, accumulated in z, gives the eigenvectors.
+// On return evals is ascending and column j of z (n x n, column-major) is its eigenvector.
+void tridiag_eigen(std::vector<double> d, std::vector<double> e, std::vector<double> &evals,
+                   std::vector<double> &z) {
+    const int n = static_cast<int>(d.size());
+    e.resize(n, 0.0);
+    z.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) z[(size_t)i * n + i] = 1.0;
+    for (int l = 0; l < n; ++l) {
+        for (int iter = 0;; ++iter) {
+            int m = l;
+            for (; m < n - 1; ++m) {   // first negligible off-diagonal entry at or below l
+                const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+                if (std::fabs(e[m]) <= 1e-16 * dd) break;
+            }
+            if (m == l) break;
+            if (iter == 100) throw std::runtime_error("tridiag_eigen: no convergence");
+            // Wilkinson shift from the leading 2x2 block
+            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double r = std::hypot(g, 1.0);
+            g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
+            double s = 1.0, c = 1.0, p = 0.0;
+            int i = m - 1;
+            for (; i >= l; --i) {
+                const double f = s * e[i], b = c * e[i];
+                r = std::hypot(f, g);
+                e[i + 1] = r;
+                if (r == 0.0) {   // the rotation split the block: deflate and restart
+                    d[i + 1] -= p;
+                    e[m] = 0.0;
+                    break;
+                }
+                s = f / r;
+                c = g / r;
+                g = d[i + 1] - p;
+                r = (d[i] - g) * s + 2.0 * c * b;
+                p = s * r;
+                d[i + 1] = g + p;
+                g = c * r - b;
+                for (int k = 0; k < n; ++k) {   // rotate columns i and i+1 of z
+                    const double zi = z[(size_t)i * n + k], zi1 = z[(size_t)(i + 1) * n + k];
+                    z[(size_t)(i + 1) * n + k] = s * zi + c * zi1;
+                    z[(size_t)i * n + k] = c * zi - s * zi1;
+                }
+            }
+            if (r == 0.0 && i >= l) continue;
+            d[l] -= p;
+            e[l] = g;
+            e[m] = 0.0;
+        }
+    }
+    // ascending order
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return d[a] < d[b]; });
+    evals.resize(n);
+    std::vector<double> zs((size_t)n * n);
+    for (int j = 0; j < n; ++j) {
+        evals[j] = d[order[j]];
+        std::copy(z.begin() + (size_t)order[j] * n, z.begin() + (size_t)(order[j] + 1) * n, zs.begin() + (size_t)j * n);
+    }
+    z.swap(zs);
+}
+
 // SplitMix64 (Steele, Lea, Flood 2014) as a counter-based stream: word i of stream
 // `seed` is mix(seed + (i + 1) * 0x9e3779b97f4a7c15), mapped to [0, 1) by its top 53 bits.
 double splitmix64_uniform(uint64_t seed, uint64_t i) {

@@ -57,6 +57,10 @@ struct Source {
     const int *slot_class;  // probing: class of each slot
     const int *slot_comp;   // probing: component (spin*3 + colour) of each slot
     const double2 *b;       // explicit: FP64 vectors, slot stride 12*vs (null for probing)
+    // deflation: the source is b - sum_{i < dk} dcoef[slot dk + i] u_i, u_i = du + i 12 vs
+    const double2 *du = nullptr;
+    const double2 *dcoef = nullptr;
+    int dk = 0;
 };
 
 enum { kStatusOK = 0, kStatusBreakdown = 1 };
@@ -99,15 +103,30 @@ void launch_reliable(int prec, const Geom &g, const MSState &s, const Source &sr
                      void *r, hipStream_t st);
 void launch_scalars_rr(const MSState &s, int npart, hipStream_t st);
 
+// Low-mode deflation helpers (FP64 vectors [12][vs]).  multi_dot: out[i] = <q_i, w> for
+// q_i = Q + i qstride, i < nq (partial: 2 nq unit_parts doubles); multi_axpy: w -= sum h_i q_i,
+// or w = sum h_i q_i with overwrite; g5_scale: v = f gamma5 v; defl_coef_probe: coef[slot k +
+// i] = <u_i, phi_slot> for probing sources; add_defl: out_slot += gamma5 sum_i coef w_i.
+void launch_multi_dot(const Geom &g, const double2 *Q, size_t qstride, int nq, const double2 *w, double *partial,
+                      double2 *out, hipStream_t st);
+void launch_multi_axpy(const Geom &g, const double2 *Q, size_t qstride, int nq, const double2 *h, double2 *w,
+                       bool overwrite, hipStream_t st);
+void launch_g5_scale(const Geom &g, double2 *v, double f, hipStream_t st);
+void launch_defl_coef_probe(const Geom &g, const double2 *u, int k, const int *slot_class, const int *slot_comp,
+                            const int *class_ptr, const int *class_sites, int nslots, double2 *coef, hipStream_t st);
+void launch_add_defl(const Geom &g, double2 *out, const double2 *w, int k, const double2 *coef, int nslots,
+                     hipStream_t st);
+
 // m(x) = mean |D_ov(x i; site j)| over the 144 entries, from d_j = D_W y_j of the twelve
 // point-source columns of `site` (Eq. 12).
 void launch_block_mean_abs(const Geom &g, const double2 *d, int site, double *m, hipStream_t st);
 
 // q(x) contraction (Eq. 16) for the classes of one batch; slot = 12*class_pos + comp.
-// inverse: the trace density of D_W^-1 from y = (D_W^dag D_W)^-1 phi instead.
+// inverse: the trace density of D_W^-1 from y = (D_W^dag D_W)^-1 phi instead.  dk deflated
+// modes add their exact-sign part from dw (H u_i / sqrt(theta_i)) and dcoef ([slot][dk]).
 void launch_contract(const Geom &g, const double2 *U64, const double2 *y, double kappa, const int *batch_classes,
                      int n_classes, int max_class_size, const int *class_ptr, const int *class_sites, double *qx,
-                     double *qxi, bool inverse, hipStream_t st);
+                     double *qxi, bool inverse, const double2 *dw, const double2 *dcoef, int dk, hipStream_t st);
 
 // Lanczos helpers (single FP64 vector); the update writes unit_parts(0, g) partials
 void launch_lanczos_update(const Geom &g, double2 *w, const double2 *v, const double2 *vprev, double alpha,

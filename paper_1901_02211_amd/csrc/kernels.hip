@@ -725,9 +725,21 @@ __device__ __forceinline__ void block_partial(double v, double *partial, size_t 
 
 // Entry c of the source of a slot at site s.
 __device__ __forceinline__ cpx<double> source_entry(const Source &src, int slot, int c, int s, size_t vs) {
-    if (src.b) return ld64(src.b + (size_t)slot * 12 * vs, vs, c, s);
-    const bool on = (src.colour[s] == src.slot_class[slot]) && (c == src.slot_comp[slot]);
-    return {on ? 1.0 : 0.0, 0.0};
+    cpx<double> v;
+    if (src.b) {
+        v = ld64(src.b + (size_t)slot * 12 * vs, vs, c, s);
+    } else {
+        const bool on = (src.colour[s] == src.slot_class[slot]) && (c == src.slot_comp[slot]);
+        v = {on ? 1.0 : 0.0, 0.0};
+    }
+    // deflated modes projected out: b - sum_i <u_i, b> u_i
+    for (int i = 0; i < src.dk; ++i) {
+        const double2 a = src.dcoef[(size_t)slot * src.dk + i];
+        const cpx<double> u = ld64(src.du + (size_t)i * 12 * vs, vs, c, s);
+        v.re -= a.x * u.re - a.y * u.im;
+        v.im -= a.x * u.im + a.y * u.re;
+    }
+    return v;
 }
 
 int unit_parts(int prec, const Geom &g) { return (prec == 0 ? 12 : 6) * site_blocks(g); }
@@ -1141,10 +1153,13 @@ void launch_scalars_rr(const MSState &s, int npart, hipStream_t st) {
 // (from D_W^-1 = D_W^dag (D_W D_W^dag)^-1, D_W D_W^dag = gamma5 D_W^dag D_W gamma5 and
 // gamma5 phi = g_j phi), so component j of D_W^-1 phi at x is [D_W y_slot](x, j):
 //   t(x) += [D_W y_slot](x, j)  (real part into qx, imaginary part into qxi).
+// With deflated modes (dk > 0), eps phi gains sum_i c_i w_i (w_i = H u_i / sqrt(theta_i),
+// c_i = <u_i, phi>), which adds 1/2 sum_i c_i w_i(x, j) to [gamma5 D_ov phi](x, j) / 2.
 template <bool INV>
 __global__ __launch_bounds__(kBlock) void k_contract(Geom g, const double2 *U64, const double2 *y, double kappa,
                                                      const int *batch_classes, const int *class_ptr,
-                                                     const int *class_sites, double *qx, double *qxi) {
+                                                     const int *class_sites, double *qx, double *qxi,
+                                                     const double2 *dw, const double2 *dcoef, int dk) {
     const int ci = blockIdx.y;
     const int cls = batch_classes[ci];
     const int beg = class_ptr[cls], end = class_ptr[cls + 1];
@@ -1167,6 +1182,13 @@ __global__ __launch_bounds__(kBlock) void k_contract(Geom g, const double2 *U64,
             const double g5 = (j < 6) ? 0.5 : -0.5;
             q += g5 * (1.0 + dre);
             qi += g5 * dim;
+            const int slot = 12 * ci + j;
+            for (int i = 0; i < dk; ++i) {
+                const double2 a = dcoef[(size_t)slot * dk + i];
+                const cpx<double> w = ld64(dw + (size_t)i * 12 * g.vs, g.vs, j, x);
+                q += 0.5 * (a.x * w.re - a.y * w.im);
+                qi += 0.5 * (a.x * w.im + a.y * w.re);
+            }
         }
     }
     qx[x] = q;
@@ -1175,14 +1197,14 @@ __global__ __launch_bounds__(kBlock) void k_contract(Geom g, const double2 *U64,
 
 void launch_contract(const Geom &g, const double2 *U64, const double2 *y, double kappa, const int *batch_classes,
                      int n_classes, int max_class_size, const int *class_ptr, const int *class_sites, double *qx,
-                     double *qxi, bool inverse, hipStream_t st) {
+                     double *qxi, bool inverse, const double2 *dw, const double2 *dcoef, int dk, hipStream_t st) {
     dim3 grid((max_class_size + kBlock - 1) / kBlock, n_classes);
     if (inverse)
         hipLaunchKernelGGL(k_contract<true>, grid, dim3(kBlock), 0, st, g, U64, y, kappa, batch_classes, class_ptr,
-                           class_sites, qx, qxi);
+                           class_sites, qx, qxi, nullptr, nullptr, 0);
     else
         hipLaunchKernelGGL(k_contract<false>, grid, dim3(kBlock), 0, st, g, U64, y, kappa, batch_classes, class_ptr,
-                           class_sites, qx, qxi);
+                           class_sites, qx, qxi, dw, dcoef, dk);
 }
 
 // ------------------------------------------------------------------ locality of D_ov (Eq. 12)
@@ -1245,6 +1267,169 @@ __global__ __launch_bounds__(kBlock) void k_scale(Geom g, double2 *dst, const do
 
 void launch_scale(const Geom &g, double2 *dst, const double2 *src, double f, hipStream_t st) {
     hipLaunchKernelGGL(k_scale, dim3(unit_parts(0, g)), dim3(kBlock), 0, st, g, dst, src, f);
+}
+
+// ------------------------------------------------------------------ low-mode deflation (FP64)
+// Complex block sum of (re, im) written to partial[idx] and partial[idx + stride].
+__device__ __forceinline__ void block_partial_c(double re, double im, double *partial, size_t idx, size_t stride) {
+    __shared__ double lds[2][kBlock / 64];
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if ((threadIdx.x & 63) == 0) {
+        lds[0][threadIdx.x >> 6] = re;
+        lds[1][threadIdx.x >> 6] = im;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int i = 0; i < kBlock / 64; ++i) {
+            a += lds[0][i];
+            b += lds[1][i];
+        }
+        partial[idx] = a;
+        partial[idx + stride] = b;
+    }
+}
+
+// partial[(2 i + {0,1}) np + block] = Re, Im of the block's share of <q_i, w>, i < nq,
+// q_i = Q + i qstride; grid (np = unit_parts(0, g), nq).
+__global__ __launch_bounds__(kBlock) void k_multi_dot(Geom g, const double2 *Q, size_t qstride, const double2 *w,
+                                                      double *partial) {
+    const int nsb = site_blocks(g);
+    const int np = gridDim.x;
+    const int c = blockIdx.x / nsb;
+    const int s = (blockIdx.x % nsb) * kBlock + threadIdx.x;
+    const int i = blockIdx.y;
+    double re = 0.0, im = 0.0;
+    if (s < g.V) {
+        const double2 q = Q[(size_t)i * qstride + c * g.vs + s], x = w[c * g.vs + s];
+        re = q.x * x.x + q.y * x.y;
+        im = q.x * x.y - q.y * x.x;
+    }
+    block_partial_c(re, im, partial, (size_t)(2 * i) * np + blockIdx.x, np);
+}
+
+// out[i] = sum of the np partials of pair i, in a fixed order (one wave per i).
+__global__ void k_reduce_pairs(const double *partial, int np, double2 *out) {
+    const int i = blockIdx.x;
+    const double re = wave_sum_partials(partial + (size_t)(2 * i) * np, np);
+    const double im = wave_sum_partials(partial + (size_t)(2 * i + 1) * np, np);
+    if (threadIdx.x == 0) out[i] = make_double2(re, im);
+}
+
+// w -= sum_{i < nq} h_i q_i, or w = sum_{i < nq} h_i q_i when overwrite is set.
+__global__ __launch_bounds__(kBlock) void k_multi_axpy(Geom g, const double2 *Q, size_t qstride, int nq,
+                                                       const double2 *h, double2 *w, int overwrite) {
+    const int nsb = site_blocks(g);
+    const int c = blockIdx.x / nsb;
+    const int s = (blockIdx.x % nsb) * kBlock + threadIdx.x;
+    if (s >= g.V) return;
+    const size_t o = c * g.vs + s;
+    double ar = 0.0, ai = 0.0;
+#pragma unroll 4
+    for (int i = 0; i < nq; ++i) {
+        const double2 q = Q[(size_t)i * qstride + o], hh = h[i];
+        ar += hh.x * q.x - hh.y * q.y;
+        ai += hh.x * q.y + hh.y * q.x;
+    }
+    if (overwrite) {
+        w[o] = make_double2(ar, ai);
+    } else {
+        const double2 t = w[o];
+        w[o] = make_double2(t.x - ar, t.y - ai);
+    }
+}
+
+// v = f gamma5 v (gamma5 = +1 on spins 0, 1 and -1 on spins 2, 3; component c = 3 spin + colour).
+__global__ __launch_bounds__(kBlock) void k_g5_scale(Geom g, double2 *v, double f) {
+    const int nsb = site_blocks(g);
+    const int c = blockIdx.x / nsb;
+    const int s = (blockIdx.x % nsb) * kBlock + threadIdx.x;
+    if (s >= g.V) return;
+    const double ff = c < 6 ? f : -f;
+    const double2 t = v[c * g.vs + s];
+    v[c * g.vs + s] = make_double2(ff * t.x, ff * t.y);
+}
+
+// Deflation coefficients of probing sources: coef[slot k + i] = <u_i, phi_slot> = sum over the
+// sites x of the slot's class of conj(u_i(x, comp)); grid (k, nslots).
+__global__ __launch_bounds__(kBlock) void k_defl_coef_probe(Geom g, const double2 *u, int k, const int *slot_class,
+                                                            const int *slot_comp, const int *class_ptr,
+                                                            const int *class_sites, double2 *coef) {
+    const int i = blockIdx.x, slot = blockIdx.y;
+    const int cls = slot_class[slot], comp = slot_comp[slot];
+    const double2 *ui = u + (size_t)i * 12 * g.vs + comp * g.vs;
+    double re = 0.0, im = 0.0;
+    for (int t = class_ptr[cls] + threadIdx.x; t < class_ptr[cls + 1]; t += kBlock) {
+        const double2 v = ui[class_sites[t]];
+        re += v.x;
+        im -= v.y;
+    }
+    __shared__ double lds[2][kBlock / 64];
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if ((threadIdx.x & 63) == 0) {
+        lds[0][threadIdx.x >> 6] = re;
+        lds[1][threadIdx.x >> 6] = im;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int j = 0; j < kBlock / 64; ++j) {
+            a += lds[0][j];
+            b += lds[1][j];
+        }
+        coef[(size_t)slot * k + i] = make_double2(a, b);
+    }
+}
+
+// out_slot += gamma5 sum_i coef[slot k + i] w_i  (D_ov b of deflated modes), grid (units, nslots).
+__global__ __launch_bounds__(kBlock) void k_add_defl(Geom g, double2 *out, const double2 *w, int k,
+                                                     const double2 *coef) {
+    const int nsb = site_blocks(g);
+    const int c = blockIdx.x / nsb;
+    const int s = (blockIdx.x % nsb) * kBlock + threadIdx.x;
+    const int slot = blockIdx.y;
+    if (s >= g.V) return;
+    double ar = 0.0, ai = 0.0;
+    for (int i = 0; i < k; ++i) {
+        const double2 a = coef[(size_t)slot * k + i], v = w[(size_t)i * 12 * g.vs + c * g.vs + s];
+        ar += a.x * v.x - a.y * v.y;
+        ai += a.x * v.y + a.y * v.x;
+    }
+    const double f = c < 6 ? 1.0 : -1.0;
+    double2 &o = out[(size_t)slot * 12 * g.vs + c * g.vs + s];
+    o = make_double2(o.x + f * ar, o.y + f * ai);
+}
+
+void launch_multi_dot(const Geom &g, const double2 *Q, size_t qstride, int nq, const double2 *w, double *partial,
+                      double2 *out, hipStream_t st) {
+    const int np = unit_parts(0, g);
+    hipLaunchKernelGGL(k_multi_dot, dim3(np, nq), dim3(kBlock), 0, st, g, Q, qstride, w, partial);
+    hipLaunchKernelGGL(k_reduce_pairs, dim3(nq), dim3(64), 0, st, partial, np, out);
+}
+
+void launch_multi_axpy(const Geom &g, const double2 *Q, size_t qstride, int nq, const double2 *h, double2 *w,
+                       bool overwrite, hipStream_t st) {
+    hipLaunchKernelGGL(k_multi_axpy, dim3(unit_parts(0, g)), dim3(kBlock), 0, st, g, Q, qstride, nq, h, w,
+                       overwrite ? 1 : 0);
+}
+
+void launch_g5_scale(const Geom &g, double2 *v, double f, hipStream_t st) {
+    hipLaunchKernelGGL(k_g5_scale, dim3(unit_parts(0, g)), dim3(kBlock), 0, st, g, v, f);
+}
+
+void launch_defl_coef_probe(const Geom &g, const double2 *u, int k, const int *slot_class, const int *slot_comp,
+                            const int *class_ptr, const int *class_sites, int nslots, double2 *coef, hipStream_t st) {
+    hipLaunchKernelGGL(k_defl_coef_probe, dim3(k, nslots), dim3(kBlock), 0, st, g, u, k, slot_class, slot_comp,
+                       class_ptr, class_sites, coef);
+}
+
+void launch_add_defl(const Geom &g, double2 *out, const double2 *w, int k, const double2 *coef, int nslots,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_add_defl, dim3(unit_parts(0, g), nslots), dim3(kBlock), 0, st, g, out, w, k, coef);
 }
 
 // ------------------------------------------------------------------ precision conversion
