@@ -43,6 +43,7 @@ BENCH = {
     "noise16": (4, 0, 16, "16^4 near-identity SU(3) eps=0.1 seed 6, SMP normal mode r=4"),
     "noise24": (6, 48, 12, "24^4 near-identity SU(3) eps=0.2 seed 7, SMP normal mode r=6"),
     "noise32x64": (8, 16, 4, "32^3x64 near-identity SU(3) eps=0.3 seed 8, SMP normal mode r=8"),
+    "rough8": (4, 0, 16, "8^4 near-identity eps=0.3 seed 60 with a Haar-random 3^4 block, SMP normal mode r=4"),
 }
 UNEVEN = ("noise16", "noise24", "noise32x64")
 
@@ -167,6 +168,8 @@ def main():
                     help="time only the first N classes and extrapolate (0 = whole map)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=0)
+    ap.add_argument("--deflate", type=int, default=0, help="deflate this many low modes of H_W^2 in each step")
+    ap.add_argument("--deflate-steps", type=int, default=80)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -197,10 +200,18 @@ def main():
     classes = list(range(ncls if args.classes == 0 else min(args.classes, ncls)))
     scale = ncls / len(classes)             # extrapolation factor of a sampled map
 
+    defl_info = {}
+
     def one_map():
-        """One step: Lanczos bounds, Zolotarev coefficients and the whole q(x) map."""
+        """One step: Lanczos bounds (or the deflated modes), Zolotarev coefficients and the whole
+        q(x) map."""
         t0 = time.perf_counter()
-        lo, hi = smpq.smpq_estimate_bounds(ctx, 300)
+        if args.deflate > 0:    # the lowest modes exactly; the interval above them
+            theta, tmax, resid = smpq.smpq_deflate(ctx, args.deflate, args.deflate_steps)
+            defl_info.update(theta=theta.tolist(), theta_max=tmax, max_resid=resid)
+            lo, hi = 0.9 * np.sqrt(theta[-1]), 1.02 * np.sqrt(tmax)
+        else:
+            lo, hi = smpq.smpq_estimate_bounds(ctx, 300)
         smpq.smpq_set_zolotarev(ctx, POLES, lo, hi)
         t1 = time.perf_counter()
         if args.classes:
@@ -281,7 +292,8 @@ def main():
                 "abs_Q_minus_round": abs(Q - round(Q)) if scale == 1.0 else None,
                 "max_abs_imag_q": st["max_abs_imag_q"], "sum_imag_q": st["sum_imag_q"],
                 "lam_min": st["lam_min"], "lam_max": st["lam_max"], "zolo_delta": st["zolo_delta"],
-                "max_true_resid_base_fp64": st["max_true_resid"]}
+                "max_true_resid_base_fp64": st["max_true_resid"],
+                "deflation": dict(modes=args.deflate, **defl_info) if args.deflate else None}
     if args.full_fp64:
         accuracy["Q_fp64"] = float(q64.sum())
 
