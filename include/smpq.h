@@ -297,8 +297,9 @@ typedef struct {
     int f32_kind, f32_nr, f64_lgr, plane_band;
 } smpq_tuning;
 
-/* Choose the variants for this lattice by timing each on n_rhs right-hand sides (two
- * rotating buffer sets, 10 launches each; fewer right-hand sides where they would take more
+/* Choose the variants for this lattice by timing each on n_rhs right-hand sides as the solver
+ * uses it: D_W followed by D_W^dag with the +sigma term and its partial sums (two rotating
+ * buffer sets, 10 pairs, best of two runs; fewer right-hand sides where they would take more
  * than half of the free device memory).  The choice is kept by the context and written to
  * *chosen (may be NULL); on an error the previous choice is kept.  Without this call a
  * context uses kind 1 / 8 where the plane fits, else kind 2 / 8 where a tile fits, else kind

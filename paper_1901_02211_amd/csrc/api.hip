@@ -976,31 +976,42 @@ std::vector<int> class_list(const smpq_ctx *c, const int32_t *classes, int n) {
 }
 
 // Mean duration of the stencil (D_W, epilogue 0) on n_rhs right-hand sides, rotating through
-// n_sets disjoint input/output/link sets; *bytes = algorithmic bytes per launch.
-double time_dslash(smpq_ctx *c, int p, int n_rhs, int n_sets, int launches, double *bytes) {
+// n_sets disjoint input/output/link sets; *bytes = algorithmic bytes per launch.  With pair, one
+// timed unit is the solver's pair D_W then D_W^dag + sigma (epilogue 1, with its partial sums),
+// and *bytes covers both launches.
+double time_dslash(smpq_ctx *c, int p, int n_rhs, int n_sets, int launches, double *bytes, bool pair = false) {
     const Geom g = c->geom();
     const size_t units = p == 0 ? 12 : 6;
     const size_t vbytes = units * 16 * c->vs;
     const size_t lbytes = (size_t)c->V * (p == 0 ? 72 * 8 : 48 * 4);
+    const int nvec = pair ? 3 : 2;
     // at most half of the free device memory: fewer right-hand sides if need be
     size_t freeb = 0, totalb = 0;
     HIPCHK(hipMemGetInfo(&freeb, &totalb));
-    const size_t per_rhs = 2 * vbytes * n_sets;
+    const size_t per_rhs = nvec * vbytes * n_sets + (pair ? sizeof(double) * partial_stride(g) : 0);
     if (freeb / 2 < lbytes * n_sets + per_rhs) throw Fail{SMPQ_ENOMEM, "not enough device memory to time the stencil"};
     n_rhs = (int)std::min<size_t>(n_rhs, (freeb / 2 - lbytes * n_sets) / per_rhs);
-    std::vector<DevMem> ins(n_sets), outs(n_sets), links(n_sets);
+    std::vector<DevMem> vecs((size_t)nvec * n_sets), links(n_sets);
+    DevMem part;
+    if (pair) part.ensure(sizeof(double) * partial_stride(g) * n_rhs);
     for (int k = 0; k < n_sets; ++k) {
-        ins[k].ensure(vbytes * n_rhs);
-        outs[k].ensure(vbytes * n_rhs);
+        for (int v = 0; v < nvec; ++v) {
+            vecs[(size_t)k * nvec + v].ensure(vbytes * n_rhs);
+            HIPCHK(hipMemsetAsync(vecs[(size_t)k * nvec + v].p, 0, vbytes * n_rhs, c->stream));
+        }
         links[k].ensure(lbytes);
         HIPCHK(hipMemcpyAsync(links[k].p, p == 0 ? c->U64.p : c->U32.p, lbytes, hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(hipMemsetAsync(ins[k].p, 0, vbytes * n_rhs, c->stream));
     }
     Slots sl{nullptr, nullptr, n_rhs};
+    const size_t st = units * c->vs;
     auto one = [&](int i) {
         const int k = i % n_sets;
-        launch_dslash(p, false, 0, links[k].p, ins[k].p, units * c->vs, 0, outs[k].p, units * c->vs, nullptr, 0, 0, g,
-                      c->kappa, 0.0, sl, n_rhs, nullptr, c->stream);
+        void *a = vecs[(size_t)k * nvec].p, *b = vecs[(size_t)k * nvec + 1].p;
+        launch_dslash(p, false, 0, links[k].p, a, st, 0, b, st, nullptr, 0, 0, g, c->kappa, 0.0, sl, n_rhs, nullptr,
+                      c->stream);
+        if (pair)
+            launch_dslash(p, true, 1, links[k].p, b, st, 0, vecs[(size_t)k * nvec + 2].p, st, a, st, 0, g, c->kappa,
+                          0.1, sl, n_rhs, part.as<double>(), c->stream);
     };
     for (int i = 0; i < n_sets; ++i) one(i);   // warm-up
     hipEvent_t e0, e1;
@@ -1017,6 +1028,7 @@ double time_dslash(smpq_ctx *c, int p, int n_rhs, int n_sets, int launches, doub
     HIPCHK(hipGetLastError());
     const double u = p == 0 ? 16.0 : 8.0;
     *bytes = (double)c->V * ((double)lbytes / c->V + (double)n_rhs * 24.0 * u);
+    if (pair) *bytes = 2.0 * *bytes + (double)c->V * n_rhs * 24.0 * u;
     return t / launches;
 }
 
@@ -1756,7 +1768,8 @@ smpq_status smpq_autotune(smpq_ctx *c, int n_rhs, smpq_tuning *chosen) {
                 c->f32_kind = k.kind;
                 c->f32_nr = k.nr;
                 c->band = k.band;
-                const double t = time_dslash(c, 1, n_rhs, 2, 10, &by);
+                const double t = std::min(time_dslash(c, 1, n_rhs, 2, 10, &by, true),
+                                          time_dslash(c, 1, n_rhs, 2, 10, &by, true));
                 if (t < best) {
                     best = t;
                     pick = k;
@@ -1769,7 +1782,8 @@ smpq_status smpq_autotune(smpq_ctx *c, int n_rhs, smpq_tuning *chosen) {
             int lpick = keep.f64_lgr;
             for (int l = 0; l <= 2; ++l) {
                 c->f64_lgr = l;
-                const double t = time_dslash(c, 0, n_rhs, 2, 10, &by);
+                const double t = std::min(time_dslash(c, 0, n_rhs, 2, 10, &by, true),
+                                          time_dslash(c, 0, n_rhs, 2, 10, &by, true));
                 if (t < best) {
                     best = t;
                     lpick = l;
