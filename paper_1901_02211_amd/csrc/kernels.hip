@@ -44,6 +44,15 @@ struct Store<double> {
 #pragma unroll
         for (int c = 0; c < 12; ++c) p[c * vs + s] = make_double2(v[c].re, v[c].im);
     }
+    // the stencil's output: written once, read by the next kernel (non-temporal)
+    __device__ static __forceinline__ void store_stream(double2 *p, size_t vs, int s, const cpx<double> v[12]) {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const d2 t = {v[c].re, v[c].im};
+            __builtin_nontemporal_store(t, reinterpret_cast<d2 *>(p + c * vs + s));
+        }
+    }
 };
 
 template <>
@@ -63,6 +72,15 @@ struct Store<float> {
 #pragma unroll
         for (int k = 0; k < 6; ++k)
             p[k * vs + s] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+    }
+    // the stencil's output: written once, read by the next kernel (non-temporal)
+    __device__ static __forceinline__ void store_stream(float4 *p, size_t vs, int s, const cpx<float> v[12]) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const f4 t = {v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im};
+            __builtin_nontemporal_store(t, reinterpret_cast<f4 *>(p + k * vs + s));
+        }
     }
 };
 
@@ -201,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_dslash(const typename Store<T>::link
                 dot += (double)a[c].re * (double)v[c].re + (double)a[c].im * (double)v[c].im;
             }
         }
-        Store<T>::store(out + slot * out_stride, g.vs, s, v);
+        Store<T>::store_stream(out + slot * out_stride, g.vs, s, v);
     }
     if constexpr (EPI == 1) {
         // lanes with equal (lane mod R) hold the same right-hand side
@@ -296,7 +314,7 @@ __global__ __launch_bounds__(kBlock) void k_dslash_f32(const float4 *__restrict_
             }
             dot[r] = d;
         }
-        Store<float>::store(out + slot * out_stride, g.vs, sv, v);
+        Store<float>::store_stream(out + slot * out_stride, g.vs, sv, v);
     }
     if constexpr (EPI == 1) {
         __shared__ double lds[NR][kBlock / 64];
@@ -431,7 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_dslash_f32_tile(const float4 *__rest
             }
             dot[r] = d;
         }
-        Store<float>::store(out + slot * out_stride, g.vs, s, v);
+        Store<float>::store_stream(out + slot * out_stride, g.vs, s, v);
     }
     if constexpr (EPI == 1) {
         __shared__ double lds[NR][kBlock / 64];
@@ -543,7 +561,7 @@ __global__ __launch_bounds__(kBlock) void k_dslash_f32_plane(const float4 *__res
             }
             dot[r] = d;
         }
-        Store<float>::store(out + slot * out_stride, g.vs, s, v);
+        Store<float>::store_stream(out + slot * out_stride, g.vs, s, v);
     }
     if constexpr (EPI == 1) {
         __shared__ double lds[NR][kBlock / 64];
@@ -676,6 +694,9 @@ void launch_dslash(int prec, bool dag, int epi, const void *U, const void *in, s
 template <class T>
 struct Unit;
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
 template <>
 struct Unit<float> {
     static constexpr int C = 2;
@@ -686,6 +707,16 @@ struct Unit<float> {
     }
     __device__ static __forceinline__ void store(float4 *p, size_t vs, int u, int s, const cpx<float> v[2]) {
         p[u * vs + s] = make_float4(v[0].re, v[0].im, v[1].re, v[1].im);
+    }
+    // streamed (non-temporal) vector load/store: data touched once per kernel
+    __device__ static __forceinline__ void load_stream(const float4 *p, size_t vs, int u, int s, cpx<float> v[2]) {
+        const f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p + u * vs + s));
+        v[0] = {t.x, t.y};
+        v[1] = {t.z, t.w};
+    }
+    __device__ static __forceinline__ void store_stream(float4 *p, size_t vs, int u, int s, const cpx<float> v[2]) {
+        const f32x4 t = {v[0].re, v[0].im, v[1].re, v[1].im};
+        __builtin_nontemporal_store(t, reinterpret_cast<f32x4 *>(p + u * vs + s));
     }
 };
 
@@ -699,7 +730,25 @@ struct Unit<double> {
     __device__ static __forceinline__ void store(double2 *p, size_t vs, int u, int s, const cpx<double> v[1]) {
         p[u * vs + s] = make_double2(v[0].re, v[0].im);
     }
+    __device__ static __forceinline__ void load_stream(const double2 *p, size_t vs, int u, int s, cpx<double> v[1]) {
+        const f64x2 t = __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(p + u * vs + s));
+        v[0] = {t.x, t.y};
+    }
+    __device__ static __forceinline__ void store_stream(double2 *p, size_t vs, int u, int s, const cpx<double> v[1]) {
+        const f64x2 t = {v[0].re, v[0].im};
+        __builtin_nontemporal_store(t, reinterpret_cast<f64x2 *>(p + u * vs + s));
+    }
 };
+
+// FP64 complex entry c of an FP64 spinor (double2 planes), streamed (non-temporal)
+__device__ __forceinline__ cpx<double> ld64_stream(const double2 *p, size_t vs, int c, int s) {
+    const f64x2 t = __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(p + c * vs + s));
+    return {t.x, t.y};
+}
+__device__ __forceinline__ void st64_stream(double2 *p, size_t vs, int c, int s, cpx<double> v) {
+    const f64x2 t = {v.re, v.im};
+    __builtin_nontemporal_store(t, reinterpret_cast<f64x2 *>(p + c * vs + s));
+}
 
 // FP64 complex entry c of an FP64 spinor (double2 planes)
 __device__ __forceinline__ cpx<double> ld64(const double2 *p, size_t vs, int c, int s) {
@@ -864,14 +913,14 @@ __global__ __launch_bounds__(kBlock) void k_r_update(Geom g, MSState S, typename
     if (s < g.V && S.status[slot] == kStatusOK) {
         const T a = (T)S.alpha[slot];
         cpx<T> rv[C], av[C];
-        Unit<T>::load(r + slot * rs, g.vs, u, s, rv);
-        Unit<T>::load(ap + slot * rs, g.vs, u, s, av);
+        Unit<T>::load_stream(r + slot * rs, g.vs, u, s, rv);
+        Unit<T>::load_stream(ap + slot * rs, g.vs, u, s, av);
 #pragma unroll
         for (int i = 0; i < C; ++i) {
             rv[i] = rv[i] - a * av[i];
             nrm += (double)rv[i].re * rv[i].re + (double)rv[i].im * rv[i].im;
         }
-        Unit<T>::store(r + slot * rs, g.vs, u, s, rv);
+        Unit<T>::store_stream(r + slot * rs, g.vs, u, s, rv);
     }
     block_partial(nrm, S.partial, (size_t)slot * S.pstride + blockIdx.x);
 }
@@ -972,14 +1021,14 @@ __global__ __launch_bounds__(kBlock) void k_shift_update(Geom g, MSState S, cons
     if (n == 0) return;
     const size_t rs = Store<T>::units * g.vs, r64 = 12 * g.vs;
     cpx<T> rv[C];
-    Unit<T>::load(r + slot * rs, g.vs, u, s, rv);
+    Unit<T>::load_stream(r + slot * rs, g.vs, u, s, rv);
     cpx<double> y64[C], x64[C];
     cpx<T> yl[C], xl[C];
     if constexpr (Y64) {
 #pragma unroll
-        for (int j = 0; j < C; ++j) y64[j] = ld64((double2 *)yt + slot * r64, g.vs, u * C + j, s);
+        for (int j = 0; j < C; ++j) y64[j] = ld64_stream((double2 *)yt + slot * r64, g.vs, u * C + j, s);
     } else {
-        Unit<T>::load((vec *)yt + slot * rs, g.vs, u, s, yl);
+        Unit<T>::load_stream((vec *)yt + slot * rs, g.vs, u, s, yl);
     }
     bool x_touched = false;
 #pragma unroll 1
@@ -989,7 +1038,7 @@ __global__ __launch_bounds__(kBlock) void k_shift_update(Geom g, MSState S, cons
         const double cy = S.upd_cy[k];
         vec *pp = p + ((size_t)slot * S.NS + i) * rs;
         cpx<T> pv[C];
-        Unit<T>::load(pp, g.vs, u, s, pv);
+        Unit<T>::load_stream(pp, g.vs, u, s, pv);
         if (cy != 0.0) {
 #pragma unroll
             for (int j = 0; j < C; ++j) {
@@ -1002,10 +1051,10 @@ __global__ __launch_bounds__(kBlock) void k_shift_update(Geom g, MSState S, cons
                 if constexpr (X64) {
 #pragma unroll
                     for (int j = 0; j < C; ++j)
-                        x64[j] = ld64((double2 *)xt + slot * r64, g.vs, u * C + j, s) +
+                        x64[j] = ld64_stream((double2 *)xt + slot * r64, g.vs, u * C + j, s) +
                                  a * cpx<double>{(double)pv[j].re, (double)pv[j].im};
                 } else {
-                    Unit<T>::load((vec *)xt + slot * rs, g.vs, u, s, xl);
+                    Unit<T>::load_stream((vec *)xt + slot * rs, g.vs, u, s, xl);
 #pragma unroll
                     for (int j = 0; j < C; ++j) xl[j] = xl[j] + (T)a * pv[j];
                 }
@@ -1015,21 +1064,21 @@ __global__ __launch_bounds__(kBlock) void k_shift_update(Geom g, MSState S, cons
             const T zn = (T)S.upd_zeta[k], bi = (T)S.upd_beta[k];
 #pragma unroll
             for (int j = 0; j < C; ++j) pv[j] = zn * rv[j] + bi * pv[j];
-            Unit<T>::store(pp, g.vs, u, s, pv);
+            Unit<T>::store_stream(pp, g.vs, u, s, pv);
         }
     }
     if constexpr (Y64) {
 #pragma unroll
-        for (int j = 0; j < C; ++j) st64((double2 *)yt + slot * r64, g.vs, u * C + j, s, y64[j]);
+        for (int j = 0; j < C; ++j) st64_stream((double2 *)yt + slot * r64, g.vs, u * C + j, s, y64[j]);
     } else {
-        Unit<T>::store((vec *)yt + slot * rs, g.vs, u, s, yl);
+        Unit<T>::store_stream((vec *)yt + slot * rs, g.vs, u, s, yl);
     }
     if (x_touched) {
         if constexpr (X64) {
 #pragma unroll
-            for (int j = 0; j < C; ++j) st64((double2 *)xt + slot * r64, g.vs, u * C + j, s, x64[j]);
+            for (int j = 0; j < C; ++j) st64_stream((double2 *)xt + slot * r64, g.vs, u * C + j, s, x64[j]);
         } else {
-            Unit<T>::store((vec *)xt + slot * rs, g.vs, u, s, xl);
+            Unit<T>::store_stream((vec *)xt + slot * rs, g.vs, u, s, xl);
         }
     }
 }
@@ -1065,19 +1114,19 @@ __global__ __launch_bounds__(kBlock) void k_fold(Geom g, Slots sl, double2 *y, f
     const size_t rs = 6 * g.vs, ys = 12 * g.vs;
     const cpx<float> z[2] = {{0.f, 0.f}, {0.f, 0.f}};
     cpx<float> a[2];
-    Unit<float>::load(yacc + slot * rs, g.vs, u, s, a);
+    Unit<float>::load_stream(yacc + slot * rs, g.vs, u, s, a);
     double2 *yp = y + slot * ys;
 #pragma unroll
     for (int j = 0; j < 2; ++j)
-        st64(yp, g.vs, 2 * u + j, s, ld64(yp, g.vs, 2 * u + j, s) + cpx<double>{(double)a[j].re, (double)a[j].im});
-    Unit<float>::store(yacc + slot * rs, g.vs, u, s, z);
+        st64_stream(yp, g.vs, 2 * u + j, s, ld64_stream(yp, g.vs, 2 * u + j, s) + cpx<double>{(double)a[j].re, (double)a[j].im});
+    Unit<float>::store_stream(yacc + slot * rs, g.vs, u, s, z);
     if (x0acc) {
-        Unit<float>::load(x0acc + slot * rs, g.vs, u, s, a);
+        Unit<float>::load_stream(x0acc + slot * rs, g.vs, u, s, a);
         double2 *xp = x0 + slot * ys;
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-            st64(xp, g.vs, 2 * u + j, s, ld64(xp, g.vs, 2 * u + j, s) + cpx<double>{(double)a[j].re, (double)a[j].im});
-        Unit<float>::store(x0acc + slot * rs, g.vs, u, s, z);
+            st64_stream(xp, g.vs, 2 * u + j, s, ld64_stream(xp, g.vs, 2 * u + j, s) + cpx<double>{(double)a[j].re, (double)a[j].im});
+        Unit<float>::store_stream(x0acc + slot * rs, g.vs, u, s, z);
     }
 }
 
