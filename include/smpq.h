@@ -222,7 +222,8 @@ smpq_status smpq_dov_locality(smpq_ctx *ctx, int64_t site, double *mean_abs, smp
  * smpq_apply_dov use
  *     eps b = sum_i w_i <u_i, b> + eps_Z(H_W) (b - sum_i u_i <u_i, b>)
  * (eps(H) = H (H^2)^(-1/2) maps u_i to w_i exactly); smpq_compute_trinv is unaffected.
- * n_modes = 0 removes the deflation.  Outputs (nullable): theta[n_modes + 1] = the deflated
+ * n_modes = 0 removes the deflation, and so do smpq_load_gauge and smpq_set_kappa (the modes
+ * belong to the previous operator).  Outputs (nullable): theta[n_modes + 1] = the deflated
  * values of H^2 ascending followed by the next Ritz value (the bottom of what the Zolotarev
  * function must cover); theta_max = the largest eigenvalue of H^2 (300 plain Lanczos steps);
  * max_resid = max_i ||H^2 u_i - theta_i u_i|| / theta_max.  With no Zolotarev coefficients set, the next q(x)

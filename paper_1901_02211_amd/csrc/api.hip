@@ -735,6 +735,13 @@ void lanczos_full(smpq_ctx *c, int steps, uint64_t seed, double2 *Qp, DevMem &w,
     beta.resize(alpha.size() - 1);
 }
 
+void drop_deflation(smpq_ctx *c) {
+    c->defl_k = 0;
+    c->defl_theta.clear();
+    c->defl_u.release();
+    c->defl_w.release();
+}
+
 // The k lowest eigenpairs of H^2 by shift-and-invert Lanczos: Lanczos on (H^2)^-1, applied
 // by an FP64 CG solve to relative residual 1e-14 (the multi-shift solver with the single
 // shift 0), turns the lowest eigenvalues theta of H^2 into the largest, best separated ones,
@@ -1174,6 +1181,7 @@ smpq_status smpq_load_gauge(smpq_ctx *c, const double *U, size_t n) {
         HIPCHK(hipMemcpy(c->U64.p, u64.data(), sizeof(double) * V * 72, hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(c->U32.p, u32.data(), sizeof(float) * V * 48, hipMemcpyHostToDevice));
         c->have_gauge = true;
+        drop_deflation(c);   // eigenvectors of the previous operator
         c->gen++;
     });
 }
@@ -1182,6 +1190,7 @@ smpq_status smpq_set_kappa(smpq_ctx *c, double kappa) {
     return guarded(c, [&] {
         if (!(kappa > 0.0 && kappa < 0.25)) throw Fail{SMPQ_EINVAL, "kappa must be in (0, 0.25)"};
         c->kappa = kappa;
+        drop_deflation(c);
         c->gen++;
     });
 }
@@ -1411,9 +1420,7 @@ smpq_status smpq_deflate(smpq_ctx *c, int n_modes, int steps, double *theta, dou
     return guarded(c, [&] {
         if (n_modes < 0 || n_modes > SMPQ_MAX_DEFLATED) throw Fail{SMPQ_EINVAL, "n_modes out of range"};
         if (n_modes == 0) {
-            c->defl_k = 0;
-            c->defl_u.release();
-            c->defl_w.release();
+            drop_deflation(c);
             c->gen++;
             return;
         }

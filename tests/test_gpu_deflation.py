@@ -73,6 +73,10 @@ def test_deflated_point_density_is_exact(rough4, prec):
     smpq.smpq_deflate(c, 0, 0)                    # removed: back to the plain result
     again, _ = smpq.smpq_compute_qx_points(c, sites)
     assert np.array_equal(again, plain)
+    smpq.smpq_deflate(c, K, 80)                   # a new gauge field drops the modes
+    smpq.smpq_load_gauge(c, U)
+    again, _ = smpq.smpq_compute_qx_points(c, sites)
+    assert np.array_equal(again, plain)
 
 
 def test_deflated_smp_classes_match_oracle(rough4):
