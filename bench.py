@@ -89,20 +89,34 @@ col, _ = colouring(lat, ({r_gap},) * 4, 0)
 b = np.zeros((lat.volume, 4, 3), dtype=np.complex128); b[col == 0, 0, 0] = 1.0
 c0, c, q, _ = zolotarev({POLES}, 0.14, 2.73)
 s = q.min()
+from oracle.dirac import apply_dw
+t0 = time.perf_counter()
+apply_dw(U, lat, {KAPPA}, b)
+t_dw = time.perf_counter() - t0
 t0 = time.perf_counter()
 try:
     multishift_cg(lambda v: apply_h2(U, lat, {KAPPA}, v) + s * v, b, q - s, {TOL}, {iters_sample})
 except NotConverged:
     pass
-print(time.perf_counter() - t0)
+print(t_dw, time.perf_counter() - t0)
 """
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
     if out.returncode != 0:
         raise RuntimeError(out.stderr)
-    t = float(out.stdout.strip().splitlines()[-1])
+    t_dw, t = (float(x) for x in out.stdout.strip().splitlines()[-1].split())
     per_iter = t / iters_sample
+    V = int(np.prod(dims))
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": per_iter * total_iters, "unit": "s/map", "cores": 1, "kind": "oracle",
+            "host_cpu": cpu_model, "host_nproc": os.cpu_count(),
+            "oracle_dw_ns_per_site": 1e9 * t_dw / V,
+            "oracle_dw_GBs": V * (72 + 48) * 8 / t_dw / 1e9,
             "sample": f"{iters_sample} multi-shift CG iterations of one r={r_gap} source on the {workload} field "
                       f"({t:.1f} s), scaled by the map's {total_iters} iterations over {n_sources} sources",
             "seconds_per_iteration": per_iter}
@@ -260,10 +274,13 @@ def main():
                 "traffic_over_algorithmic": tr["traffic_over_algorithmic"] if tr else None,
                 "launch_ms": round(mean_ms, 4), "launches": kd["launches"],
                 "algorithmic_bytes_per_launch": bytes_launch}
+    map_GBs = (st["dslash_bytes"] + st["update_bytes"]) / (st["t_solve_s"]) / 1e9
 
     ds_insitu = st["dslash_bytes"] / (st["dslash_ms"] * 1e-3) / 1e9
     trd = measured_traffic("dslash")
     print("bench: standalone stencil", file=sys.stderr, flush=True)
+    copy_ms = smpq.smpq_bench_copy(ctx, 1 << 31, 20)
+    copy_GBs = 2.0 * (1 << 31) / (copy_ms * 1e-3) / 1e9
     ms32, by32 = smpq.smpq_bench_dslash(ctx, smpq.SMPQ_MIXED_FP32, 24, 4, 50)
     ms64, by64 = smpq.smpq_bench_dslash(ctx, smpq.SMPQ_FP64, 24, 4, 50)
     dslash = {"insitu_GBs": round(ds_insitu, 1), "insitu_frac": round(ds_insitu / HBM_PEAK_GBS, 4),
@@ -322,6 +339,10 @@ def main():
                                         "f64_rhs_per_block": 1 << tuning["f64_lgr"]}},
         "speedup_vs_fp64": round(fp64["s_per_map"] / (ms_per_step / 1000.0), 3),
         "roofline": roofline, "dslash": dslash, "fp64": fp64, "accuracy": accuracy,
+        "bandwidth_context": {"device_copy_GBs": round(copy_GBs, 1),
+                              "device_copy_note": "hipMemcpyAsync device to device, 2 GiB, read + write bytes",
+                              "map_stencil_and_update_GBs": round(map_GBs, 1),
+                              "map_note": "stencil + shift-update algorithmic bytes over the whole solve time"},
         "breakdown_s": {"bounds": round(st["t_bounds_s"], 3), "solve": round(st["t_solve_s"], 3),
                         "contract": round(st["t_contract_s"], 3)},
         "iterations": {"total": st["total_iters"], "max": st["max_iters"], "reliable_updates": st["n_reliable_updates"],

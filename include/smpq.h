@@ -285,6 +285,11 @@ smpq_status smpq_compute_qx_multi(smpq_ctx *const *ctxs, int n_ctx, const int32_
                                   const int *n_classes, double *const *qx, double *const *qx_imag,
                                   smpq_stats *st, int *failed);
 
+/* Device-to-device copy of `bytes` bytes (hipMemcpyAsync between two buffers of the context's
+ * device, alternating direction), mean duration per copy over `launches` copies: the practical
+ * bandwidth ceiling (2 * bytes / time) beside the roofline figures. */
+smpq_status smpq_bench_copy(smpq_ctx *ctx, size_t bytes, int launches, double *ms_per_copy);
+
 /* Stencil variants.  f32_kind: 0 = one site per thread (f32_nr = 2, 4 or 8 right-hand sides
  * per thread, links held in registers across them); 1 = one 16x16 xy-plane per block staged
  * in LDS (nx*ny = 256; f32_nr = 4, 8 or 16); 2 = xy-tiles of ty rows plus one halo row on

@@ -21,7 +21,7 @@ __all__ = [
     "smpq_get_zolotarev", "smpq_set_solver", "smpq_set_batch", "smpq_set_scheme",
     "smpq_set_point_scheme", "smpq_get_coloring", "smpq_get_scheme_rmin", "smpq_apply_dw", "smpq_apply_dov",
     "smpq_compute_qx", "smpq_compute_qx_classes", "smpq_compute_trinv", "smpq_dov_locality", "smpq_deflate", "smpq_compute_qx_points", "smpq_prepare", "smpq_set_stream",
-    "smpq_set_timing", "smpq_set_graphs", "smpq_bench_dslash", "smpq_autotune",
+    "smpq_set_timing", "smpq_set_graphs", "smpq_bench_dslash", "smpq_bench_copy", "smpq_autotune",
     "smpq_set_tuning", "smpq_get_tuning", "smpq_set_memory_limit", "smpq_compute_qx_multi",
 ]
 
@@ -87,6 +87,7 @@ _SIG = {
     "smpq_bench_dslash": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_double_p,
                                          _c_double_p]),
     "smpq_autotune": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(SmpqTuning)]),
+    "smpq_bench_copy": (ctypes.c_int, [_vp, ctypes.c_size_t, ctypes.c_int, _c_double_p]),
     "smpq_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(SmpqTuning)]),
     "smpq_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(SmpqTuning)]),
     "smpq_set_memory_limit": (ctypes.c_int, [_vp, ctypes.c_size_t]),
@@ -394,3 +395,10 @@ def smpq_compute_qx_multi(ctxs, classes=None):
         msg = _lib.smpq_last_error(ctxs[k].ptr).decode() if 0 <= k < n else ""
         raise SmpqError(rc, f"context {k}: {msg}")
     return [(qx[k], qi[k], st[k].as_dict()) for k in range(n)]
+
+
+def smpq_bench_copy(ctx, nbytes, launches=20):
+    """Mean ms of one device-to-device copy of nbytes."""
+    ms = ctypes.c_double()
+    _check(ctx, _lib.smpq_bench_copy(ctx.ptr, int(nbytes), int(launches), ctypes.byref(ms)))
+    return ms.value

@@ -1725,6 +1725,31 @@ smpq_status smpq_bench_dslash(smpq_ctx *c, smpq_precision prec, int n_rhs, int n
     });
 }
 
+smpq_status smpq_bench_copy(smpq_ctx *c, size_t bytes, int launches, double *ms) {
+    return guarded(c, [&] {
+        if (bytes == 0 || launches < 1 || !ms) throw Fail{SMPQ_EINVAL, "bad arguments"};
+        need_device(c);
+        DevMem a, b;
+        a.ensure(bytes);
+        b.ensure(bytes);
+        HIPCHK(hipMemsetAsync(a.p, 0, bytes, c->stream));
+        HIPCHK(hipMemcpyAsync(b.p, a.p, bytes, hipMemcpyDeviceToDevice, c->stream));   // warm-up
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, c->stream));
+        for (int i = 0; i < launches; ++i)
+            HIPCHK(hipMemcpyAsync(i & 1 ? a.p : b.p, i & 1 ? b.p : a.p, bytes, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipEventRecord(e1, c->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *ms = t / launches;
+    });
+}
+
 smpq_status smpq_set_tuning(smpq_ctx *c, const smpq_tuning *t) {
     return guarded(c, [&] {
         if (!t) throw Fail{SMPQ_EINVAL, "null tuning"};
