@@ -209,3 +209,30 @@ def test_scheme_scan_special_cases():
     assert abs(rows[(2, 0)]["Q"] - _golden("noise4_smp")["qx"].sum()) < 1e-9
     assert (rows[(2, 0)]["r_min"], rows[(2, 0)]["nearest"]) == (2.0, 4)
     assert [w["n_sources"] for w in res["rows"]] == sorted(w["n_sources"] for w in res["rows"])
+
+
+def test_full_size_32x64_properties():
+    """32^3 x 64 (V = 2097152) in the benchmark's launch configuration (SMP r = 8, mixed
+    precision, a batch as large as the memory allows): the free field gives q(x) = 0 on every
+    probed site (tr_s gamma5 of the free overlap kernel vanishes), and on the noise field the
+    imaginary part of q sums to zero over each class (phi^dag eps phi is real)."""
+    dims = si.WORKLOADS["noise32x64"]["dims"]
+    print("32^3x64 free field and noise field, r = 8, three classes", flush=True)
+    classes = [0, 1111, 4095]
+    free = smpq.smpq_create(dims, 0)
+    smpq.smpq_load_gauge(free, si.near_identity_su3(dims, 0.0, 0))
+    smpq.smpq_set_zolotarev(free, 14, 0.15, 2.75)
+    smpq.smpq_set_solver(free, smpq.SMPQ_MIXED_FP32, TOL, 10000, 50)
+    smpq.smpq_set_scheme(free, (8, 8, 8, 8), 0)
+    q, qi, st = smpq.smpq_compute_qx_classes(free, classes)
+    col = smpq.smpq_get_coloring(free)
+    m = np.isin(col, classes)
+    assert st["n_sources"] == 36 and m.sum() == 3 * 512
+    assert np.abs(q[m]).max() < 1e-5 and st["max_true_resid"] <= 10 * TOL
+    del free
+    c = _ctx("noise32x64", smpq.SMPQ_MIXED_FP32)
+    smpq.smpq_set_scheme(c, (8, 8, 8, 8), 0)
+    q, qi, st = smpq.smpq_compute_qx_classes(c, classes)
+    for k in classes:
+        assert abs(qi[col == k].sum()) < 1e-5
+    assert np.abs(q[m]).max() > 1e-4          # a real field gives a non-trivial density
