@@ -11,7 +11,7 @@ FP32 with FP64 reliable updates every 50 iterations and FP64 accumulation.
 maps that take minutes are timed on a sample of classes and the value is extrapolated by
 classes/sample (labelled "extrapolated").  --workload uneven times 16^4 + 24^4 + 32^3x64
 together, the same fraction of classes of each, concurrently (one stream per lattice) and
-one after another.
+one after another; --workload ensemble does the same for eight whole 8^4 maps.
 
 Printed: one JSON line.  value = seconds per map (lower is better).  Beside it:
   roofline      the dominant kernel of the step (HIP events on the library's stream),
@@ -170,12 +170,48 @@ def uneven(args, smpq, si):
     print(json.dumps(line), flush=True)
 
 
+def ensemble(args, smpq, si):
+    """Eight 8^4 near-identity fields (eps 0.3, seeds 10-17), SMP r = 2 (192 sources each), whole
+    maps: concurrently through smpq_compute_qx_multi and one after another.  Small lattices
+    leave the GPU idle between short launches and host round trips; several contexts fill it."""
+    dims, n = (8, 8, 8, 8), 8
+    ctxs = []
+    for k in range(n):
+        c = smpq.smpq_create(dims, 0)
+        smpq.smpq_load_gauge(c, si.near_identity_su3(dims, 0.3, 10 + k))
+        smpq.smpq_set_scheme(c, (2,) * 4, 0)
+        smpq.smpq_set_solver(c, smpq.SMPQ_MIXED_FP32, TOL, 10000, RELIABLE)
+        smpq.smpq_set_zolotarev(c, POLES, *smpq.smpq_estimate_bounds(c, 300))
+        ctxs.append(c)
+    smpq.smpq_compute_qx_multi(ctxs)                 # untimed: workspaces, graphs
+    for c in ctxs:
+        smpq.smpq_compute_qx(c)
+    t0 = time.perf_counter()
+    seq = [smpq.smpq_compute_qx(c) for c in ctxs]
+    t_seq = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    par = smpq.smpq_compute_qx_multi(ctxs)
+    t_par = time.perf_counter() - t0
+    same = all(np.array_equal(a[0], b[0]) for a, b in zip(seq, par))
+    line = {
+        "metric": "sec per ensemble of eight 8^4 q(x) maps (r=2), concurrent",
+        "value": round(t_par, 4), "unit": "s/ensemble", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(1000 * t_par, 2), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "8 x 8^4 near-identity SU(3) eps=0.3 seeds 10-17, SMP normal mode r=2, mixed precision",
+                   "sources_per_map": seq[0][3]["n_sources"], "extrapolated": False},
+        "sequential_s": round(t_seq, 4), "concurrent_over_sequential": round(t_par / t_seq, 4),
+        "Q": [round(float(x[2]), 6) for x in seq], "results_identical": same,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--workload", default="noise16x32", choices=sorted(BENCH) + ["uneven"])
+    ap.add_argument("--workload", default="noise16x32", choices=sorted(BENCH) + ["uneven", "ensemble"])
     ap.add_argument("--fp64-classes", type=int, default=-1, help="classes in the FP64 comparison sample")
     ap.add_argument("--full-fp64", action="store_true", help="run the FP64 comparison as a whole map")
     ap.add_argument("--classes", type=int, default=-1,
@@ -196,6 +232,8 @@ def main():
 
     if args.workload == "uneven":
         return uneven(args, smpq, si)
+    if args.workload == "ensemble":
+        return ensemble(args, smpq, si)
     WORKLOAD = args.workload
     DIMS = si.WORKLOADS[WORKLOAD]["dims"]
     R_GAP, sample, fp64_default, desc = BENCH[WORKLOAD]
