@@ -90,6 +90,9 @@ typedef struct {
                                     sources, taken after the solve (0 in FP64)              */
 } smpq_stats;
 
+/* Environment: SMPQ_TRACE (any value) when a context is created makes it print one line per
+ * device batch to stderr (sources, CG iterations, solve time). */
+
 /* Create a context for a lattice dims[4] = {nx, ny, nz, nt} on HIP device `device`
  * (-1: host only).  kappa starts at 0.21 (section 1), the solver at FP64 with
  * tol 1e-12, max_iter 10000 and a reliable update every 50 iterations.

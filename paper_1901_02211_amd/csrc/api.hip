@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <thread>
@@ -163,6 +165,7 @@ struct smpq_ctx {
     DevMem qx, qxi, lz;
     bool timing = false;
     bool use_graphs = true;
+    bool trace = std::getenv("SMPQ_TRACE") != nullptr;   // one line per batch on stderr
     // captured groups of kGroup CG iterations, one per accumulation variant; rebuilt when
     // anything they capture (workspace, links, coefficients, solver settings) changes
     // [timed][variant]; the timed graphs carry event nodes around the stencil and update kernels
@@ -920,6 +923,9 @@ void qx_classes(smpq_ctx *c, const std::vector<int> &classes, bool point, smpq_s
                         c->defl_w.as<double2>(), c->defl_coef.as<double2>(), dk, c->stream);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(c->stream));
+        if (c->trace)
+            std::fprintf(stderr, "smpq: batch of %d sources on V = %d: %lld iterations (max %lld), %.3f s solve\n",
+                         12 * nc, c->V, r.iters_sum, r.iters_max, t1 - t0);
         if (st) {
             st->t_solve_s += t1 - t0;
             st->t_contract_s += now_s() - t1;
