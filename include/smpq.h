@@ -220,17 +220,17 @@ smpq_status smpq_dov_locality(smpq_ctx *ctx, int64_t site, double *mean_abs, smp
  * (theta_i, u_i) of H_W^2 = D_W^dag D_W by `steps` steps of shift-and-invert Lanczos: Lanczos
  * with full reorthogonalisation on (H_W^2)^-1, each application an FP64 CG solve to relative
  * residual 1e-14 (start vector from the SplitMix64 stream 1; every Lanczos vector, 192 V_pad
- * bytes, is held on the device during the call); theta_i = <u_i, H^2 u_i> of the Ritz vectors.
- * It keeps u_i and w_i = H_W u_i / sqrt(theta_i).  From then on smpq_compute_qx, _classes, _points, _multi and
- * smpq_apply_dov use
+ * bytes, is held on the device during the call); theta_i = <u_i, H^2 u_i> of the Ritz
+ * vectors.  It keeps u_i and w_i = H_W u_i / sqrt(theta_i).  From then on smpq_compute_qx,
+ * _classes, _points, _multi and smpq_apply_dov use
  *     eps b = sum_i w_i <u_i, b> + eps_Z(H_W) (b - sum_i u_i <u_i, b>)
  * (eps(H) = H (H^2)^(-1/2) maps u_i to w_i exactly); smpq_compute_trinv is unaffected.
  * n_modes = 0 removes the deflation, and so do smpq_load_gauge and smpq_set_kappa (the modes
  * belong to the previous operator).  Outputs (nullable): theta[n_modes + 1] = the deflated
  * values of H^2 ascending followed by the next Ritz value (the bottom of what the Zolotarev
  * function must cover); theta_max = the largest eigenvalue of H^2 (300 plain Lanczos steps);
- * max_resid = max_i ||H^2 u_i - theta_i u_i|| / theta_max.  With no Zolotarev coefficients set, the next q(x)
- * computation takes the interval [0.9 sqrt(theta[n_modes]), 1.02 sqrt(theta_max)].
+ * max_resid = max_i ||H^2 u_i - theta_i u_i|| / theta_max.  With no Zolotarev coefficients
+ * set, the next q(x) computation takes [0.9 sqrt(theta[n_modes]), 1.02 sqrt(theta_max)].
  * Errors: EINVAL (n_modes outside 0..SMPQ_MAX_DEFLATED, steps <= n_modes), ENUMERIC (the
  * Lanczos process ended before n_modes + 1 steps). */
 smpq_status smpq_deflate(smpq_ctx *ctx, int n_modes, int steps, double *theta, double *theta_max,
@@ -254,8 +254,10 @@ smpq_status smpq_set_stream(smpq_ctx *ctx, void *stream);
  * kernels inside the solver; results appear in smpq_stats. */
 smpq_status smpq_set_timing(smpq_ctx *ctx, int enable);
 
-/* Run each group of CG iterations as a captured HIP graph (1, the default) or as eager
- * launches (0).  Per-kernel timing (smpq_set_timing) always uses eager launches. */
+/* Run each group of 10 CG iterations as a captured HIP graph (1, the default) or as eager
+ * launches (0).  With per-kernel timing (smpq_set_timing) the graphs carry event-record
+ * nodes around the timed kernels; where the runtime cannot capture those, timed groups run
+ * eagerly. */
 smpq_status smpq_set_graphs(smpq_ctx *ctx, int enable);
 
 /* Standalone timing of the Wilson stencil: `launches` applications of D_W in the
@@ -275,8 +277,11 @@ smpq_status smpq_set_memory_limit(smpq_ctx *ctx, size_t bytes);
  * with its own scheme, coefficients and precision): the q(x) of Eq. 16 per context, as
  * smpq_compute_qx_classes.  Contexts are prepared one after another (bounds by Lanczos when
  * no coefficients were set); contexts without a memory limit then share 80% of the free
- * device memory in proportion to V x (number of classes), and every context solves on its own
- * stream from its own host thread, so the batches of different contexts overlap on the GPU.
+ * device memory: one batch of 12 right-hand sides each first, the rest in proportion to
+ * V x (number of classes), never more than a context can use (the excess goes to the
+ * others).  Every context solves on its own stream from its own host thread, so the batches
+ * of different contexts overlap on the GPU.  Results equal those of separate calls bit for
+ * bit (each source's solve is independent of the batch it runs in).
  *   ctxs[n_ctx]      distinct contexts on one device, with distinct streams, gauge and scheme set
  *   classes, n_classes  per-context class lists (NULL, or classes[k] NULL: every class)
  *   qx[k]            V_k doubles, written in full (sites of unlisted classes are 0)
