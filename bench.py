@@ -49,10 +49,15 @@ UNEVEN = ("noise16", "noise24", "noise32x64")
 
 
 def kernel_source_hash():
+    """Hash of the device code (kernels.hip and wilson_site.h without comments and blank
+    lines), so that profiles/traffic.json is used only for the kernels it was measured on."""
     h = hashlib.sha256()
     for f in ("kernels.hip", "wilson_site.h"):
-        with open(os.path.join(ROOT, "paper_1901_02211_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1901_02211_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

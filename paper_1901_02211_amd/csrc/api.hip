@@ -1,6 +1,8 @@
 // C ABI of libsmpq (include/smpq.h): context, gauge residency, Lanczos bounds,
 // Zolotarev set-up, probing schemes, and the batched multi-shift CG driver that turns
-// probing sources into q(x) (Xiong, Zhang, Zou, arXiv:1901.02211, sections 1-2).
+// probing sources into q(x) (Xiong, Zhang, Zou, arXiv:1901.02211, sections 1-2); around it
+// the stencil autotuner, concurrent contexts, low-mode deflation, the locality diagnostic and
+// the trace of D_W^-1 by the same probing (Conclusion).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

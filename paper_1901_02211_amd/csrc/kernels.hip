@@ -4,15 +4,22 @@
 //                  sides interleaved over the lanes of a block share each link fetch
 //  k_dslash_f32    the FP32 stencil: one site per thread, its eight links held in registers
 //                  for several right-hand sides (k_dslash_f32_plane: the same with one
-//                  16x16 xy-plane per block staged in LDS); all take an optional epilogue
-//                  "+ sigma aux" with a fused <aux, out> partial for H^2 + sigma (Eq. 4).
+//                  16x16 xy-plane per block staged in LDS; k_dslash_f32_tile: xy-tiles of any
+//                  width <= 64 with halo rows); all take an optional epilogue "+ sigma aux"
+//                  with a fused <aux, out> partial for H^2 + sigma (Eq. 4).
 //  k_cg_init ...   multi-shift CG for (D_W^dag D_W + q_i) x_i = b (Eqs. 6-8): residual
 //                  update, fused update of every active shift's search direction plus the
 //                  running rational sum y = c_0 b + sum_i c_i x_i, scalar recurrences on the
 //                  device (one wave per right-hand side), FP64 residual replacement.
 //  k_contract      q(x) += 1/2 [gamma5 D_ov phi](x, alpha, a) on the probed sites (Eq. 16), or
 //                  the probing estimate of tr D_W^-1 (x, x) from the unshifted solve.
+//  k_multi_dot ... low-mode deflation: many dot products and linear combinations at once
+//                  (Lanczos reorthogonalisation, Ritz vectors), deflated sources and terms.
+//  k_block_mean_abs  locality of D_ov (Eq. 12): mean |D_ov(x, . ; y, .)| per site.
 //
+// Vectors that a kernel touches once (search directions, residuals, running sums, stencil
+// outputs) use non-temporal loads and stores; stencil inputs and links stay cached, since
+// neighbouring sites and right-hand-side groups reuse them through L2.
 // Reductions are two-pass and fixed-order (per-block partials, then one wave per
 // right-hand side), so every FP64 result is bitwise reproducible from run to run.
 #include <hip/hip_runtime.h>
