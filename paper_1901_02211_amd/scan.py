@@ -9,6 +9,7 @@ of D_W^-1 (the application proposed in the Conclusion).  Every solve runs throug
 """
 import argparse
 import json
+import sys
 import time
 
 import numpy as np
@@ -41,6 +42,7 @@ def scan(U, dims, gaps=(2, 4, 8), modes=(0, 1, 2), precision=smpq.SMPQ_MIXED_FP3
     smpq.smpq_autotune(c, 48)
     t0 = time.perf_counter()
     _, n_pt = smpq.smpq_set_point_scheme(c)
+    print(f"scan: exact density from {n_pt} point sources", file=sys.stderr, flush=True)
     q_ex, _, _ = _density(c, quantity)
     Q_ex = float(q_ex.sum())
     t_ex = time.perf_counter() - t0
@@ -52,6 +54,7 @@ def scan(U, dims, gaps=(2, 4, 8), modes=(0, 1, 2), precision=smpq.SMPQ_MIXED_FP3
             except smpq.SmpqError:
                 continue            # r does not divide the lattice, or the mode's condition fails
             rmin, nearest = smpq.smpq_get_scheme_rmin(c)
+            print(f"scan: r = {r}, mode {mode}, {nsrc} sources", file=sys.stderr, flush=True)
             t0 = time.perf_counter()
             q, qi, iters = _density(c, quantity)
             Q = float(q.sum())

@@ -158,6 +158,8 @@ WORKLOADS = {
     # 4^4 and 8^4 near-identity (eps 0.3) with a Haar-random 2^4 / 3^4 block: isolated low modes
     "rough4": dict(dims=(4, 4, 4, 4), kind="rough", eps=0.3, seed=50, block=2, r=2),
     "rough8": dict(dims=(8, 8, 8, 8), kind="rough", eps=0.3, seed=60, block=3, r=(2, 4)),
+    # 12^4 (the smallest lattice of Tables 1 and 2), noise eps=0.3, seed 12, Haar gauge seed 13
+    "noise12": dict(dims=(12, 12, 12, 12), kind="noise", eps=0.3, seed=12, gauge_seed=13, r=(2, 3, 4, 6)),
     # 8^4, near-identity noise eps=0.3, seed 10 (scheme scans; Haar gauge transform seed 11 on request)
     "noise8": dict(dims=(8, 8, 8, 8), kind="noise", eps=0.3, seed=10, r=(2, 4)),
     # 8^4, U(1) flux (1,1) (Q = 2), noise eps=0.1 seed 1, Haar gauge transform seed 2;
