@@ -232,7 +232,8 @@ smpq_status smpq_dov_locality(smpq_ctx *ctx, int64_t site, double *mean_abs, smp
  * max_resid = max_i ||H^2 u_i - theta_i u_i|| / theta_max.  With no Zolotarev coefficients
  * set, the next q(x) computation takes [0.9 sqrt(theta[n_modes]), 1.02 sqrt(theta_max)].
  * Errors: EINVAL (n_modes outside 0..SMPQ_MAX_DEFLATED, steps <= n_modes), ENUMERIC (the
- * Lanczos process ended before n_modes + 1 steps). */
+ * Lanczos process ended before n_modes + 1 steps), ENOCONV (a mode's relative residual is
+ * above 1e-12 after `steps` steps: more steps are needed; no deflation is kept). */
 smpq_status smpq_deflate(smpq_ctx *ctx, int n_modes, int steps, double *theta, double *theta_max,
                          double *max_resid);
 

@@ -740,6 +740,10 @@ void lanczos_full(smpq_ctx *c, int steps, uint64_t seed, double2 *Qp, DevMem &w,
     beta.resize(alpha.size() - 1);
 }
 
+// largest relative residual ||H^2 u - theta u|| / theta_max a deflated mode may have: the
+// angle to the true eigenvector is about this times theta_max / (gap to the next eigenvalue)
+constexpr double kDeflTol = 1e-12;
+
 void drop_deflation(smpq_ctx *c) {
     c->defl_k = 0;
     c->defl_theta.clear();
@@ -835,6 +839,14 @@ void deflate(smpq_ctx *c, int k, int steps, double *theta_out, double *tmax_out,
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
+    if (!(worst <= kDeflTol)) {   // unconverged modes would bend eps: refuse them
+        drop_deflation(c);
+        char msg[160];
+        std::snprintf(msg, sizeof msg,
+                      "deflated modes not converged: residual %.2e of theta_max after %d Lanczos steps "
+                      "(needs <= %.0e; take more steps)", worst, m, kDeflTol);
+        throw Fail{SMPQ_ENOCONV, msg};
+    }
     c->defl_theta = th;
     c->defl_next = 1.0 / ev[m - 1 - k];
     c->defl_tmax = tmax_b;

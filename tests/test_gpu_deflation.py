@@ -47,10 +47,15 @@ def test_ritz_pairs_match_dense_spectrum(rough4):
     print("deflation: Lanczos Ritz pairs on rough4", flush=True)
     c = _ctx(dims, U, smpq.SMPQ_FP64, interval)
     theta, tmax, resid = smpq.smpq_deflate(c, K, 80)
+    print(f"Ritz residual {resid:.2e}", flush=True)
     assert np.abs(np.sqrt(theta[:K]) - a[:K]).max() < 1e-10
     assert abs(np.sqrt(theta[K]) - a[K]) < 1e-6
     assert abs(np.sqrt(tmax) - a[-1]) < 1e-6
     assert resid < 1e-11
+    # too few steps leave the modes unconverged: refused, and no deflation is kept
+    with pytest.raises(smpq.SmpqError) as e:
+        smpq.smpq_deflate(c, K, K + 2)
+    assert e.value.status == -5
 
 
 @pytest.mark.parametrize("prec", [smpq.SMPQ_FP64, smpq.SMPQ_MIXED_FP32])
