@@ -46,6 +46,10 @@ BENCH = {
     "rough8": (4, 0, 16, "8^4 near-identity eps=0.3 seed 60 with a Haar-random 3^4 block, SMP normal mode r=4"),
 }
 UNEVEN = ("noise16", "noise24", "noise32x64")
+# storage of the shifted search directions in the mixed path -> precision, label
+DIR_STORAGE = {"fp32": ("SMPQ_MIXED_FP32", ""),
+               "fp16": ("SMPQ_MIXED_FP16DIR", "; shifted search directions stored in FP16 (scaled)"),
+               "bf16": ("SMPQ_MIXED_BF16DIR", "; shifted search directions stored in BF16")}
 
 
 def kernel_source_hash():
@@ -225,6 +229,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=0)
     ap.add_argument("--deflate", type=int, default=0, help="deflate this many low modes of H_W^2 in each step")
     ap.add_argument("--deflate-steps", type=int, default=80)
+    ap.add_argument("--dir-storage", default="fp32", choices=sorted(DIR_STORAGE),
+                    help="storage of the shifted systems' search directions in the mixed path")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -253,7 +259,8 @@ def main():
     ctx = smpq.smpq_create(DIMS, 0)
     smpq.smpq_load_gauge(ctx, U)                    # resident in HBM before any timed region
     ncls, nsrc = smpq.smpq_set_scheme(ctx, (R_GAP,) * 4, 0)
-    smpq.smpq_set_solver(ctx, smpq.SMPQ_MIXED_FP32, TOL, 10000, RELIABLE)
+    prec_mixed = getattr(smpq, DIR_STORAGE[args.dir_storage][0])
+    smpq.smpq_set_solver(ctx, prec_mixed, TOL, 10000, RELIABLE)
     classes = list(range(ncls if args.classes == 0 else min(args.classes, ncls)))
     scale = ncls / len(classes)             # extrapolation factor of a sampled map
 
@@ -373,7 +380,8 @@ def main():
         "config": {"workload": desc,
                    "lattice": list(DIMS), "n_sources": st["n_sources"], "n_batches": st["n_batches"],
                    "kappa": KAPPA, "zolotarev_poles": POLES, "cg_tol": TOL, "reliable_interval": RELIABLE,
-                   "precision": "FP32 stencil and CG body, FP64 scalars/reliable updates/accumulation",
+                   "precision": "FP32 stencil and CG body, FP64 scalars/reliable updates/accumulation"
+                                + DIR_STORAGE[args.dir_storage][1],
                    "classes": len(classes), "classes_per_map": ncls,
                    "extrapolated": scale != 1.0,
                    "stencil_variants": {"f32_kind": ["site", "plane", "xy-tile"][tuning["f32_kind"]],

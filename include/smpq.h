@@ -58,9 +58,17 @@ typedef enum {
 
 typedef enum {
     SMPQ_FP64 = 0,       /* every vector, link and scalar in FP64                    */
-    SMPQ_MIXED_FP32 = 1  /* D_W and the CG body in FP32; FP64 CG scalars, FP64 reliable
+    SMPQ_MIXED_FP32 = 1, /* D_W and the CG body in FP32; FP64 CG scalars, FP64 reliable
                             updates of the residual, FP64 solution accumulators and
                             FP64 contraction                                          */
+    SMPQ_MIXED_FP16DIR = 2, /* SMPQ_MIXED_FP32 with the search directions of the shifted
+                            systems (all but the base system, whose direction D_W reads)
+                            stored in FP16, each divided by a per-direction FP64 scale
+                            zeta_i |r| / sqrt(24 V) that keeps its entries near 1; arithmetic
+                            stays FP32.  Halves the bytes of those directions; accuracy
+                            is measured against the FP64 oracle, not guaranteed to the
+                            SMPQ_MIXED_FP32 tolerance                                  */
+    SMPQ_MIXED_BF16DIR = 3  /* the same with BF16 storage (8-bit significand)           */
 } smpq_precision;
 
 typedef struct {
@@ -137,7 +145,7 @@ smpq_status smpq_get_zolotarev(const smpq_ctx *ctx, int *n_poles, double *c0, do
 
 /* Solver settings: precision, relative residual tol per shift (a shift stops once
  * zeta_i |r| <= tol |b|), iteration limit (ENOCONV when reached) and the interval, in
- * iterations, of FP64 residual replacement in SMPQ_MIXED_FP32.  (section 2.1, Eqs. 6-8) */
+ * iterations, of FP64 residual replacement in the mixed precisions.  (section 2.1, Eqs. 6-8) */
 smpq_status smpq_set_solver(smpq_ctx *ctx, smpq_precision prec, double tol, int max_iter,
                             int reliable_interval);
 

@@ -15,7 +15,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 __all__ = [
-    "SMPQ_FP64", "SMPQ_MIXED_FP32", "SmpqError", "SmpqStats", "SmpqTuning", "LIB_PATH", "EXPORTS",
+    "SMPQ_FP64", "SMPQ_MIXED_FP32", "SMPQ_MIXED_FP16DIR", "SMPQ_MIXED_BF16DIR", "SmpqError", "SmpqStats", "SmpqTuning", "LIB_PATH", "EXPORTS",
     "smpq_create", "smpq_destroy", "smpq_strerror", "smpq_last_error", "smpq_load_gauge",
     "smpq_set_kappa", "smpq_lanczos", "smpq_estimate_bounds", "smpq_set_zolotarev",
     "smpq_get_zolotarev", "smpq_set_solver", "smpq_set_batch", "smpq_set_scheme",
@@ -27,6 +27,8 @@ __all__ = [
 
 SMPQ_FP64 = 0
 SMPQ_MIXED_FP32 = 1
+SMPQ_MIXED_FP16DIR = 2   # FP32 body, shifted search directions stored in FP16 (scaled)
+SMPQ_MIXED_BF16DIR = 3   # the same in BF16
 _c_int_p = ctypes.POINTER(ctypes.c_int)
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p

@@ -72,7 +72,7 @@ struct DevMem {
 // Device workspace of one batch of right-hand sides.
 struct Workspace {
     int prec = -1, NS = 0, B = 0;
-    DevMem r, tmp, ap, p, y, x0, tmp64, ap64, yacc, x0acc;
+    DevMem r, tmp, ap, p, ph, y, x0, tmp64, ap64, yacc, x0acc;
     DevMem st_d;   // doubles of the MSState
     DevMem st_i;   // ints of the MSState
     DevMem st_l;   // long longs of the MSState
@@ -248,9 +248,16 @@ void spinor_from_device(const smpq_ctx *c, const std::vector<double> &stage, int
 constexpr int kGroup = 10;
 constexpr int kDirectY = 30;   // a multiple of kGroup
 
+// Internal precision codes follow smpq_precision: 0 FP64; 1 FP32 body; 2 / 3 FP32 body with
+// the shifted search directions stored in FP16 / BF16.  vec_prec is the precision of the
+// residual, the stencil and every other vector; dir_store the storage of the shifted directions.
+inline int vec_prec(int prec) { return prec == 0 ? 0 : 1; }
+inline int dir_store(int prec) { return prec == 2 ? kDirF16 : prec == 3 ? kDirBF16 : kDirF32; }
+
 size_t bytes_per_slot(const smpq_ctx *c, int prec, int NS) {
-    const size_t v64 = 12 * 16 * c->vs, v32 = 6 * 16 * c->vs;
+    const size_t v64 = 12 * 16 * c->vs, v32 = 6 * 16 * c->vs, v16 = v32 / 2;
     if (prec == 0) return (3 + NS) * v64 + v64;
+    if (dir_store(prec) != kDirF32) return 6 * v32 + NS * v16 + 4 * v64;
     return (5 + NS) * v32 + 4 * v64;
 }
 
@@ -264,7 +271,7 @@ void ensure_workspace(smpq_ctx *c, int prec, int NS, int B) {
     const size_t vt = prec == 0 ? v64 : v32;
     if (w.prec == prec && w.NS == NS && w.B >= B && w.S.rr) return;
     c->gen++;
-    w.r.release(); w.tmp.release(); w.ap.release(); w.p.release(); w.y.release();
+    w.r.release(); w.tmp.release(); w.ap.release(); w.p.release(); w.ph.release(); w.y.release();
     w.x0.release(); w.tmp64.release(); w.ap64.release(); w.yacc.release(); w.x0acc.release();
     w.prec = prec;
     w.NS = NS;
@@ -272,9 +279,14 @@ void ensure_workspace(smpq_ctx *c, int prec, int NS, int B) {
     w.r.ensure(vt * B);
     w.tmp.ensure(vt * B);
     w.ap.ensure(vt * B);
-    w.p.ensure(vt * B * NS);
+    if (dir_store(prec) != kDirF32) {
+        w.p.ensure(vt * B);              // base directions
+        w.ph.ensure(v32 / 2 * B * NS);   // shifted directions, 16 bits
+    } else {
+        w.p.ensure(vt * B * NS);
+    }
     w.y.ensure(v64 * B);
-    if (prec == 1) {
+    if (prec >= 1) {
         w.x0.ensure(v64 * B);
         w.tmp64.ensure(v64 * B);
         w.ap64.ensure(v64 * B);
@@ -282,9 +294,9 @@ void ensure_workspace(smpq_ctx *c, int prec, int NS, int B) {
         w.x0acc.ensure(v32 * B);
     }
     const size_t pstride = partial_stride(g);
-    w.st_d.ensure(sizeof(double) * ((size_t)B * (5 + 3 * NS + 3 * NS)));
+    w.st_d.ensure(sizeof(double) * ((size_t)B * (5 + 3 * NS + 3 * NS + 3 * NS)));
     w.st_i.ensure(sizeof(int) * ((size_t)B * (2 * NS + 4 + 2 * NS) + 16));
-    w.st_l.ensure(sizeof(long long) * (size_t)B * 3);
+    w.st_l.ensure(sizeof(long long) * (size_t)B * 4);
     w.partial.ensure(sizeof(double) * (size_t)B * pstride);
     w.list.ensure(sizeof(int) * B);
     w.count.ensure(sizeof(int) * 4);
@@ -304,6 +316,10 @@ void ensure_workspace(smpq_ctx *c, int prec, int NS, int B) {
     S.upd_cy = d; d += (size_t)B * NS;
     S.upd_zeta = d; d += (size_t)B * NS;
     S.upd_beta = d; d += (size_t)B * NS;
+    S.sh_scale = d; d += (size_t)B * NS;
+    S.upd_sold = d; d += (size_t)B * NS;
+    S.upd_snew = d; d += (size_t)B * NS;
+    S.dir_norm = 1.0 / std::sqrt(24.0 * (double)c->V);
     int *ip = w.st_i.as<int>();
     S.sh_active = ip; ip += (size_t)B * NS;
     S.sh_iters = ip; ip += (size_t)B * NS;
@@ -317,6 +333,7 @@ void ensure_workspace(smpq_ctx *c, int prec, int NS, int B) {
     S.cnt_entries = lp; lp += B;
     S.cnt_pupd = lp; lp += B;
     S.cnt_active = lp; lp += B;
+    S.cnt_base_pupd = lp; lp += B;
     S.partial = w.partial.as<double>();
     S.pstride = pstride;
     S.list = w.list.as<int>();
@@ -328,7 +345,7 @@ void ensure_workspace(smpq_ctx *c, int prec, int NS, int B) {
 // Free the right-hand-side vectors of the workspace (the next ensure_workspace lays it out again).
 void release_workspace(smpq_ctx *c) {
     Workspace &w = c->ws;
-    w.r.release(); w.tmp.release(); w.ap.release(); w.p.release(); w.y.release();
+    w.r.release(); w.tmp.release(); w.ap.release(); w.p.release(); w.ph.release(); w.y.release();
     w.x0.release(); w.tmp64.release(); w.ap64.release(); w.yacc.release(); w.x0acc.release();
     w.prec = -1;
     w.B = 0;
@@ -338,7 +355,7 @@ void release_workspace(smpq_ctx *c) {
 
 size_t workspace_bytes(const smpq_ctx *c) {
     const Workspace &w = c->ws;
-    return (size_t)w.r.bytes + w.tmp.bytes + w.ap.bytes + w.p.bytes + w.y.bytes + w.x0.bytes + w.tmp64.bytes +
+    return (size_t)w.r.bytes + w.tmp.bytes + w.ap.bytes + w.p.bytes + w.ph.bytes + w.y.bytes + w.x0.bytes + w.tmp64.bytes +
            w.ap64.bytes + w.yacc.bytes + w.x0acc.bytes;
 }
 
@@ -404,27 +421,29 @@ void enqueue_iteration(smpq_ctx *c, int prec, const MSState &S, bool y64, bool x
     const Geom g = c->geom();
     hipStream_t s = c->stream;
     const int NS = S.NS, B = S.B;
-    const size_t rs = (prec == 0 ? 12 : 6) * c->vs;
-    const void *U = prec == 0 ? c->U64.p : c->U32.p;
-    const int np_unit = unit_parts(prec, g), np_ds = dslash_partials(prec, g);
-    const bool mixed = prec == 1;
+    const int vp = vec_prec(prec), dir = dir_store(prec);
+    const size_t rs = (vp == 0 ? 12 : 6) * c->vs;
+    // the base direction: one of NS per slot, or (16-bit shifted directions) the only one
+    const size_t pst = dir == kDirF32 ? NS * rs : rs, pofs = dir == kDirF32 ? S.i0 * rs : 0;
+    const void *U = vp == 0 ? c->U64.p : c->U32.p;
+    const int np_unit = unit_parts(vp, g), np_ds = dslash_partials(vp, g);
+    const bool mixed = prec >= 1;
     const Slots act{S.list, S.count, 0};
     if (tm) tm->dslash.record(s, captured);
-    launch_dslash(prec, false, 0, U, w.p.p, NS * rs, S.i0 * rs, w.tmp.p, rs, nullptr, 0, 0, g, c->kappa, 0.0, act,
-                  B, nullptr, s);
+    launch_dslash(vp, false, 0, U, w.p.p, pst, pofs, w.tmp.p, rs, nullptr, 0, 0, g, c->kappa, 0.0, act, B, nullptr, s);
     if (tm) {
         tm->dslash.record(s, captured);
         tm->dslash.record(s, captured);
     }
-    launch_dslash(prec, true, 1, U, w.tmp.p, rs, 0, w.ap.p, rs, w.p.p, NS * rs, S.i0 * rs, g, c->kappa,
-                  c->coef->s0, act, B, S.partial, s);
+    launch_dslash(vp, true, 1, U, w.tmp.p, rs, 0, w.ap.p, rs, w.p.p, pst, pofs, g, c->kappa, c->coef->s0, act, B,
+                  S.partial, s);
     if (tm) tm->dslash.record(s, captured);
     launch_scalars_alpha(S, np_ds, s);
-    launch_r_update(prec, g, S, w.r.p, w.ap.p, s);
+    launch_r_update(vp, g, S, w.r.p, w.ap.p, s);
     launch_scalars_beta(S, np_unit, s);
     if (tm) tm->update.record(s, captured);
-    launch_shift_update(prec, g, S, w.r.p, w.p.p, y64 ? w.y.p : w.yacc.p, y64,
-                        mixed ? (x64 ? w.x0.p : w.x0acc.p) : nullptr, x64, s);
+    launch_shift_update(vp, g, S, w.r.p, w.p.p, y64 ? w.y.p : w.yacc.p, y64,
+                        mixed ? (x64 ? w.x0.p : w.x0acc.p) : nullptr, x64, dir, w.ph.p, s);
     if (tm) tm->update.record(s, captured);
     launch_compact(S, s);
 }
@@ -432,7 +451,7 @@ void enqueue_iteration(smpq_ctx *c, int prec, const MSState &S, bool y64, bool x
 // One group of kGroup iterations starting at iteration it0, plus the fold of the FP32 running
 // sum of y at its end when the group used it.
 void enqueue_group(smpq_ctx *c, int prec, const MSState &S, int it0, GroupTimers *tm, bool captured) {
-    const bool mixed = prec == 1;
+    const bool mixed = prec >= 1;
     const bool y64 = !mixed || it0 < kDirectY;
     const bool x64 = mixed && (c->reliable == 0 || it0 < c->reliable);
     for (int gi = 0; gi < kGroup; ++gi) enqueue_iteration(c, prec, S, y64, x64, tm, captured);
@@ -509,12 +528,13 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
     hipStream_t s = c->stream;
     const double s0 = c->coef->s0;
     const size_t rs64 = 12 * c->vs;
-    const int np_unit = unit_parts(prec, g);
+    const int vp = vec_prec(prec), dir = dir_store(prec);
+    const int np_unit = unit_parts(vp, g);
     const Slots act{S.list, S.count, 0};
-    const bool mixed = prec == 1;
+    const bool mixed = prec >= 1;
 
-    launch_cg_init(prec, g, src, nslots, NS, c->coef->c0, w.r.p, w.p.p, w.y.as<double2>(), mixed ? w.yacc.p : nullptr,
-                   mixed ? w.x0.as<double2>() : nullptr, mixed ? w.x0acc.p : nullptr, S.partial, s);
+    launch_cg_init(vp, g, src, nslots, NS, c->coef->c0, w.r.p, w.p.p, w.y.as<double2>(), mixed ? w.yacc.p : nullptr,
+                   mixed ? w.x0.as<double2>() : nullptr, mixed ? w.x0acc.p : nullptr, S.partial, dir, w.ph.p, S.i0, s);
     launch_scalars_init(S, np_unit, nslots, s);
     launch_compact(S, s);
     HIPCHK(hipGetLastError());
@@ -531,7 +551,7 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
                           c->kappa, 0.0, act, S.B, nullptr, s);
             launch_dslash(0, true, 1, c->U64.p, w.tmp64.p, rs64, 0, w.ap64.p, rs64, w.x0.p, rs64, 0, g,
                           c->kappa, s0, act, S.B, S.partial, s);
-            launch_reliable(prec, g, S, src, w.ap64.as<double2>(), w.r.p, s);
+            launch_reliable(vp, g, S, src, w.ap64.as<double2>(), w.r.p, s);
             launch_scalars_rr(S, np_unit, s);
             res.n_reliable++;
         }
@@ -563,7 +583,7 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
                       S.B, nullptr, s);
         launch_dslash(0, true, 1, c->U64.p, w.tmp64.p, rs64, 0, w.ap64.p, rs64, w.x0.p, rs64, 0, g, c->kappa, s0,
                       act, S.B, S.partial, s);
-        launch_reliable(prec, g, S, src, w.ap64.as<double2>(), w.r.p, s);
+        launch_reliable(vp, g, S, src, w.ap64.as<double2>(), w.r.p, s);
         launch_scalars_rr(S, np_unit, s);
         HIPCHK(hipGetLastError());
         std::vector<double> rr(nslots), bn(nslots);
@@ -574,12 +594,14 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
             res.max_true_resid = std::max(res.max_true_resid, std::sqrt(rr[k]) / bn[k]);
     }
     std::vector<int> status(nslots), iters(nslots);
-    std::vector<long long> ent(nslots), pup(nslots), actv(nslots);
+    std::vector<long long> ent(nslots), pup(nslots), actv(nslots), bpup(nslots);
     HIPCHK(hipMemcpy(status.data(), S.status, sizeof(int) * nslots, hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(iters.data(), S.iters, sizeof(int) * nslots, hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(ent.data(), S.cnt_entries, sizeof(long long) * nslots, hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(pup.data(), S.cnt_pupd, sizeof(long long) * nslots, hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(actv.data(), S.cnt_active, sizeof(long long) * nslots, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(bpup.data(), S.cnt_base_pupd, sizeof(long long) * nslots, hipMemcpyDeviceToHost));
+    long long base_pupd = 0;
     for (int k = 0; k < nslots; ++k) {
         if (status[k] != kStatusOK) throw Fail{SMPQ_ENUMERIC, "CG breakdown: <p, A p> <= 0 or not finite"};
         res.iters_sum += iters[k];
@@ -587,10 +609,14 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
         res.entries += ent[k];
         res.pupd += pup[k];
         res.active += actv[k];
+        base_pupd += bpup[k];
     }
     if (st) {
         const double s_t = prec == 0 ? 16.0 : 8.0;           // bytes per complex spinor entry
         const double link_site = prec == 0 ? 576.0 : 192.0;   // link bytes per site (FP32: two rows)
+        // bytes per complex entry of a listed direction: the base direction (one entry per
+        // slot-iteration) is stored like r, 16-bit shifted directions take 4
+        const double s_dir = dir == kDirF32 ? s_t : 4.0;
         const double V = c->V;
         // algorithmic bytes: D_W reads links once and each input/output spinor once; the
         // second stencil also reads p for the "+ s0 p" term.  Per active slot-iteration.
@@ -615,7 +641,9 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
                 acc_bytes += ny * 2.0 * 192.0 + (n - ny) * 2.0 * 96.0 + nx * 2.0 * 192.0 + (n - nx) * 2.0 * 96.0;
             }
         }
-        st->update_bytes += V * ((double)res.active * 12.0 * s_t + acc_bytes + (double)(res.entries + res.pupd) * 12.0 * s_t);
+        const double dir_units = (double)(res.active + base_pupd) * s_t +
+                                 (double)(res.entries - res.active + res.pupd - base_pupd) * s_dir;
+        st->update_bytes += V * ((double)res.active * 12.0 * s_t + acc_bytes + 12.0 * dir_units);
         st->update_launches += res.iters_max;
         st->n_reliable_updates += res.n_reliable;
         st->max_true_resid = std::max(st->max_true_resid, res.max_true_resid);
@@ -890,7 +918,7 @@ void auto_zolo(smpq_ctx *c, smpq_stats *st) {
 // q(x) for the listed classes of a colouring (scheme or point), written into the
 // device arrays qx/qxi (which the caller zeroes).
 void qx_classes(smpq_ctx *c, const std::vector<int> &classes, bool point, smpq_stats *st, bool inverse = false) {
-    const int prec = c->prec == SMPQ_FP64 ? 0 : 1;
+    const int prec = (int)c->prec;
     use_coef(c, inverse);
     const int NS = c->coef->n;
     const int total = (int)classes.size() * 12;
@@ -1257,7 +1285,8 @@ smpq_status smpq_get_zolotarev(const smpq_ctx *cc, int *n, double *c0, double *c
 
 smpq_status smpq_set_solver(smpq_ctx *c, smpq_precision prec, double tol, int max_iter, int reliable) {
     return guarded(c, [&] {
-        if (prec != SMPQ_FP64 && prec != SMPQ_MIXED_FP32) throw Fail{SMPQ_EINVAL, "unknown precision"};
+        if (prec != SMPQ_FP64 && prec != SMPQ_MIXED_FP32 && prec != SMPQ_MIXED_FP16DIR && prec != SMPQ_MIXED_BF16DIR)
+            throw Fail{SMPQ_EINVAL, "unknown precision"};
         if (!(tol > 0.0 && tol < 1.0)) throw Fail{SMPQ_EINVAL, "tol must be in (0, 1)"};
         if (max_iter < 1) throw Fail{SMPQ_EINVAL, "max_iter must be >= 1"};
         if (reliable < 0) throw Fail{SMPQ_EINVAL, "reliable_interval must be >= 0"};
@@ -1391,7 +1420,7 @@ smpq_status smpq_apply_dov(smpq_ctx *c, const double *in, double *out, int n) {
         if (!in || !out || n < 1) throw Fail{SMPQ_EINVAL, "need input, output and n_rhs >= 1"};
         need_device(c);
         require_gauge_zolo(c);
-        const int prec = c->prec == SMPQ_FP64 ? 0 : 1;
+        const int prec = (int)c->prec;
         use_coef(c, false);
         const int NS = c->zolo.n;
         const Geom g = c->geom();
@@ -1549,7 +1578,7 @@ smpq_status smpq_compute_qx_multi(smpq_ctx *const *ctxs, int n_ctx, const int32_
         for (int k = 0; k < n_ctx; ++k) {
             smpq_ctx *c = ctxs[k];
             if (c->mem_limit > 0 || cls[k].empty()) continue;
-            const double slot = (double)bytes_per_slot(c, c->prec == SMPQ_FP64 ? 0 : 1, c->zolo.n);
+            const double slot = (double)bytes_per_slot(c, (int)c->prec, c->zolo.n);
             slotb[k] = slot;
             share[k] = 12.0 * slot;
             cap[k] = 12.0 * (double)cls[k].size() * slot;
@@ -1584,7 +1613,7 @@ smpq_status smpq_compute_qx_multi(smpq_ctx *const *ctxs, int n_ctx, const int32_
         for (int k = 0; k < n_ctx; ++k) {
             smpq_ctx *c = ctxs[k];
             const smpq_status s = guarded(c, [&] {
-                const int prec = c->prec == SMPQ_FP64 ? 0 : 1;
+                const int prec = (int)c->prec;
                 if (cls[k].empty()) return;
                 planned[k] = choose_batch(c, prec, c->zolo.n, (int)cls[k].size() * 12, true);
                 if (c->ws.prec != prec || c->ws.NS != c->zolo.n || c->ws.B != planned[k]) release_workspace(c);
@@ -1594,7 +1623,7 @@ smpq_status smpq_compute_qx_multi(smpq_ctx *const *ctxs, int n_ctx, const int32_
         for (int k = 0; k < n_ctx; ++k) {
             smpq_ctx *c = ctxs[k];
             const smpq_status s = guarded(c, [&] {
-                if (planned[k] > 0) ensure_workspace(c, c->prec == SMPQ_FP64 ? 0 : 1, c->zolo.n, planned[k]);
+                if (planned[k] > 0) ensure_workspace(c, (int)c->prec, c->zolo.n, planned[k]);
                 if (planned[k] > 0 && c->defl_k > 0)
                     c->defl_coef.ensure(sizeof(double2) * (size_t)planned[k] * c->defl_k);
             });
@@ -1652,7 +1681,7 @@ smpq_status smpq_dov_locality(smpq_ctx *c, int64_t site, double *mean_abs, smpq_
         if (st) std::memset(st, 0, sizeof(*st));
         need_device(c);
         require_gauge_zolo(c);
-        const int prec = c->prec == SMPQ_FP64 ? 0 : 1;
+        const int prec = (int)c->prec;
         use_coef(c, false);
         ensure_point_device(c);
         ensure_workspace(c, prec, c->zolo.n, std::max(12, c->ws.prec == prec && c->ws.NS == c->zolo.n ? c->ws.B : 12));
@@ -1710,7 +1739,7 @@ smpq_status smpq_prepare(smpq_ctx *c) {
         need_device(c);
         require_gauge_zolo(c);
         if (!c->have_scheme) throw Fail{SMPQ_ESTATE, "no scheme set"};
-        const int prec = c->prec == SMPQ_FP64 ? 0 : 1;
+        const int prec = (int)c->prec;
         const int B = choose_batch(c, prec, c->zolo.n, 12 * c->n_classes, true);
         ensure_workspace(c, prec, c->zolo.n, B);
         ensure_scheme_device(c);

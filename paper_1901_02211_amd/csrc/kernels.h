@@ -44,7 +44,11 @@ struct MSState {
     int *done, *iters, *status;
     int *upd_n, *upd_idx, *upd_pupd;
     double *upd_cy, *upd_zeta, *upd_beta;
-    long long *cnt_entries, *cnt_pupd, *cnt_active;
+    // 16-bit shifted directions: p_i is stored as p_i / sh_scale[slot NS + i]; per update-list
+    // entry the scale that decodes the stored direction and the reciprocal of the new one
+    double *sh_scale, *upd_sold, *upd_snew;
+    double dir_norm;     // 1 / sqrt(24 V): a direction of norm n has entries of size ~ n dir_norm
+    long long *cnt_entries, *cnt_pupd, *cnt_active, *cnt_base_pupd;
     const double *c, *delta;
     double *partial;     // per-block partial sums, slot stride pstride
     size_t pstride;
@@ -83,9 +87,16 @@ bool valid_tuning(int prec, const Geom &g);            // g's tuning names an in
 int unit_parts(int prec, const Geom &g);        // partials per slot written by element-wise kernels
 size_t partial_stride(const Geom &g);           // slot stride of the partial buffer (>= both)
 
+// Storage of the shifted search directions p_i (i != base) in the FP32 path: FP32, or FP16 /
+// BF16 scaled by a per-direction FP64 factor (the base direction, which the stencil reads,
+// stays FP32).  With 16-bit storage, p holds only the base direction of each slot (slot
+// stride one vector) and ph the NS directions in 16 bits (the base entry unused).
+enum { kDirF32 = 0, kDirF16 = 1, kDirBF16 = 2 };
+
 // r = p_i = b, y = c0 b; FP32 path: yacc = 0, x0 = 0, x0acc = 0 (pass null otherwise)
 void launch_cg_init(int prec, const Geom &g, const Source &src, int nslots, int NS, double c0, void *r,
-                    void *p, double2 *y, void *yacc, double2 *x0, void *x0acc, double *partial, hipStream_t st);
+                    void *p, double2 *y, void *yacc, double2 *x0, void *x0acc, double *partial, int dir, void *ph,
+                    int i0, hipStream_t st);
 void launch_scalars_init(const MSState &s, int npart, int nslots, hipStream_t st);
 void launch_scalars_alpha(const MSState &s, int npart, hipStream_t st);
 void launch_r_update(int prec, const Geom &g, const MSState &s, void *r, const void *ap, hipStream_t st);
@@ -94,7 +105,7 @@ void launch_scalars_beta(const MSState &s, int npart, hipStream_t st);
 // the storage precision of p.  xt (FP32 path only, else null) receives alpha p_base: the FP64
 // x0 when x64, else a running sum.  The FP64 path always uses y64 (and no xt).
 void launch_shift_update(int prec, const Geom &g, const MSState &s, const void *r, void *p, void *yt, bool y64,
-                         void *xt, bool x64, hipStream_t st);
+                         void *xt, bool x64, int dir, void *ph, hipStream_t st);
 // FP32 path: y += yacc, yacc = 0 (and x0 += x0acc, x0acc = 0 when x0acc is not null)
 void launch_fold(const Geom &g, Slots sl, int max_slots, double2 *y, void *yacc, double2 *x0, void *x0acc,
                  hipStream_t st);

@@ -757,6 +757,36 @@ __device__ __forceinline__ void st64_stream(double2 *p, size_t vs, int c, int s,
     __builtin_nontemporal_store(t, reinterpret_cast<f64x2 *>(p + c * vs + s));
 }
 
+// A shifted search direction in 16 bits: one FP32 unit (4 reals) in 8 bytes, holding p / scale.
+// Conversions round to nearest even (v_cvt_pk_f16_f32 / v_cvt_pk_bf16_f32 on gfx950).
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+template <int D>
+struct Dir16;
+template <>
+struct Dir16<kDirF16> {
+    using v = f16x4;
+};
+template <>
+struct Dir16<kDirBF16> {
+    using v = bf16x4;
+};
+
+template <int D>
+__device__ __forceinline__ void load_dir16(const void *p, size_t vs, int u, int s, float scale, cpx<float> v[2]) {
+    using h = typename Dir16<D>::v;
+    const h t = __builtin_nontemporal_load(reinterpret_cast<const h *>(p) + u * vs + s);
+    const f32x4 f = __builtin_convertvector(t, f32x4);
+    v[0] = {f.x * scale, f.y * scale};
+    v[1] = {f.z * scale, f.w * scale};
+}
+template <int D>
+__device__ __forceinline__ void store_dir16(void *p, size_t vs, int u, int s, float inv_scale, const cpx<float> v[2]) {
+    using h = typename Dir16<D>::v;
+    const f32x4 f = {v[0].re * inv_scale, v[0].im * inv_scale, v[1].re * inv_scale, v[1].im * inv_scale};
+    __builtin_nontemporal_store(__builtin_convertvector(f, h), reinterpret_cast<h *>(p) + u * vs + s);
+}
+
 // FP64 complex entry c of an FP64 spinor (double2 planes)
 __device__ __forceinline__ cpx<double> ld64(const double2 *p, size_t vs, int c, int s) {
     const double2 t = p[c * vs + s];
@@ -803,11 +833,12 @@ int unit_parts(int prec, const Geom &g) { return (prec == 0 ? 12 : 6) * site_blo
 // r = b, p_i = b for every shift, y = c0 b (FP64), running accumulators yacc = x0acc = 0 in the
 // iteration precision (FP32 path only; the FP64 path accumulates into y directly and has no x0);
 // partial = |b|^2 per block.
-template <class T>
+template <class T, int D>
 __global__ __launch_bounds__(kBlock) void k_cg_init(Geom g, Source src, int NS, double c0,
                                                     typename Store<T>::vec *r, typename Store<T>::vec *p, double2 *y,
                                                     typename Store<T>::vec *yacc, double2 *x0,
-                                                    typename Store<T>::vec *x0acc, double *partial, size_t pstride) {
+                                                    typename Store<T>::vec *x0acc, double *partial, size_t pstride,
+                                                    void *ph, int i0) {
     constexpr int C = Unit<T>::C;
     const int slot = blockIdx.y;
     const int nsb = site_blocks(g);
@@ -829,7 +860,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(Geom g, Source src, int NS, 
             if (x0) st64(x0 + (size_t)slot * 12 * g.vs, g.vs, c, s, {0.0, 0.0});
         }
         Unit<T>::store(r + slot * rs, g.vs, u, s, bt);
-        for (int i = 0; i < NS; ++i) Unit<T>::store(p + ((size_t)slot * NS + i) * rs, g.vs, u, s, bt);
+        if constexpr (D == kDirF32) {
+            for (int i = 0; i < NS; ++i) Unit<T>::store(p + ((size_t)slot * NS + i) * rs, g.vs, u, s, bt);
+        } else {
+            // base direction in FP32, the others in 16 bits with scale 1
+            Unit<T>::store(p + slot * rs, g.vs, u, s, bt);
+            for (int i = 0; i < NS; ++i)
+                if (i != i0)
+                    store_dir16<D>(static_cast<typename Dir16<D>::v *>(ph) + ((size_t)slot * NS + i) * rs, g.vs, u,
+                                   s, 1.0f, bt);
+        }
         if (yacc) Unit<T>::store(yacc + slot * rs, g.vs, u, s, z);
         if (x0acc) Unit<T>::store(x0acc + slot * rs, g.vs, u, s, z);
     }
@@ -837,14 +877,22 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(Geom g, Source src, int NS, 
 }
 
 void launch_cg_init(int prec, const Geom &g, const Source &src, int nslots, int NS, double c0, void *r, void *p,
-                    double2 *y, void *yacc, double2 *x0, void *x0acc, double *partial, hipStream_t st) {
+                    double2 *y, void *yacc, double2 *x0, void *x0acc, double *partial, int dir, void *ph, int i0,
+                    hipStream_t st) {
     dim3 grid(unit_parts(prec, g), nslots);
-    if (prec == 0)
-        hipLaunchKernelGGL(k_cg_init<double>, grid, dim3(kBlock), 0, st, g, src, NS, c0, (double2 *)r, (double2 *)p, y,
-                           (double2 *)yacc, x0, (double2 *)x0acc, partial, partial_stride(g));
-    else
-        hipLaunchKernelGGL(k_cg_init<float>, grid, dim3(kBlock), 0, st, g, src, NS, c0, (float4 *)r, (float4 *)p, y,
-                           (float4 *)yacc, x0, (float4 *)x0acc, partial, partial_stride(g));
+    if (prec == 0) {
+        if (dir != kDirF32) throw std::invalid_argument("16-bit directions need the FP32 path");
+        hipLaunchKernelGGL((k_cg_init<double, kDirF32>), grid, dim3(kBlock), 0, st, g, src, NS, c0, (double2 *)r,
+                           (double2 *)p, y, (double2 *)yacc, x0, (double2 *)x0acc, partial, partial_stride(g), ph, i0);
+        return;
+    }
+#define SMPQ_CI(D)                                                                                                 \
+    hipLaunchKernelGGL((k_cg_init<float, D>), grid, dim3(kBlock), 0, st, g, src, NS, c0, (float4 *)r, (float4 *)p, y, \
+                       (float4 *)yacc, x0, (float4 *)x0acc, partial, partial_stride(g), ph, i0)
+    if (dir == kDirF16) SMPQ_CI(kDirF16);
+    else if (dir == kDirBF16) SMPQ_CI(kDirBF16);
+    else SMPQ_CI(kDirF32);
+#undef SMPQ_CI
 }
 
 // ------------------------------------------------------------------ CG scalars (one wave per slot)
@@ -865,6 +913,7 @@ __global__ void k_scalars_init(MSState S, int npart, int nslots) {
         S.zeta_new[k] = 1.0;
         S.sh_active[k] = rr > 0.0;
         S.sh_iters[k] = 0;
+        S.sh_scale[k] = 1.0;
     }
     S.done[slot] = !(rr > 0.0);
     S.iters[slot] = 0;
@@ -873,6 +922,7 @@ __global__ void k_scalars_init(MSState S, int npart, int nslots) {
     S.cnt_entries[slot] = 0;
     S.cnt_pupd[slot] = 0;
     S.cnt_active[slot] = 0;
+    S.cnt_base_pupd[slot] = 0;
 }
 
 void launch_scalars_init(const MSState &s, int npart, int nslots, hipStream_t st) {
@@ -993,7 +1043,23 @@ __global__ void k_scalars_beta(MSState S, int npart) {
         for (int e = 0; e < n; ++e) S.upd_pupd[slot * S.NS + e] = 0;
         S.done[slot] = 1;
     }
-    for (int e = 0; e < n; ++e) npupd += S.upd_pupd[slot * S.NS + e];
+    // 16-bit directions: the stored p_i is decoded with its current scale and the new one is
+    // stored divided by zeta^i_{k+1} |r_{k+1}| dir_norm, which keeps its entries near 1
+    for (int e = 0; e < n; ++e) {
+        const int u = slot * S.NS + e;
+        const int k = slot * S.NS + S.upd_idx[u];
+        S.upd_sold[u] = S.sh_scale[k];
+        if (S.upd_pupd[u]) {
+            double sc = S.upd_zeta[u] * rn * S.dir_norm;
+            if (!(sc > 0.0) || !isfinite(sc)) sc = S.sh_scale[k];
+            S.sh_scale[k] = sc;
+            S.upd_snew[u] = 1.0 / sc;
+            npupd++;
+            if (S.upd_idx[u] == S.i0) S.cnt_base_pupd[slot] += 1;
+        } else {
+            S.upd_snew[u] = 1.0;
+        }
+    }
     S.upd_n[slot] = n;
     S.cnt_entries[slot] += n;
     S.cnt_pupd[slot] += npupd;
@@ -1012,10 +1078,11 @@ void launch_scalars_beta(const MSState &s, int npart, hipStream_t st) {
 // p_i = zeta^i r + beta^i p_i; x0 += alpha p_base where an x0 target is given (FP32 path).
 // The sums go either straight into the FP64 vectors (Y64 / X64) or into running sums in the
 // storage precision of p, which k_fold adds to FP64 every few iterations.  The FP64 path
-// always accumulates into y directly.
-template <class T, bool Y64, bool X64>
+// always accumulates into y directly.  D: storage of the shifted directions (kDirF32: all NS
+// directions in p; 16-bit: the base in p, slot stride one vector, the others scaled in ph).
+template <class T, bool Y64, bool X64, int D>
 __global__ __launch_bounds__(kBlock) void k_shift_update(Geom g, MSState S, const typename Store<T>::vec *r,
-                                                         typename Store<T>::vec *p, void *yt, void *xt) {
+                                                         typename Store<T>::vec *p, void *yt, void *xt, void *ph) {
     using vec = typename Store<T>::vec;
     constexpr int C = Unit<T>::C;
     if ((int)blockIdx.y >= *S.count) return;
@@ -1043,9 +1110,16 @@ __global__ __launch_bounds__(kBlock) void k_shift_update(Geom g, MSState S, cons
         const int k = slot * S.NS + e;
         const int i = S.upd_idx[k];
         const double cy = S.upd_cy[k];
-        vec *pp = p + ((size_t)slot * S.NS + i) * rs;
+        const bool full = D == kDirF32 || i == S.i0;   // this direction is stored in T
+        vec *pp = D == kDirF32 ? p + ((size_t)slot * S.NS + i) * rs : p + slot * rs;
         cpx<T> pv[C];
-        Unit<T>::load_stream(pp, g.vs, u, s, pv);
+        if constexpr (D == kDirF32) {
+            Unit<T>::load_stream(pp, g.vs, u, s, pv);
+        } else {
+            if (full) Unit<T>::load_stream(pp, g.vs, u, s, pv);
+            else load_dir16<D>(static_cast<typename Dir16<D>::v *>(ph) + ((size_t)slot * S.NS + i) * rs, g.vs, u, s,
+                               (float)S.upd_sold[k], pv);
+        }
         if (cy != 0.0) {
 #pragma unroll
             for (int j = 0; j < C; ++j) {
@@ -1071,7 +1145,13 @@ __global__ __launch_bounds__(kBlock) void k_shift_update(Geom g, MSState S, cons
             const T zn = (T)S.upd_zeta[k], bi = (T)S.upd_beta[k];
 #pragma unroll
             for (int j = 0; j < C; ++j) pv[j] = zn * rv[j] + bi * pv[j];
-            Unit<T>::store_stream(pp, g.vs, u, s, pv);
+            if constexpr (D == kDirF32) {
+                Unit<T>::store_stream(pp, g.vs, u, s, pv);
+            } else {
+                if (full) Unit<T>::store_stream(pp, g.vs, u, s, pv);
+                else store_dir16<D>(static_cast<typename Dir16<D>::v *>(ph) + ((size_t)slot * S.NS + i) * rs, g.vs,
+                                    u, s, (float)S.upd_snew[k], pv);
+            }
         }
     }
     if constexpr (Y64) {
@@ -1091,20 +1171,30 @@ __global__ __launch_bounds__(kBlock) void k_shift_update(Geom g, MSState S, cons
 }
 
 void launch_shift_update(int prec, const Geom &g, const MSState &s, const void *r, void *p, void *yt, bool y64,
-                         void *xt, bool x64, hipStream_t st) {
+                         void *xt, bool x64, int dir, void *ph, hipStream_t st) {
     dim3 grid(unit_parts(prec, g), s.B);
     if (prec == 0) {
-        hipLaunchKernelGGL((k_shift_update<double, true, true>), grid, dim3(kBlock), 0, st, g, s, (const double2 *)r,
-                           (double2 *)p, yt, xt);
+        if (dir != kDirF32) throw std::invalid_argument("16-bit directions need the FP32 path");
+        hipLaunchKernelGGL((k_shift_update<double, true, true, kDirF32>), grid, dim3(kBlock), 0, st, g, s,
+                           (const double2 *)r, (double2 *)p, yt, xt, ph);
         return;
     }
-#define SMPQ_SU(Y, X)                                                                                           \
-    hipLaunchKernelGGL((k_shift_update<float, Y, X>), grid, dim3(kBlock), 0, st, g, s, (const float4 *)r, (float4 *)p, \
-                       yt, xt)
-    if (y64 && x64) SMPQ_SU(true, true);
-    else if (y64) SMPQ_SU(true, false);
-    else if (x64) SMPQ_SU(false, true);
-    else SMPQ_SU(false, false);
+#define SMPQ_SU(Y, X, D)                                                                                          \
+    hipLaunchKernelGGL((k_shift_update<float, Y, X, D>), grid, dim3(kBlock), 0, st, g, s, (const float4 *)r,        \
+                       (float4 *)p, yt, xt, ph)
+#define SMPQ_SU_D(D)                     \
+    if (y64 && x64) SMPQ_SU(true, true, D); \
+    else if (y64) SMPQ_SU(true, false, D);  \
+    else if (x64) SMPQ_SU(false, true, D);  \
+    else SMPQ_SU(false, false, D)
+    if (dir == kDirF16) {
+        SMPQ_SU_D(kDirF16);
+    } else if (dir == kDirBF16) {
+        SMPQ_SU_D(kDirBF16);
+    } else {
+        SMPQ_SU_D(kDirF32);
+    }
+#undef SMPQ_SU_D
 #undef SMPQ_SU
 }
 

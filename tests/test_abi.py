@@ -104,8 +104,11 @@ def test_argument_errors():
         smpq.smpq_set_zolotarev(c, 0, 0.1, 1.0)
     with pytest.raises(smpq.SmpqError):
         smpq.smpq_set_solver(c, smpq.SMPQ_FP64, 0.0, 10, 0)
-    with pytest.raises(smpq.SmpqError):
-        smpq.smpq_set_solver(c, 5, 1e-12, 10, 0)
+    for bad in (4, 5, -1):
+        with pytest.raises(smpq.SmpqError):
+            smpq.smpq_set_solver(c, bad, 1e-12, 10, 0)
+    for ok in (smpq.SMPQ_MIXED_FP16DIR, smpq.SMPQ_MIXED_BF16DIR, smpq.SMPQ_FP64):
+        smpq.smpq_set_solver(c, ok, 1e-12, 10, 0)
     V = 4 * 4 * 4 * 6
     U = np.zeros((V, 4, 3, 3), dtype=complex)
     U[:] = np.eye(3)

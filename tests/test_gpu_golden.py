@@ -84,6 +84,29 @@ def test_flux8_smp_full_map(prec):
     assert abs(Q - g["qx"].sum()) < (1e-9 if prec == smpq.SMPQ_FP64 else 1e-4)
 
 
+@pytest.mark.parametrize("prec, bound, qbound", [(smpq.SMPQ_MIXED_FP16DIR, 2e-3, 0.1),
+                                                 (smpq.SMPQ_MIXED_BF16DIR, 1e-2, 0.3)])
+def test_flux8_dir16_storage(prec, bound, qbound):
+    """Shifted search directions stored in 16 bits: the base systems run exactly as in the FP32
+    path (same iteration counts, FP64 true residual at the tolerance) and q(x) carries the
+    storage's rounding, bounded here (measured: max |dq| 1e-4 / 5e-4 and dQ 0.02 / 0.06 for
+    FP16 / BF16 on this map) but far outside the FP32 path's 1e-5 and 1e-4."""
+    print(f"flux8 SMP r=2 full map, 16-bit shifted directions, precision {prec}", flush=True)
+    g = _golden("flux8_smp2")
+    ref = _ctx("flux8", smpq.SMPQ_MIXED_FP32)
+    smpq.smpq_set_scheme(ref, (2, 2, 2, 2), 0)
+    _, _, _, st32 = smpq.smpq_compute_qx(ref)
+    c = _ctx("flux8", prec)
+    smpq.smpq_set_scheme(c, (2, 2, 2, 2), 0)
+    q, qi, Q, st = smpq.smpq_compute_qx(c)
+    assert st["total_iters"] == st32["total_iters"]
+    assert 0.0 < st["max_true_resid"] <= 10 * TOL
+    err = np.abs(q - g["qx"]).max()
+    assert np.isfinite(err) and err < bound
+    assert np.abs(qi - g["qx_imag"]).max() < bound
+    assert abs(Q - g["qx"].sum()) < qbound
+
+
 def test_flux8_point_subset():
     print("flux8 point sources on the 64-site subset", flush=True)
     g = _golden("flux8_point")
