@@ -289,7 +289,7 @@ def main():
 
     # untimed set-up: workspace allocation and first launches of every kernel
     smpq.smpq_set_zolotarev(ctx, POLES, 0.14, 2.73)
-    tuning = smpq.smpq_autotune(ctx, 96)
+    tuning = smpq.smpq_autotune(ctx, 0)            # at the map's batch size
     print(f"bench: stencil variants {tuning}", file=sys.stderr, flush=True)
     smpq.smpq_prepare(ctx)
     smpq.smpq_compute_qx_classes(ctx, [0])

@@ -323,7 +323,9 @@ typedef struct {
 /* Choose the variants for this lattice by timing each on n_rhs right-hand sides as the solver
  * uses it: D_W followed by D_W^dag with the +sigma term and its partial sums (two rotating
  * buffer sets, 10 pairs, best of two runs; fewer right-hand sides where they would take more
- * than half of the free device memory).  The choice is kept by the context and written to
+ * than half of the free device memory).  n_rhs = 0 times the batch size that a whole q(x)
+ * map of the current scheme, coefficients and precision would use (ESTATE without them):
+ * the variants' order can change with the number of right-hand sides through L2 reuse.  The choice is kept by the context and written to
  * *chosen (may be NULL); on an error the previous choice is kept.  Without this call a
  * context uses kind 1 / 8 where the plane fits, else kind 2 / 8 where a tile fits, else kind
  * 0 / 4, with plane_band 1 and f64_lgr 1. */

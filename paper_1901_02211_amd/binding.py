@@ -345,7 +345,8 @@ def smpq_bench_dslash(ctx, precision, n_rhs, n_sets, launches):
 
 
 def smpq_autotune(ctx, n_rhs=48):
-    """Times the stencil variants on this lattice; returns the chosen ones as a dict."""
+    """Times the stencil variants on this lattice; returns the chosen ones as a dict.
+    n_rhs = 0 times them on the batch a whole map of the current scheme would use."""
     t = SmpqTuning()
     _check(ctx, _lib.smpq_autotune(ctx.ptr, int(n_rhs), ctypes.byref(t)))
     return t.as_dict()

@@ -1826,9 +1826,14 @@ smpq_status smpq_get_tuning(smpq_ctx *c, smpq_tuning *t) {
 
 smpq_status smpq_autotune(smpq_ctx *c, int n_rhs, smpq_tuning *chosen) {
     return guarded(c, [&] {
-        if (n_rhs < 1) throw Fail{SMPQ_EINVAL, "n_rhs must be >= 1"};
+        if (n_rhs < 0) throw Fail{SMPQ_EINVAL, "n_rhs must be >= 0"};
         need_device(c);
         if (!c->have_gauge) throw Fail{SMPQ_ESTATE, "no gauge field loaded"};
+        if (n_rhs == 0) {   // the batch a whole q(x) map of the current scheme would use
+            if (c->n_classes == 0) throw Fail{SMPQ_ESTATE, "n_rhs = 0 needs a probing scheme"};
+            if (!c->have_zolo) throw Fail{SMPQ_ESTATE, "n_rhs = 0 needs the Zolotarev coefficients"};
+            n_rhs = choose_batch(c, (int)c->prec, c->zolo.n, 12 * c->n_classes, true);
+        }
         double by;
         struct Cand {
             int kind, nr, band;

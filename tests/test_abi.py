@@ -104,6 +104,9 @@ def test_argument_errors():
         smpq.smpq_set_zolotarev(c, 0, 0.1, 1.0)
     with pytest.raises(smpq.SmpqError):
         smpq.smpq_set_solver(c, smpq.SMPQ_FP64, 0.0, 10, 0)
+    with pytest.raises(smpq.SmpqError) as e:
+        smpq.smpq_autotune(c, -1)
+    assert e.value.status == -1
     for bad in (4, 5, -1):
         with pytest.raises(smpq.SmpqError):
             smpq.smpq_set_solver(c, bad, 1e-12, 10, 0)

@@ -101,6 +101,16 @@ def test_autotune_picks_a_valid_variant_and_keeps_parity():
     assert np.abs(out32 - ref).max() <= 2e-6 * np.abs(ref).max()
     out64 = smpq.smpq_apply_dw(c, psi, precision=smpq.SMPQ_FP64)
     assert np.abs(out64 - ref).max() <= 1e-13 * np.abs(ref).max()
+    # n_rhs = 0: timed on the batch a whole map would use, which needs a scheme and coefficients
+    with pytest.raises(smpq.SmpqError) as e:
+        smpq.smpq_autotune(c, 0)
+    assert e.value.status == -6
+    smpq.smpq_set_scheme(c, (2, 2, 2, 2), 0)
+    smpq.smpq_set_zolotarev(c, 14, 0.15, 2.75)
+    t0 = smpq.smpq_autotune(c, 0)
+    assert (t0["f32_kind"], t0["f32_nr"]) in [(k, n) for k, n, _ in SITE_VARIANTS + PLANE_VARIANTS + TILE_VARIANTS]
+    out32 = smpq.smpq_apply_dw(c, psi, precision=smpq.SMPQ_MIXED_FP32)
+    assert np.abs(out32 - ref).max() <= 2e-6 * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("dims", [(24, 16, 2, 2), (32, 16, 4, 3), (8, 64, 2, 2)])
