@@ -534,8 +534,9 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
     const bool mixed = prec >= 1;
 
     launch_cg_init(vp, g, src, nslots, NS, c->coef->c0, w.r.p, w.p.p, w.y.as<double2>(), mixed ? w.yacc.p : nullptr,
-                   mixed ? w.x0.as<double2>() : nullptr, mixed ? w.x0acc.p : nullptr, S.partial, dir, w.ph.p, S.i0, s);
+                   mixed ? w.x0.as<double2>() : nullptr, mixed ? w.x0acc.p : nullptr, S.partial, dir, s);
     launch_scalars_init(S, np_unit, nslots, s);
+    if (dir != kDirF32) launch_dir16_init(g, S, nslots, w.r.p, dir, w.ph.p, s);
     launch_compact(S, s);
     HIPCHK(hipGetLastError());
 

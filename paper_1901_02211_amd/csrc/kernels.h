@@ -93,10 +93,13 @@ size_t partial_stride(const Geom &g);           // slot stride of the partial bu
 // stride one vector) and ph the NS directions in 16 bits (the base entry unused).
 enum { kDirF32 = 0, kDirF16 = 1, kDirBF16 = 2 };
 
-// r = p_i = b, y = c0 b; FP32 path: yacc = 0, x0 = 0, x0acc = 0 (pass null otherwise)
+// r = p_i = b, y = c0 b; FP32 path: yacc = 0, x0 = 0, x0acc = 0 (pass null otherwise).  With
+// 16-bit directions only r and the base direction are written; launch_dir16_init writes the
+// others after launch_scalars_init has set their scales from |b|.
 void launch_cg_init(int prec, const Geom &g, const Source &src, int nslots, int NS, double c0, void *r,
-                    void *p, double2 *y, void *yacc, double2 *x0, void *x0acc, double *partial, int dir, void *ph,
-                    int i0, hipStream_t st);
+                    void *p, double2 *y, void *yacc, double2 *x0, void *x0acc, double *partial, int dir,
+                    hipStream_t st);
+void launch_dir16_init(const Geom &g, const MSState &s, int nslots, const void *r, int dir, void *ph, hipStream_t st);
 void launch_scalars_init(const MSState &s, int npart, int nslots, hipStream_t st);
 void launch_scalars_alpha(const MSState &s, int npart, hipStream_t st);
 void launch_r_update(int prec, const Geom &g, const MSState &s, void *r, const void *ap, hipStream_t st);

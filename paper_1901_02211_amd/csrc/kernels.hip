@@ -837,8 +837,7 @@ template <class T, int D>
 __global__ __launch_bounds__(kBlock) void k_cg_init(Geom g, Source src, int NS, double c0,
                                                     typename Store<T>::vec *r, typename Store<T>::vec *p, double2 *y,
                                                     typename Store<T>::vec *yacc, double2 *x0,
-                                                    typename Store<T>::vec *x0acc, double *partial, size_t pstride,
-                                                    void *ph, int i0) {
+                                                    typename Store<T>::vec *x0acc, double *partial, size_t pstride) {
     constexpr int C = Unit<T>::C;
     const int slot = blockIdx.y;
     const int nsb = site_blocks(g);
@@ -863,12 +862,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(Geom g, Source src, int NS, 
         if constexpr (D == kDirF32) {
             for (int i = 0; i < NS; ++i) Unit<T>::store(p + ((size_t)slot * NS + i) * rs, g.vs, u, s, bt);
         } else {
-            // base direction in FP32, the others in 16 bits with scale 1
+            // the base direction; the 16-bit ones follow from r once |b| is known (k_dir16_init)
             Unit<T>::store(p + slot * rs, g.vs, u, s, bt);
-            for (int i = 0; i < NS; ++i)
-                if (i != i0)
-                    store_dir16<D>(static_cast<typename Dir16<D>::v *>(ph) + ((size_t)slot * NS + i) * rs, g.vs, u,
-                                   s, 1.0f, bt);
         }
         if (yacc) Unit<T>::store(yacc + slot * rs, g.vs, u, s, z);
         if (x0acc) Unit<T>::store(x0acc + slot * rs, g.vs, u, s, z);
@@ -877,22 +872,48 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(Geom g, Source src, int NS, 
 }
 
 void launch_cg_init(int prec, const Geom &g, const Source &src, int nslots, int NS, double c0, void *r, void *p,
-                    double2 *y, void *yacc, double2 *x0, void *x0acc, double *partial, int dir, void *ph, int i0,
-                    hipStream_t st) {
+                    double2 *y, void *yacc, double2 *x0, void *x0acc, double *partial, int dir, hipStream_t st) {
     dim3 grid(unit_parts(prec, g), nslots);
     if (prec == 0) {
         if (dir != kDirF32) throw std::invalid_argument("16-bit directions need the FP32 path");
         hipLaunchKernelGGL((k_cg_init<double, kDirF32>), grid, dim3(kBlock), 0, st, g, src, NS, c0, (double2 *)r,
-                           (double2 *)p, y, (double2 *)yacc, x0, (double2 *)x0acc, partial, partial_stride(g), ph, i0);
+                           (double2 *)p, y, (double2 *)yacc, x0, (double2 *)x0acc, partial, partial_stride(g));
         return;
     }
-#define SMPQ_CI(D)                                                                                                 \
-    hipLaunchKernelGGL((k_cg_init<float, D>), grid, dim3(kBlock), 0, st, g, src, NS, c0, (float4 *)r, (float4 *)p, y, \
-                       (float4 *)yacc, x0, (float4 *)x0acc, partial, partial_stride(g), ph, i0)
-    if (dir == kDirF16) SMPQ_CI(kDirF16);
-    else if (dir == kDirBF16) SMPQ_CI(kDirBF16);
-    else SMPQ_CI(kDirF32);
-#undef SMPQ_CI
+    if (dir == kDirF32)
+        hipLaunchKernelGGL((k_cg_init<float, kDirF32>), grid, dim3(kBlock), 0, st, g, src, NS, c0, (float4 *)r,
+                           (float4 *)p, y, (float4 *)yacc, x0, (float4 *)x0acc, partial, partial_stride(g));
+    else   // only the base direction's layout depends on the 16-bit format
+        hipLaunchKernelGGL((k_cg_init<float, kDirF16>), grid, dim3(kBlock), 0, st, g, src, NS, c0, (float4 *)r,
+                           (float4 *)p, y, (float4 *)yacc, x0, (float4 *)x0acc, partial, partial_stride(g));
+}
+
+// 16-bit directions: p_i = b = r for every shift but the base, stored with the scale that
+// k_scalars_init set from |b| (so that the entries of any source are near 1).
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_dir16_init(Geom g, MSState S, const float4 *r, void *ph) {
+    const int slot = blockIdx.y;
+    const int nsb = site_blocks(g);
+    const int u = blockIdx.x / nsb;
+    const int s = (blockIdx.x % nsb) * kBlock + threadIdx.x;
+    if (s >= g.V) return;
+    const size_t rs = Store<float>::units * g.vs;
+    cpx<float> v[2];
+    Unit<float>::load(r + slot * rs, g.vs, u, s, v);
+    for (int i = 0; i < S.NS; ++i)
+        if (i != S.i0)
+            store_dir16<D>(static_cast<typename Dir16<D>::v *>(ph) + ((size_t)slot * S.NS + i) * rs, g.vs, u, s,
+                           (float)(1.0 / S.sh_scale[slot * S.NS + i]), v);
+}
+
+void launch_dir16_init(const Geom &g, const MSState &s, int nslots, const void *r, int dir, void *ph, hipStream_t st) {
+    dim3 grid(unit_parts(1, g), nslots);
+    if (dir == kDirF16)
+        hipLaunchKernelGGL(k_dir16_init<kDirF16>, grid, dim3(kBlock), 0, st, g, s, (const float4 *)r, ph);
+    else if (dir == kDirBF16)
+        hipLaunchKernelGGL(k_dir16_init<kDirBF16>, grid, dim3(kBlock), 0, st, g, s, (const float4 *)r, ph);
+    else
+        throw std::invalid_argument("launch_dir16_init: not a 16-bit format");
 }
 
 // ------------------------------------------------------------------ CG scalars (one wave per slot)
@@ -913,7 +934,7 @@ __global__ void k_scalars_init(MSState S, int npart, int nslots) {
         S.zeta_new[k] = 1.0;
         S.sh_active[k] = rr > 0.0;
         S.sh_iters[k] = 0;
-        S.sh_scale[k] = 1.0;
+        S.sh_scale[k] = rr > 0.0 ? sqrt(rr) * S.dir_norm : 1.0;
     }
     S.done[slot] = !(rr > 0.0);
     S.iters[slot] = 0;
