@@ -105,6 +105,12 @@ def test_flux8_dir16_storage(prec, bound, qbound):
     assert np.isfinite(err) and err < bound
     assert np.abs(qi - g["qx_imag"]).max() < bound
     assert abs(Q - g["qx"].sum()) < qbound
+    # explicit sources far outside FP16's range: the directions' scales start from |b|
+    phi = 1e6 * si.random_spinors(si.WORKLOADS["flux8"]["dims"], 1, 5)
+    o32 = smpq.smpq_apply_dov(ref, phi)
+    o16 = smpq.smpq_apply_dov(c, phi)
+    assert np.isfinite(o16).all()
+    assert np.abs(o16 - o32).max() < 10 * bound * np.abs(o32).max()
 
 
 def test_flux8_point_subset():
