@@ -9,6 +9,7 @@ Workloads (smpq_inputs.WORKLOADS):
               batch (the batch size of the benchmark)
 Tolerances: FP64 path max |dq| <= 1e-10; mixed path max |dq| <= 1e-5 and |dQ| <= 1e-4.
 """
+import json
 import os
 
 import numpy as np
@@ -285,3 +286,22 @@ def test_resumable_map_matches_one_call(tmp_path):
     smpq.smpq_set_scheme(c, (2, 2, 2, 2), 1)
     with pytest.raises(ValueError):
         compute_qx_resumable(c, path)
+
+
+def test_resumable_command_line(tmp_path, capsys):
+    """The time-boxed command line on the noise4 map (r = 2, 16 classes in chunks of 4): a call
+    stopped by its time limit leaves no state, the next one completes the map, which equals the
+    oracle's within the mixed tolerance and carries the summed statistics."""
+    print("resume command line, noise4 r=2", flush=True)
+    from paper_1901_02211_amd.resume import main
+    g = _golden("noise4_smp")
+    state = str(tmp_path / "noise4.npz")
+    args = ["--workload", "noise4", "--r", "2", "--state", state, "--chunk", "4"]
+    assert main(args + ["--time-limit", "1e-9"]) == 3          # stops before its first chunk
+    assert main(args) == 0
+    out = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    st = np.load(state)
+    assert st["done"].all() and st["iters"] == out["iterations"] > 0
+    assert np.abs(st["qx"] - g["qx"]).max() < 1e-5
+    assert abs(out["Q"] - g["qx"].sum()) < 1e-4
+    assert main(args) == 0                                       # complete: nothing left to do
