@@ -13,6 +13,7 @@ classes/sample (labelled "extrapolated").  --workload uneven times 16^4 + 24^4 +
 together, the same fraction of classes of each, concurrently (one stream per lattice) and
 one after another; --workload ensemble does the same for eight whole 8^4 maps.
 
+Defaults: 3 steps (maps), no warmup; value = their mean (median_s and step_s beside it).
 Printed: one JSON line.  value = seconds per map (lower is better).  Beside it:
   roofline      the dominant kernel of the step (HIP events on the library's stream),
                 algorithmic bytes per launch / mean launch duration vs 8 TB/s
@@ -218,7 +219,7 @@ def ensemble(args, smpq, si):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="noise16x32", choices=sorted(BENCH) + ["uneven", "ensemble"])
     ap.add_argument("--fp64-classes", type=int, default=-1, help="classes in the FP64 comparison sample")
@@ -394,6 +395,8 @@ def main():
                               "device_copy_note": "hipMemcpyAsync device to device, 2 GiB, read + write bytes",
                               "map_stencil_and_update_GBs": round(map_GBs, 1),
                               "map_note": "stencil + shift-update algorithmic bytes over the whole solve time"},
+        "step_s": [round(t * scale, 3) for t in times],
+        "median_s": round(float(np.median(times)) * scale, 3),
         "breakdown_s": {"bounds": round(st["t_bounds_s"], 3), "solve": round(st["t_solve_s"], 3),
                         "contract": round(st["t_contract_s"], 3)},
         "iterations": {"total": st["total_iters"], "max": st["max_iters"], "reliable_updates": st["n_reliable_updates"],
