@@ -66,14 +66,16 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload):
     """Counter-measured HBM bytes / algorithmic bytes of a kernel, from the committed summary,
-    if it was measured on the current kernel source."""
+    if it was measured on the current kernel source and this workload."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         data = json.load(f)
+    if data.get("workload") != workload:
+        return None
     entry = data.get(kernel)
     if not entry or entry.get("kernel_hash") != kernel_source_hash():
         return None
@@ -318,7 +320,7 @@ def main():
     mean_ms = kd["ms"] / kd["launches"]
     bytes_launch = kd["bytes"] / kd["launches"]
     achieved = bytes_launch / (mean_ms * 1e-3) / 1e9
-    tr = measured_traffic(dom)
+    tr = measured_traffic(dom, WORKLOAD)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": round(tr["traffic_over_algorithmic"] * bytes_launch) if tr else None,
@@ -328,7 +330,7 @@ def main():
     map_GBs = (st["dslash_bytes"] + st["update_bytes"]) / (st["t_solve_s"]) / 1e9
 
     ds_insitu = st["dslash_bytes"] / (st["dslash_ms"] * 1e-3) / 1e9
-    trd = measured_traffic("dslash")
+    trd = measured_traffic("dslash", WORKLOAD)
     print("bench: standalone stencil", file=sys.stderr, flush=True)
     copy_ms = smpq.smpq_bench_copy(ctx, 1 << 31, 20)
     copy_GBs = 2.0 * (1 << 31) / (copy_ms * 1e-3) / 1e9
