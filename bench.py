@@ -366,6 +366,7 @@ def main():
                 "deflation": dict(modes=args.deflate, **defl_info) if args.deflate else None}
     if args.full_fp64:
         accuracy["Q_fp64"] = float(q64.sum())
+        accuracy["abs_Q_minus_round_fp64"] = abs(float(q64.sum()) - round(float(q64.sum())))
 
     cpu = None
     if not args.no_cpu:
