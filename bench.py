@@ -388,7 +388,7 @@ def main():
                                 + DIR_STORAGE[args.dir_storage][1],
                    "classes": len(classes), "classes_per_map": ncls,
                    "extrapolated": scale != 1.0,
-                   "stencil_variants": {"f32_kind": ["site", "plane", "xy-tile"][tuning["f32_kind"]],
+                   "stencil_variants": {"f32_kind": ["site", "plane", "xy-tile", "plane, xy links in LDS"][tuning["f32_kind"]],
                                         "f32_rhs_per_thread": tuning["f32_nr"],
                                         "plane_band": tuning["plane_band"],
                                         "f64_rhs_per_block": 1 << tuning["f64_lgr"]}},

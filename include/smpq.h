@@ -313,7 +313,8 @@ smpq_status smpq_bench_copy(smpq_ctx *ctx, size_t bytes, int launches, double *m
  * per thread, links held in registers across them); 1 = one 16x16 xy-plane per block staged
  * in LDS (nx*ny = 256; f32_nr = 4, 8 or 16); 2 = xy-tiles of ty rows plus one halo row on
  * each side staged in LDS, ty the largest divisor of ny with nx*ty <= 256 and a multiple of 64
- * (nx <= 64; f32_nr = 4, 8 or 16).  plane_band (kinds 1 and 2; 1, 2 or 4, dividing nz): the
+ * (nx <= 64; f32_nr = 4, 8 or 16); 3 = kind 1 with the plane's x and y links in LDS instead
+ * of registers, at 3 waves per SIMD.  plane_band (kinds 1-3; 1, 2 or 4, dividing nz): the
  * blocks take the (z, t) planes in bands of that many z with t running inside a band, so the
  * +-t neighbours of a plane were read shortly before (1 = z fastest).  f64_lgr: the FP64
  * stencil interleaves 2^f64_lgr = 1, 2 or 4 right-hand sides over the lanes of a block.

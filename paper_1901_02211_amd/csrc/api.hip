@@ -1841,8 +1841,8 @@ smpq_status smpq_autotune(smpq_ctx *c, int n_rhs, smpq_tuning *chosen) {
         };
         std::vector<Cand> cand = {{0, 2, 1}, {0, 4, 1}, {0, 8, 1}};
         const Geom g0 = c->geom();
-        for (int kind = 1; kind <= 2; ++kind) {
-            if (kind == 1 ? !plane_tileable(g0) : g0.tile_y == 0) continue;
+        for (int kind = 1; kind <= 3; ++kind) {
+            if (kind == 2 ? g0.tile_y == 0 : !plane_tileable(g0)) continue;
             for (int nr : {4, 8, 16})
                 for (int band : {1, 2, 4})
                     if (c->dims[2] % band == 0) cand.push_back({kind, nr, band});

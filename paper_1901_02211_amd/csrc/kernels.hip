@@ -4,9 +4,10 @@
 //                  sides interleaved over the lanes of a block share each link fetch
 //  k_dslash_f32    the FP32 stencil: one site per thread, its eight links held in registers
 //                  for several right-hand sides (k_dslash_f32_plane: the same with one
-//                  16x16 xy-plane per block staged in LDS; k_dslash_f32_tile: xy-tiles of any
-//                  width <= 64 with halo rows); all take an optional epilogue "+ sigma aux"
-//                  with a fused <aux, out> partial for H^2 + sigma (Eq. 4).
+//                  16x16 xy-plane per block staged in LDS, _xyl also its x and y links;
+//                  k_dslash_f32_tile: xy-tiles of any width <= 64 with halo rows); all take an
+//                  optional epilogue "+ sigma aux" with a fused <aux, out> partial for
+//                  H^2 + sigma (Eq. 4).
 //  k_cg_init ...   multi-shift CG for (D_W^dag D_W + q_i) x_i = b (Eqs. 6-8): residual
 //                  update, fused update of every active shift's search direction plus the
 //                  running rational sum y = c_0 b + sum_i c_i x_i, scalar recurrences on the
@@ -476,8 +477,8 @@ __global__ __launch_bounds__(kBlock) void k_dslash_f32_tile(const float4 *__rest
     }
 }
 
-template <int NR, bool DAG, int EPI>
-__global__ __launch_bounds__(kBlock) void k_dslash_f32_plane(const float4 *__restrict__ U, const float4 *__restrict__ in,
+template <int NR, bool DAG, int EPI, bool XYL>
+__device__ __forceinline__ void dslash_f32_plane_body(const float4 *__restrict__ U, const float4 *__restrict__ in,
                                                              size_t in_stride, size_t in_extra,
                                                              float4 *__restrict__ out, size_t out_stride,
                                                              const float4 *__restrict__ aux, size_t aux_stride,
@@ -486,6 +487,9 @@ __global__ __launch_bounds__(kBlock) void k_dslash_f32_plane(const float4 *__res
                                                              size_t pstride) {
     constexpr int SF = DAG ? -1 : 1;
     __shared__ float4 tile[6][kBlock];
+    // XYL: the plane's x and y links in LDS (the backward ones are the neighbours' forward
+    // links within the plane), so that fewer registers per thread hold links
+    __shared__ float4 lxy[XYL ? 2 : 1][3][XYL ? kBlock : 1];
     const int L = xcd_swizzle(blockIdx.x, gridDim.x);
     const int sb = L % nsb, rg = L / nsb;
     const int cnt = slot_count(sl);
@@ -499,13 +503,18 @@ __global__ __launch_bounds__(kBlock) void k_dslash_f32_plane(const float4 *__res
     for (int mu = 0; mu < 4; ++mu)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
+            if (XYL && mu < 2) {
+                if constexpr (XYL) lxy[mu][j][threadIdx.x] = U[(size_t)(mu * 3 + j) * g.V + s];
+                continue;   // visible after the first barrier of the loop below
+            }
             lf[mu][j] = U[(size_t)(mu * 3 + j) * g.V + s];
             lb[mu][j] = U[(size_t)(mu * 3 + j) * g.V + nb.bwd[mu]];
         }
     const int xf = nb.fwd[0] - base, xb = nb.bwd[0] - base, yf = nb.fwd[1] - base, yb = nb.bwd[1] - base;
-    double dot[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) dot[r] = 0.0;
+    // EPI 1: per right-hand side, the block's <aux, out> is summed per wave at once and the
+    // wave sums kept in LDS (no accumulators held across the loop)
+    __shared__ double ldsdot[EPI == 1 ? NR : 1][kBlock / 64];
+    [[maybe_unused]] const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll 1
     for (int r = 0; r < NR; ++r) {
         const int k = k0 + r;
@@ -540,12 +549,15 @@ __global__ __launch_bounds__(kBlock) void k_dslash_f32_plane(const float4 *__res
             P[2 * j + 1] = {t_.z, t_.w};                                             \
         }
 #define SMPQ_TILE_HOP(MU, LF, LB)                                                    \
-        unpack_rows(lf[MU][0], lf[MU][1], lf[MU][2], u);                             \
+        if constexpr (XYL) unpack_rows(lxy[MU][0][threadIdx.x], lxy[MU][1][threadIdx.x],  \
+                                       lxy[MU][2][threadIdx.x], u);                  \
+        else unpack_rows(lf[MU][0], lf[MU][1], lf[MU][2], u);                        \
         SMPQ_TILE_LOAD(LF, p)                                                        \
         project<MU, SF>(p, h);                                                       \
         su3_mul(u, h, w);                                                            \
         accumulate<MU, SF>(acc, w);                                                  \
-        unpack_rows(lb[MU][0], lb[MU][1], lb[MU][2], u);                             \
+        if constexpr (XYL) unpack_rows(lxy[MU][0][LB], lxy[MU][1][LB], lxy[MU][2][LB], u); \
+        else unpack_rows(lb[MU][0], lb[MU][1], lb[MU][2], u);                        \
         SMPQ_TILE_LOAD(LB, p)                                                        \
         project<MU, -SF>(p, h);                                                      \
         su3_dag_mul(u, h, w);                                                        \
@@ -566,26 +578,43 @@ __global__ __launch_bounds__(kBlock) void k_dslash_f32_plane(const float4 *__res
                 v[c] = v[c] + sigma * p[c];
                 d += (double)p[c].re * (double)v[c].re + (double)p[c].im * (double)v[c].im;
             }
-            dot[r] = d;
+            d = wave_sum(d);
+            if (lane == 0) ldsdot[r][wv] = d;
         }
         Store<float>::store_stream(out + slot * out_stride, g.vs, s, v);
     }
     if constexpr (EPI == 1) {
-        __shared__ double lds[NR][kBlock / 64];
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const double t = wave_sum(dot[r]);
-            if (lane == 0) lds[r][wv] = t;
-        }
         __syncthreads();
         if ((int)threadIdx.x < NR && k0 + (int)threadIdx.x < cnt) {
             double t = 0.0;
 #pragma unroll
-            for (int i = 0; i < kBlock / 64; ++i) t += lds[threadIdx.x][i];
+            for (int i = 0; i < kBlock / 64; ++i) t += ldsdot[threadIdx.x][i];
             partial[(size_t)slot_of(sl, k0 + threadIdx.x) * pstride + sb] = t;
         }
     }
+}
+
+
+template <int NR, bool DAG, int EPI>
+__global__ __launch_bounds__(kBlock) void k_dslash_f32_plane(const float4 *__restrict__ U, const float4 *__restrict__ in,
+                                                             size_t in_stride, size_t in_extra,
+                                                             float4 *__restrict__ out, size_t out_stride,
+                                                             const float4 *__restrict__ aux, size_t aux_stride,
+                                                             size_t aux_extra, Geom g, float kappa, float sigma,
+                                                             Slots sl, int nsb, double *__restrict__ partial,
+                                                             size_t pstride) {
+    dslash_f32_plane_body<NR, DAG, EPI, false>(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra,
+                                               g, kappa, sigma, sl, nsb, partial, pstride);
+}
+
+// The same with the x and y links in LDS, at 3 waves per SIMD.
+template <int NR, bool DAG, int EPI>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_dslash_f32_plane_xyl(
+    const float4 *__restrict__ U, const float4 *__restrict__ in, size_t in_stride, size_t in_extra,
+    float4 *__restrict__ out, size_t out_stride, const float4 *__restrict__ aux, size_t aux_stride, size_t aux_extra,
+    Geom g, float kappa, float sigma, Slots sl, int nsb, double *__restrict__ partial, size_t pstride) {
+    dslash_f32_plane_body<NR, DAG, EPI, true>(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra,
+                                              g, kappa, sigma, sl, nsb, partial, pstride);
 }
 
 __host__ __device__ int site_blocks(const Geom &g) { return (g.V + kBlock - 1) / kBlock; }
@@ -604,13 +633,13 @@ static int tile_blocks(const Geom &g) { return g.V / (g.nx * g.tile_y); }
 
 int dslash_partials(int prec, const Geom &g) {
     if (prec == 0) return fp64_parts(g);
-    return g.f32_kind >= 2 ? tile_blocks(g) : site_blocks(g);
+    return g.f32_kind == 2 ? tile_blocks(g) : site_blocks(g);
 }
 
 bool valid_tuning(int prec, const Geom &g) {
     if (prec == 0) return g.f64_lgr >= 0 && g.f64_lgr <= 2;
     const bool nr_tile = g.f32_nr == 4 || g.f32_nr == 8 || g.f32_nr == 16;
-    if (g.f32_kind == 1) return plane_tileable(g) && nr_tile && g.band >= 1 && g.nz % g.band == 0;
+    if (g.f32_kind == 1 || g.f32_kind == 3) return plane_tileable(g) && nr_tile && g.band >= 1 && g.nz % g.band == 0;
     const bool tiled = g.tile_y > 0 && g.tile_y == tile_rows(g.nx, g.ny);
     const bool band_ok = g.band >= 1 && g.nz % g.band == 0;
     if (g.f32_kind == 2) return tiled && nr_tile && band_ok;
@@ -636,10 +665,15 @@ template <int NR, bool DAG, int EPI, int KIND>
 static void launch_f32(const void *U, const void *in, size_t in_stride, size_t in_extra, void *out, size_t out_stride,
                        const void *aux, size_t aux_stride, size_t aux_extra, const Geom &g, double kappa, double sigma,
                        Slots sl, int max_slots, double *partial, hipStream_t st) {
-    const int nsb = KIND >= 2 ? tile_blocks(g) : site_blocks(g);
+    const int nsb = KIND == 2 ? tile_blocks(g) : site_blocks(g);
     const int ngr = (max_slots + NR - 1) / NR;
     if constexpr (KIND == 2)
         hipLaunchKernelGGL((k_dslash_f32_tile<NR, DAG, EPI>), dim3(nsb * ngr), dim3(g.nx * g.tile_y), 0, st,
+                           (const float4 *)U, (const float4 *)in, in_stride, in_extra, (float4 *)out, out_stride,
+                           (const float4 *)aux, aux_stride, aux_extra, g, (float)kappa, (float)sigma, sl, nsb, partial,
+                           partial_stride(g));
+    else if constexpr (KIND == 3)
+        hipLaunchKernelGGL((k_dslash_f32_plane_xyl<NR, DAG, EPI>), dim3(nsb * ngr), dim3(kBlock), 0, st,
                            (const float4 *)U, (const float4 *)in, in_stride, in_extra, (float4 *)out, out_stride,
                            (const float4 *)aux, aux_stride, aux_extra, g, (float)kappa, (float)sigma, sl, nsb, partial,
                            partial_stride(g));
@@ -669,6 +703,10 @@ static void launch_f32_tuned(const void *U, const void *in, size_t in_stride, si
         if (g.f32_nr == 4) SMPQ_F32(4, 1);
         else if (g.f32_nr == 16) SMPQ_F32(16, 1);
         else SMPQ_F32(8, 1);
+    } else if (g.f32_kind == 3) {
+        if (g.f32_nr == 4) SMPQ_F32(4, 3);
+        else if (g.f32_nr == 16) SMPQ_F32(16, 3);
+        else SMPQ_F32(8, 3);
     } else {
         if (g.f32_nr == 2) SMPQ_F32(2, 0);
         else if (g.f32_nr == 8) SMPQ_F32(8, 0);

@@ -34,7 +34,7 @@ def _zolo_interval(U, lat):
 
 
 SITE_VARIANTS = [(0, nr, lgr) for nr, lgr in ((2, 0), (4, 1), (8, 2))]
-PLANE_VARIANTS = [(1, nr, lgr) for nr, lgr in ((4, 0), (8, 1), (16, 2))]
+PLANE_VARIANTS = [(k, nr, lgr) for k in (1, 3) for nr, lgr in ((4, 0), (8, 1), (16, 2))]
 TILE_VARIANTS = [(2, nr, lgr) for nr, lgr in ((4, 0), (8, 1), (16, 2))]
 
 
@@ -58,8 +58,9 @@ def test_dslash_parity(dims, nrhs):
             out32 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_MIXED_FP32)
             assert np.abs(out32 - ref).max() <= 2e-6 * scale, tune
     # the plane kernel needs 16x16 xy-planes
-    with pytest.raises(smpq.SmpqError):
-        smpq.smpq_set_tuning(c, 1, 8, 1)
+    for kind in (1, 3):
+        with pytest.raises(smpq.SmpqError):
+            smpq.smpq_set_tuning(c, kind, 8, 1)
 
 
 @pytest.mark.parametrize("dims", [(16, 16, 2, 2), (16, 16, 3, 2), (16, 16, 4, 3)])
@@ -123,8 +124,9 @@ def test_dslash_parity_xy_tiles(dims, nrhs):
     U = si.near_identity_su3(dims, 0.5, 15)
     psi = si.random_spinors(dims, nrhs, 16)
     c = _ctx(dims, U)
-    with pytest.raises(smpq.SmpqError):
-        smpq.smpq_set_tuning(c, 1, 8, 1)
+    for kind in (1, 3):
+        with pytest.raises(smpq.SmpqError):
+            smpq.smpq_set_tuning(c, kind, 8, 1)
     for dag in (False, True):
         ref = np.stack([apply_dw(U, lat, KAPPA, p, dagger=dag) for p in psi])
         for tune in TILE_VARIANTS:
@@ -138,7 +140,8 @@ def test_dslash_parity_xy_tiles(dims, nrhs):
         smpq.smpq_set_tuning(c, 2, 8, 1, 3)
 
 
-@pytest.mark.parametrize("dims,kind,band", [((16, 16, 2, 2), 1, 1), ((16, 16, 2, 2), 2, 2), ((24, 16, 2, 2), 2, 2)])
+@pytest.mark.parametrize("dims,kind,band", [((16, 16, 2, 2), 1, 1), ((16, 16, 2, 2), 2, 2), ((24, 16, 2, 2), 2, 2),
+                                             ((16, 16, 2, 2), 3, 2)])
 def test_qx_plane_tiled_mixed(dims, kind, band):
     lat = Lattice(dims)
     U = si.near_identity_su3(dims, 0.3, 13)
