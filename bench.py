@@ -236,8 +236,8 @@ def main():
                     help="storage of the shifted systems' search directions in the mixed path")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(sources shard over GPUs with no hot-loop communication; see the design notes)",
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the probing sources would shard over GPUs with no communication in the solver loop)",
               file=sys.stderr)
         sys.exit(2)
 
