@@ -148,3 +148,35 @@ def test_multi_context_argument_errors():
     assert e.value.status == -4
     smpq.smpq_set_memory_limit(a, 1 << 30)
     smpq.smpq_set_memory_limit(a, 0)
+
+
+def _header():
+    return re.sub(r"/\*.*?\*/", "", open(f"{ROOT}/include/smpq.h").read(), flags=re.S)
+
+
+def _struct_fields(src, name):
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + ";", src).group(1)
+    out = []
+    for decl in filter(None, (d.strip() for d in body.split(";"))):
+        ctype, names = decl.split(None, 1)
+        out += [(n.strip(), ctype) for n in names.split(",")]
+    return out
+
+
+def _enum_values(src, name):
+    body = re.search(r"typedef enum \{([^}]*)\}\s*" + name + ";", src).group(1)
+    return {k: int(v) for k, v in re.findall(r"(SMPQ_[A-Z0-9_]+)\s*=\s*(-?\d+)", body)}
+
+
+def test_binding_layouts_match_the_header():
+    """The ctypes structures and constants of the binding are the header's, field by field."""
+    import ctypes
+    src = _header()
+    ctype = {"double": ctypes.c_double, "int64_t": ctypes.c_int64, "int": ctypes.c_int}
+    for struct, cls in (("smpq_stats", smpq.SmpqStats), ("smpq_tuning", smpq.SmpqTuning)):
+        want = [(n, ctype[t]) for n, t in _struct_fields(src, struct)]
+        assert [(n, t) for n, t in cls._fields_] == want, struct
+    for name, value in _enum_values(src, "smpq_precision").items():
+        assert getattr(smpq, name) == value, name
+    assert _enum_values(src, "smpq_status")["SMPQ_ESTATE"] == -6
+    assert int(re.search(r"#define SMPQ_MAX_POLES (\d+)", src).group(1)) == 32
