@@ -7,20 +7,29 @@ whole q(x) map: Lanczos bounds + Zolotarev + every multi-shift CG solve + contra
 copy-out of q(x) and Q, with the gauge field already resident in HBM.  The map runs in
 FP32 with FP64 reliable updates every 50 iterations and FP64 accumulation.
 
+Wall-clock budget (--budget-s, default 470 s for the whole process): --steps and --warmup are
+upper bounds.  At most one untimed warmup map runs (the set-up already primes workspaces and
+graphs); timed maps stop once the next would not leave room for the legs after them (the FP64
+map, the CPU leg, the standalone figures).  `steps` reports the maps actually timed,
+`steps_requested` the request.
+
 --workload selects another lattice of the same family (24^3x48 flux, 16^4, 24^4, 32^3x64);
 maps that take minutes are timed on a sample of classes and the value is extrapolated by
 classes/sample (labelled "extrapolated").  --workload uneven times 16^4 + 24^4 + 32^3x64
 together, the same fraction of classes of each, concurrently (one stream per lattice) and
 one after another; --workload ensemble does the same for eight whole 8^4 maps.
 
-Defaults: 3 steps (maps), no warmup; value = their mean (median_s and step_s beside it).
-Printed: one JSON line.  value = seconds per map (lower is better).  Beside it:
+Printed: one JSON line.  value = mean seconds per map of the timed maps (lower is better).
+Beside it:
   roofline      the dominant kernel of the step (HIP events on the library's stream),
                 algorithmic bytes per launch / mean launch duration vs 8 TB/s
   dslash        the Wilson stencil in situ and standalone (rotating buffers > 1 GB)
-  fp64          the plain FP64 GPU path on a sample of classes, scaled to a map
-  accuracy      mixed vs FP64 GPU on the sample; |Q - round(Q)| of the map
-  cpu_baseline  the FP64 numpy oracle on a bounded sample (single thread), scaled
+  fp64          the plain FP64 GPU path: the whole map when the map is whole (else a sample
+                of classes, scaled)
+  accuracy      mixed vs FP64 GPU (max |dq|, dQ) and |Q - round(Q)| of both maps
+  cpu_baseline  the FP64 numpy oracle, one process per host core: a bounded sample of the
+                workload scaled to a map, and one whole 4^4 map timed as it runs (with the
+                GPU's time for the same map and the GPU-vs-oracle difference)
 """
 import argparse
 import hashlib
@@ -32,6 +41,7 @@ import time
 
 import numpy as np
 
+T_START = time.perf_counter()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -82,147 +92,174 @@ def measured_traffic(kernel, workload):
     return entry
 
 
-def cpu_baseline(workload, dims, r_gap, total_iters, n_sources, iters_sample):
-    """Time the oracle's multi-shift CG on one source of the workload for a bounded number of
-    iterations in a single-threaded subprocess; scale by the map's measured iteration count."""
-    code = f"""
-import os, sys, time
-sys.path.insert(0, {ROOT!r})
+def host_cores():
+    """Host cores the CPU leg may use: the process's CPU affinity, at most 16 (the host share
+    of one GPU on the MI355X boxes)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        return ""
+
+
+# The CPU leg runs in a child interpreter that never touches the GPU and forks its workers
+# there: one process per host core, one BLAS thread each.  It prints one JSON line per part.
+CPU_LEG = r"""
+import json, os, sys, time
+sys.path.insert(0, ROOT)
+import multiprocessing as mp
 import numpy as np
 import smpq_inputs as si
 from oracle.lattice import Lattice
-from oracle.dirac import apply_h2
+from oracle.dirac import apply_dw, apply_h2
 from oracle.mscg import multishift_cg, NotConverged
-from oracle.lanczos import bounds
-from oracle.zolotarev import zolotarev
 from oracle.probing import colouring
-U = si.workload({workload!r}); lat = Lattice({tuple(dims)!r})
-col, _ = colouring(lat, ({r_gap},) * 4, 0)
-b = np.zeros((lat.volume, 4, 3), dtype=np.complex128); b[col == 0, 0, 0] = 1.0
-c0, c, q, _ = zolotarev({POLES}, 0.14, 2.73)
-s = q.min()
-from oracle.dirac import apply_dw
-t0 = time.perf_counter()
-apply_dw(U, lat, {KAPPA}, b)
-t_dw = time.perf_counter() - t0
-t0 = time.perf_counter()
-try:
-    multishift_cg(lambda v: apply_h2(U, lat, {KAPPA}, v) + s * v, b, q - s, {TOL}, {iters_sample})
-except NotConverged:
-    pass
-print(t_dw, time.perf_counter() - t0)
-"""
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
-    if out.returncode != 0:
-        raise RuntimeError(out.stderr)
-    t_dw, t = (float(x) for x in out.stdout.strip().splitlines()[-1].split())
-    per_iter = t / iters_sample
-    V = int(np.prod(dims))
-    cpu_model = ""
+from oracle.zolotarev import zolotarev
+from oracle.charge import qx_probing
+
+P, WORKLOAD, DIMS, RGAP, ITERS, POLES, KAPPA, TOL, SMALL = json.loads(sys.argv[1])
+DIMS = tuple(DIMS)
+
+def big_source(k):
+    # ITERS multi-shift CG iterations of the source (class k, spin-colour 0) of the workload
+    b = np.zeros((LAT.volume, 4, 3), dtype=np.complex128)
+    b[COL == k, 0, 0] = 1.0
+    t0 = time.perf_counter()
     try:
-        with open("/proc/cpuinfo") as f:
-            cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
-    except OSError:
+        multishift_cg(lambda v: apply_h2(U, LAT, KAPPA, v) + S0 * v, b, QS - S0, TOL, ITERS)
+    except NotConverged:
         pass
-    return {"value": per_iter * total_iters, "unit": "s/map", "cores": 1, "kind": "oracle",
-            "host_cpu": cpu_model, "host_nproc": os.cpu_count(),
-            "oracle_dw_ns_per_site": 1e9 * t_dw / V,
-            "oracle_dw_GBs": V * (72 + 48) * 8 / t_dw / 1e9,
-            "sample": f"{iters_sample} multi-shift CG iterations of one r={r_gap} source on the {workload} field "
-                      f"({t:.1f} s), scaled by the map's {total_iters} iterations over {n_sources} sources",
-            "seconds_per_iteration": per_iter}
+    return time.perf_counter() - t0
+
+def small_class(k):
+    return qx_probing(U4, LAT4, KAPPA, Z4, COL4, [k], TOL, 5000)
+
+if __name__ == "__main__":
+    ctx = mp.get_context("fork")
+    # part 1: a bounded sample of the big workload, one source per core at once
+    U = si.workload(WORKLOAD); LAT = Lattice(DIMS)
+    COL, _ = colouring(LAT, (RGAP,) * 4, 0)
+    c0, c, QS, _ = zolotarev(POLES, 0.14, 2.73)
+    S0 = float(QS.min())
+    t0 = time.perf_counter(); apply_dw(U, LAT, KAPPA, np.ones((LAT.volume, 4, 3), dtype=np.complex128))
+    t_dw = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    with ctx.Pool(P) as pool:
+        per = pool.map(big_source, list(range(P)))
+    wall = time.perf_counter() - t0
+    print(json.dumps({"part": "sample", "wall_s": wall, "worker_s": per, "dw_s": t_dw}), flush=True)
+    del U
+    # part 2: one whole small map (every class), classes spread over the cores
+    U4 = si.workload(SMALL["workload"]); LAT4 = Lattice(tuple(SMALL["dims"]))
+    COL4, ncls = colouring(LAT4, (SMALL["r"],) * 4, 0)
+    Z4 = zolotarev(POLES, SMALL["lo"], SMALL["hi"])
+    t0 = time.perf_counter()
+    with ctx.Pool(P) as pool:
+        parts = pool.map(small_class, list(range(int(ncls))))
+    wall = time.perf_counter() - t0
+    q = np.sum(parts, axis=0).real
+    print(json.dumps({"part": "small_map", "wall_s": wall, "classes": int(ncls), "q": q.tolist()}), flush=True)
+"""
 
 
-def uneven(args, smpq, si):
-    """16^4 + 24^4 + 32^3x64 together: the same fraction of the classes of each lattice, solved
-    concurrently (smpq_compute_qx_multi) and one after another; both scaled to whole maps."""
-    frac = 1.0 / 256 if args.classes < 0 else 1.0 / max(1, args.classes)
-    ctxs, plan = [], []
-    for name in UNEVEN:
-        r = BENCH[name][0]
-        print(f"bench: building {name}", file=sys.stderr, flush=True)
-        c = smpq.smpq_create(si.WORKLOADS[name]["dims"], 0)
-        smpq.smpq_load_gauge(c, si.workload(name))
-        ncls, _ = smpq.smpq_set_scheme(c, (r,) * 4, 0)
-        smpq.smpq_set_solver(c, smpq.SMPQ_MIXED_FP32, TOL, 10000, RELIABLE)
-        smpq.smpq_set_zolotarev(c, POLES, *smpq.smpq_estimate_bounds(c, 300))
-        smpq.smpq_autotune(c, 48)
-        k = max(1, round(ncls * frac))
-        ctxs.append(c)
-        plan.append((name, ncls, list(range(k))))
-    for c, (_, _, cl) in zip(ctxs, plan):   # untimed: workspaces, graphs, first launches
-        smpq.smpq_compute_qx_classes(c, cl[:1])
-    t0 = time.perf_counter()
-    seq = [smpq.smpq_compute_qx_classes(c, cl) for c, (_, _, cl) in zip(ctxs, plan)]
-    t_seq = time.perf_counter() - t0
-    print(f"bench: one after another {t_seq:.2f} s", file=sys.stderr, flush=True)
-    smpq.smpq_compute_qx_multi(ctxs, [cl[:1] for _, _, cl in plan])
-    t0 = time.perf_counter()
-    par = smpq.smpq_compute_qx_multi(ctxs, [cl for _, _, cl in plan])
-    t_par = time.perf_counter() - t0
-    print(f"bench: concurrent {t_par:.2f} s", file=sys.stderr, flush=True)
-    same = all(np.array_equal(a[0], b[0]) for a, b in zip(seq, par))
-    scale = sum(n for _, n, _ in plan) / sum(len(cl) for _, _, cl in plan)
-    line = {
-        "metric": "sec per set of q(x) maps (16^4 + 24^4 + 32^3x64), concurrent",
-        "value": round(t_par * scale, 3), "unit": "s/set", "n_gpus": 1, "steps": 1, "warmup": 0,
-        "ms_per_step": round(1000 * t_par * scale, 1), "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "16^4 r=4 + 24^4 r=6 + 32^3x64 r=8, near-identity SU(3), mixed precision",
-                   "lattices": {n: {"classes_timed": len(cl), "classes_per_map": nc,
-                                    "sources_timed": 12 * len(cl),
-                                    "iterations": st[2]["total_iters"], "batches": st[2]["n_batches"]}
-                                for (n, nc, cl), st in zip(plan, par)},
-                   "extrapolated": True, "fraction_of_each_map": frac},
-        "sequential_s_per_set": round(t_seq * scale, 3),
-        "concurrent_over_sequential": round(t_par / t_seq, 4),
-        "results_identical": same,
-    }
-    print(json.dumps(line), flush=True)
+def cpu_baseline(workload, dims, r_gap, total_iters, n_sources, iters_sample, small, timeout_s):
+    """The FP64 oracle on the host cores, one process per core: (1) `iters_sample` multi-shift CG
+    iterations of one source of the workload on every core at once, scaled by the map's measured
+    iteration count to seconds per map; (2) one whole small map (every class of `small`) timed
+    as it runs.  Parts that do not finish within timeout_s are left out."""
+    P = host_cores()
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    arg = json.dumps([P, workload, list(dims), r_gap, iters_sample, POLES, KAPPA, TOL, small])
+    proc = subprocess.Popen([sys.executable, "-c", CPU_LEG.replace("ROOT", repr(ROOT), 1), arg],
+                            stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+    try:
+        out, err = proc.communicate(timeout=timeout_s)
+    except subprocess.TimeoutExpired:
+        proc.kill()
+        out, err = proc.communicate()
+    parts = {}
+    for ln in out.splitlines():
+        try:
+            d = json.loads(ln)
+            parts[d["part"]] = d
+        except (ValueError, KeyError):
+            pass
+    res = {"value": None, "unit": "s/map", "cores": P, "kind": "oracle", "host_cpu": cpu_model(),
+           "host_nproc": os.cpu_count()}
+    if "sample" in parts:
+        p = parts["sample"]
+        rate = P * iters_sample / p["wall_s"]        # CG iterations per second over all cores
+        V = int(np.prod(dims))
+        res.update(value=total_iters / rate,
+                   sample=f"{iters_sample} multi-shift CG iterations of {P} sources of the {workload} field, "
+                          f"one per core at once ({p['wall_s']:.1f} s), scaled by the map's {total_iters} "
+                          f"iterations over {n_sources} sources (extrapolated)",
+                   seconds_per_iteration_per_core=float(np.mean(p["worker_s"])) / iters_sample,
+                   oracle_dw_ns_per_site=1e9 * p["dw_s"] / V,
+                   oracle_dw_GBs=V * (72 + 48) * 8 / p["dw_s"] / 1e9)
+    else:
+        res["sample"] = f"not finished within {timeout_s:.0f} s"
+    if "small_map" in parts:
+        p = parts["small_map"]
+        res["whole_small_map"] = {"workload": small["label"], "s_per_map": round(p["wall_s"], 3),
+                                  "classes": p["classes"], "extrapolated": False,
+                                  "q": np.asarray(p["q"])}
+    if proc.returncode not in (0, None) and not parts:
+        res["error"] = err.strip().splitlines()[-1] if err.strip() else f"exit {proc.returncode}"
+    return res
 
 
-def ensemble(args, smpq, si):
-    """Eight 8^4 near-identity fields (eps 0.3, seeds 10-17), SMP r = 2 (192 sources each), whole
-    maps: concurrently through smpq_compute_qx_multi and one after another.  Small lattices
-    leave the GPU idle between short launches and host round trips; several contexts fill it."""
-    dims, n = (8, 8, 8, 8), 8
-    ctxs = []
-    for k in range(n):
-        c = smpq.smpq_create(dims, 0)
-        smpq.smpq_load_gauge(c, si.near_identity_su3(dims, 0.3, 10 + k))
-        smpq.smpq_set_scheme(c, (2,) * 4, 0)
-        smpq.smpq_set_solver(c, smpq.SMPQ_MIXED_FP32, TOL, 10000, RELIABLE)
-        smpq.smpq_set_zolotarev(c, POLES, *smpq.smpq_estimate_bounds(c, 300))
-        ctxs.append(c)
-    smpq.smpq_compute_qx_multi(ctxs)                 # untimed: workspaces, graphs
-    for c in ctxs:
-        smpq.smpq_compute_qx(c)
-    t0 = time.perf_counter()
-    seq = [smpq.smpq_compute_qx(c) for c in ctxs]
-    t_seq = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    par = smpq.smpq_compute_qx_multi(ctxs)
-    t_par = time.perf_counter() - t0
-    same = all(np.array_equal(a[0], b[0]) for a, b in zip(seq, par))
-    line = {
-        "metric": "sec per ensemble of eight 8^4 q(x) maps (r=2), concurrent",
-        "value": round(t_par, 4), "unit": "s/ensemble", "n_gpus": 1, "steps": 1, "warmup": 0,
-        "ms_per_step": round(1000 * t_par, 2), "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "8 x 8^4 near-identity SU(3) eps=0.3 seeds 10-17, SMP normal mode r=2, mixed precision",
-                   "sources_per_map": seq[0][3]["n_sources"], "extrapolated": False},
-        "sequential_s": round(t_seq, 4), "concurrent_over_sequential": round(t_par / t_seq, 4),
-        "Q": [round(float(x[2]), 6) for x in seq], "results_identical": same,
-    }
-    print(json.dumps(line), flush=True)
+class Clock:
+    """Wall clock of the whole process against a budget (seconds from the import of bench.py)."""
+
+    def __init__(self, budget_s, now=None, t0=None):
+        self.now = now if now is not None else (lambda: time.perf_counter())
+        self.t0 = now() if t0 is None else t0
+        self.budget = budget_s
+
+    def elapsed(self):
+        return self.now() - self.t0
+
+    def left(self):
+        return self.budget - self.elapsed()
+
+
+def timed_maps(one_map, steps, clock, reserve, estimate_s=None):
+    """Time whole maps: at most `steps`, at least one, and no further map once the next one (at
+    the mean duration so far) would leave less than reserve(duration) seconds of the budget.
+    one_map() returns a tuple whose first entry is its duration.  Returns the per-map results."""
+    out = []
+    for _ in range(steps):
+        est = float(np.mean([r[0] for r in out])) if out else estimate_s
+        if out and clock.left() - 1.05 * est < reserve(est):
+            break
+        out.append(one_map())
+    return out
+
+
+SMALL_MAP = {"workload": "noise4", "label": "4^4 near-identity SU(3) eps=0.3 seed 0, SMP normal mode r=2 "
+                                         "(192 sources), interval [0.13, 2.62]",
+             "dims": [4, 4, 4, 4], "r": 2, "lo": 0.13, "hi": 2.62}
+FP64_OVER_MIXED = 2.4      # expected FP64 / mixed map time, for planning only (measured: 2.25)
+CPU_LEG_S = 75.0           # time allowed for the CPU leg
+EXTRAS_S = 25.0            # standalone stencil, copy, small-map and slack
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=3, help="timed maps requested (an upper bound under --budget-s)")
+    ap.add_argument("--warmup", type=int, default=0, help="untimed maps requested (at most one is run)")
+    ap.add_argument("--budget-s", type=float, default=470.0,
+                    help="wall-clock budget of the whole process; timed maps stop early to keep it")
     ap.add_argument("--workload", default="noise16x32", choices=sorted(BENCH) + ["uneven", "ensemble"])
     ap.add_argument("--fp64-classes", type=int, default=-1, help="classes in the FP64 comparison sample")
     ap.add_argument("--full-fp64", action="store_true", help="run the FP64 comparison as a whole map")
@@ -240,6 +277,7 @@ def main():
               f"(the probing sources would shard over GPUs with no communication in the solver loop)",
               file=sys.stderr)
         sys.exit(2)
+    clock = Clock(args.budget_s, t0=T_START)
 
     import paper_1901_02211_amd as smpq
     import smpq_inputs as si
@@ -257,6 +295,7 @@ def main():
         args.fp64_classes = fp64_default
     if args.cpu_iters <= 0:
         args.cpu_iters = max(2, round(8 * 131072 / int(np.prod(DIMS))))
+    whole_fp64 = args.full_fp64 or args.classes == 0    # whole maps: compare whole maps
     print(f"bench: building {WORKLOAD} {DIMS}", file=sys.stderr, flush=True)
     U = si.workload(WORKLOAD)
     ctx = smpq.smpq_create(DIMS, 0)
@@ -288,27 +327,33 @@ def main():
             q, qi, Q, st = smpq.smpq_compute_qx(ctx)
         t2 = time.perf_counter()
         st["t_bounds_s"] = t1 - t0
+        print(f"bench: map {t2 - t0:.2f} s, Q = {Q:.6f}, iters {st['total_iters']}, batches {st['n_batches']} "
+              f"({clock.elapsed():.0f} s of {clock.budget:.0f})", file=sys.stderr, flush=True)
         return t2 - t0, q, Q, st
 
     # untimed set-up: workspace allocation and first launches of every kernel
     smpq.smpq_set_zolotarev(ctx, POLES, 0.14, 2.73)
     tuning = smpq.smpq_autotune(ctx, 0)            # at the map's batch size
-    print(f"bench: stencil variants {tuning}", file=sys.stderr, flush=True)
+    print(f"bench: stencil variants {tuning} ({clock.elapsed():.0f} s)", file=sys.stderr, flush=True)
     smpq.smpq_prepare(ctx)
     smpq.smpq_compute_qx_classes(ctx, [0])
     smpq.smpq_set_timing(ctx, True)
-    for w in range(args.warmup):
-        print(f"bench: warmup step {w}", file=sys.stderr, flush=True)
-        one_map()
-    times, last = [], None
-    for k in range(args.steps):
-        dt, q, Q, st = one_map()
-        times.append(dt)
-        last = (q, Q, st)
-        print(f"bench: step {k}: {dt:.2f} s, Q = {Q:.6f}, iters {st['total_iters']}, "
-              f"batches {st['n_batches']}", file=sys.stderr, flush=True)
-    q_mixed, Q, st = last
-    ms_per_step = 1000.0 * float(np.mean(times)) * scale
+    est = None
+    warm = 0
+    if args.warmup > 0:     # one untimed map: workspaces and graphs are already primed above
+        print("bench: warmup map", file=sys.stderr, flush=True)
+        est = one_map()[0]
+        warm = 1
+    # what must still fit after the timed maps: the FP64 map (whole or sampled), the CPU leg
+    # and the standalone figures
+    fp64_est = lambda m: FP64_OVER_MIXED * m * (1.0 if whole_fp64 else min(1.0, args.fp64_classes / len(classes)))
+    cpu_s = 0.0 if args.no_cpu else CPU_LEG_S
+    reserve = lambda m: fp64_est(m) + cpu_s + EXTRAS_S
+    runs = timed_maps(one_map, args.steps, clock, reserve, est)
+    times = [r[0] for r in runs]
+    _, q_mixed, Q, st = runs[-1]
+    map_s = float(np.mean(times))
+    ms_per_step = 1000.0 * map_s * scale
 
     # kernels: dominant by in-situ time
     kern = {
@@ -343,9 +388,11 @@ def main():
               "standalone_fp64_n24_GBs": round(by64 / ms64 / 1e6, 1),
               "standalone_note": "24 right-hand sides, 4 rotating input/output/link sets (> 1 GB)"}
 
-    # plain FP64 GPU path on a sample of classes (or the whole map)
-    print("bench: FP64 comparison", file=sys.stderr, flush=True)
-    fcls = list(range(ncls)) if args.full_fp64 else list(range(min(args.fp64_classes, len(classes))))
+    # plain FP64 GPU path: the whole map when it fits the budget, else a sample of classes
+    fcls = list(range(min(args.fp64_classes, len(classes))))
+    if whole_fp64 and clock.left() - FP64_OVER_MIXED * map_s * scale >= cpu_s + 10.0:
+        fcls = list(classes)
+    print(f"bench: FP64 comparison on {len(fcls)} classes ({clock.elapsed():.0f} s)", file=sys.stderr, flush=True)
     smpq.smpq_set_solver(ctx, smpq.SMPQ_FP64, TOL, 10000, 0)
     smpq.smpq_set_timing(ctx, False)
     t0 = time.perf_counter()
@@ -353,35 +400,55 @@ def main():
     t64 = time.perf_counter() - t0
     colour = smpq.smpq_get_coloring(ctx)
     mask = np.isin(colour, fcls)
+    fp64_whole = len(fcls) == ncls
     fp64 = {"seconds": round(t64, 3), "classes": len(fcls),
             "s_per_map": round(t64 * ncls / len(fcls), 3),
-            "scaled": not args.full_fp64, "total_iters": st64["total_iters"]}
+            "scaled": not fp64_whole, "total_iters": st64["total_iters"]}
     accuracy = {"max_abs_dq_mixed_vs_fp64": float(np.abs(q_mixed[mask] - q64[mask]).max()),
-                "dQ_mixed_vs_fp64_on_sample": float(q_mixed[mask].sum() - q64[mask].sum()),
+                "dQ_mixed_vs_fp64": float(q_mixed[mask].sum() - q64[mask].sum()),
+                "dQ_over": "whole map" if fp64_whole else f"{len(fcls)} classes",
                 "Q": Q if scale == 1.0 else None,
                 "abs_Q_minus_round": abs(Q - round(Q)) if scale == 1.0 else None,
                 "max_abs_imag_q": st["max_abs_imag_q"], "sum_imag_q": st["sum_imag_q"],
                 "lam_min": st["lam_min"], "lam_max": st["lam_max"], "zolo_delta": st["zolo_delta"],
                 "max_true_resid_base_fp64": st["max_true_resid"],
                 "deflation": dict(modes=args.deflate, **defl_info) if args.deflate else None}
-    if args.full_fp64:
-        accuracy["Q_fp64"] = float(q64.sum())
-        accuracy["abs_Q_minus_round_fp64"] = abs(float(q64.sum()) - round(float(q64.sum())))
+    if fp64_whole:
+        Q64 = float(q64.sum())
+        accuracy["Q_fp64"] = Q64
+        accuracy["abs_Q_minus_round_fp64"] = abs(Q64 - round(Q64))
 
     cpu = None
     if not args.no_cpu:
-        print("bench: CPU oracle sample", file=sys.stderr, flush=True)
+        # the small whole map on the GPU too (both precisions), beside the oracle's
+        print(f"bench: CPU oracle ({host_cores()} cores, {clock.elapsed():.0f} s)", file=sys.stderr, flush=True)
         cpu = cpu_baseline(WORKLOAD, DIMS, R_GAP, round(st["total_iters"] * scale), round(st["n_sources"] * scale),
-                           args.cpu_iters)
+                           args.cpu_iters, SMALL_MAP, max(20.0, min(CPU_LEG_S, clock.left() - 10.0)))
+        small = cpu.get("whole_small_map")
+        if small is not None:
+            c4 = smpq.smpq_create(SMALL_MAP["dims"], 0)
+            smpq.smpq_load_gauge(c4, si.workload(SMALL_MAP["workload"]))
+            smpq.smpq_set_scheme(c4, (SMALL_MAP["r"],) * 4, 0)
+            smpq.smpq_set_zolotarev(c4, POLES, SMALL_MAP["lo"], SMALL_MAP["hi"])
+            qcpu = small.pop("q")
+            for name, prec, rel in (("fp64", smpq.SMPQ_FP64, 0), ("mixed", smpq.SMPQ_MIXED_FP32, RELIABLE)):
+                smpq.smpq_set_solver(c4, prec, TOL, 10000, rel)
+                smpq.smpq_compute_qx(c4)                  # untimed: workspace and graphs
+                t0 = time.perf_counter()
+                q4 = smpq.smpq_compute_qx(c4)[0]
+                small[f"gpu_{name}_s_per_map"] = round(time.perf_counter() - t0, 4)
+                small[f"gpu_{name}_max_abs_dq_vs_oracle"] = float(np.abs(q4 - qcpu).max())
+            smpq.smpq_destroy(c4)
 
+    solve_s = st["t_solve_s"]
     line = {
         "metric": "sec per q(x) map + D_W HBM GB/s; mixed/batched vs plain FP64 at 16^3x32"
                   if WORKLOAD == "noise16x32" else f"sec per q(x) map, {WORKLOAD}",
         "value": round(ms_per_step / 1000.0, 3), "unit": "s/map",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 1),
+        "n_gpus": 1, "steps": len(times), "warmup": warm, "ms_per_step": round(ms_per_step, 1),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": desc,
+        "config": {"workload": ("one whole q(x) map: " if scale == 1.0 else "") + desc,
                    "lattice": list(DIMS), "n_sources": st["n_sources"], "n_batches": st["n_batches"],
                    "kappa": KAPPA, "zolotarev_poles": POLES, "cg_tol": TOL, "reliable_interval": RELIABLE,
                    "precision": "FP32 stencil and CG body, FP64 scalars/reliable updates/accumulation"
@@ -392,6 +459,7 @@ def main():
                                         "f32_rhs_per_thread": tuning["f32_nr"],
                                         "plane_band": tuning["plane_band"],
                                         "f64_rhs_per_block": 1 << tuning["f64_lgr"]}},
+        "steps_requested": args.steps, "warmup_requested": args.warmup, "budget_s": args.budget_s,
         "speedup_vs_fp64": round(fp64["s_per_map"] / (ms_per_step / 1000.0), 3),
         "roofline": roofline, "dslash": dslash, "fp64": fp64, "accuracy": accuracy,
         "bandwidth_context": {"device_copy_GBs": round(copy_GBs, 1),
@@ -400,11 +468,15 @@ def main():
                               "map_note": "stencil + shift-update algorithmic bytes over the whole solve time"},
         "step_s": [round(t * scale, 3) for t in times],
         "median_s": round(float(np.median(times)) * scale, 3),
-        "breakdown_s": {"bounds": round(st["t_bounds_s"], 3), "solve": round(st["t_solve_s"], 3),
-                        "contract": round(st["t_contract_s"], 3)},
+        "breakdown_s": {"bounds": round(st["t_bounds_s"], 3), "solve": round(solve_s, 3),
+                        "contract": round(st["t_contract_s"], 3),
+                        "solve_stencil": round(st["dslash_ms"] * 1e-3, 3),
+                        "solve_shift_update": round(st["update_ms"] * 1e-3, 3),
+                        "solve_rest": round(solve_s - (st["dslash_ms"] + st["update_ms"]) * 1e-3, 3)},
         "iterations": {"total": st["total_iters"], "max": st["max_iters"], "reliable_updates": st["n_reliable_updates"],
                        "mean_active_shifts": round(st["shift_updates"] / max(1, st["total_iters"]), 2)},
         "cpu_baseline": cpu,
+        "wall_s": round(clock.elapsed(), 1),
     }
     print(json.dumps(line), flush=True)
 

@@ -147,9 +147,26 @@ smpq_status smpq_get_zolotarev(const smpq_ctx *ctx, int *n_poles, double *c0, do
 
 /* Solver settings: precision, relative residual tol per shift (a shift stops once
  * zeta_i |r| <= tol |b|), iteration limit (ENOCONV when reached) and the interval, in
- * iterations, of FP64 residual replacement in the mixed precisions.  (section 2.1, Eqs. 6-8) */
+ * iterations, of FP64 residual replacement in the mixed precisions (0: none).  The solver
+ * runs in groups of 10 iterations and tests convergence after each group, so
+ * reliable_interval must be 0 or a multiple of 10 (EINVAL otherwise); max_iter is reached
+ * at the end of the group that crosses it.  (section 2.1, Eqs. 6-8) */
 smpq_status smpq_set_solver(smpq_ctx *ctx, smpq_precision prec, double tol, int max_iter,
                             int reliable_interval);
+
+/* What a result computed with this context depends on besides the scheme and the Zolotarev
+ * coefficients (for checkpoints that must not mix configurations): kappa, the solver settings
+ * and a hash of the gauge field. */
+typedef struct {
+    double kappa;
+    int precision;              /* smpq_precision                                        */
+    double tol;
+    int max_iter, reliable_interval;
+    uint64_t gauge_hash;        /* FNV-1a (64 bit) of the bytes of the host field passed to
+                                   the last successful smpq_load_gauge; 0 before one       */
+} smpq_settings;
+
+smpq_status smpq_get_settings(const smpq_ctx *ctx, smpq_settings *out);
 
 /* Upper bound on the right-hand sides resident on the device at once (0: automatic,
  * from free device memory).  Rounded down to a multiple of 12 when >= 12. */

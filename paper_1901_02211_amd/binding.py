@@ -18,7 +18,7 @@ __all__ = [
     "SMPQ_FP64", "SMPQ_MIXED_FP32", "SMPQ_MIXED_FP16DIR", "SMPQ_MIXED_BF16DIR", "SmpqError", "SmpqStats", "SmpqTuning", "LIB_PATH", "EXPORTS",
     "smpq_create", "smpq_destroy", "smpq_strerror", "smpq_last_error", "smpq_load_gauge",
     "smpq_set_kappa", "smpq_lanczos", "smpq_estimate_bounds", "smpq_set_zolotarev",
-    "smpq_get_zolotarev", "smpq_set_solver", "smpq_set_batch", "smpq_set_scheme",
+    "smpq_get_zolotarev", "smpq_set_solver", "smpq_get_settings", "SmpqSettings", "smpq_set_batch", "smpq_set_scheme",
     "smpq_set_point_scheme", "smpq_get_coloring", "smpq_get_scheme_rmin", "smpq_apply_dw", "smpq_apply_dov",
     "smpq_compute_qx", "smpq_compute_qx_classes", "smpq_compute_trinv", "smpq_dov_locality", "smpq_deflate", "smpq_compute_qx_points", "smpq_prepare", "smpq_set_stream",
     "smpq_set_timing", "smpq_set_graphs", "smpq_bench_dslash", "smpq_bench_copy", "smpq_autotune",
@@ -36,6 +36,14 @@ _vp = ctypes.c_void_p
 
 class SmpqTuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int) for n in ("f32_kind", "f32_nr", "f64_lgr", "plane_band")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class SmpqSettings(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.c_double), ("precision", ctypes.c_int), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int), ("reliable_interval", ctypes.c_int), ("gauge_hash", ctypes.c_uint64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -66,6 +74,7 @@ _SIG = {
     "smpq_set_zolotarev": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double]),
     "smpq_get_zolotarev": (ctypes.c_int, [_vp, _c_int_p, _c_double_p, _c_double_p, _c_double_p, _c_double_p]),
     "smpq_set_solver": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int]),
+    "smpq_get_settings": (ctypes.c_int, [_vp, ctypes.POINTER(SmpqSettings)]),
     "smpq_set_batch": (ctypes.c_int, [_vp, ctypes.c_int]),
     "smpq_set_scheme": (ctypes.c_int, [_vp, _c_int_p, ctypes.c_int, _c_int_p, _c_int_p]),
     "smpq_set_point_scheme": (ctypes.c_int, [_vp, _c_int_p, _c_int_p]),
@@ -202,6 +211,13 @@ def smpq_get_zolotarev(ctx):
 
 def smpq_set_solver(ctx, precision=SMPQ_FP64, tol=1e-12, max_iter=10000, reliable_interval=50):
     _check(ctx, _lib.smpq_set_solver(ctx.ptr, int(precision), float(tol), int(max_iter), int(reliable_interval)))
+
+
+def smpq_get_settings(ctx):
+    """dict: kappa, precision, tol, max_iter, reliable_interval, gauge_hash."""
+    out = SmpqSettings()
+    _check(ctx, _lib.smpq_get_settings(ctx.ptr, ctypes.byref(out)))
+    return out.as_dict()
 
 
 def smpq_set_batch(ctx, max_rhs):

@@ -129,6 +129,7 @@ struct smpq_ctx {
     std::string err;
     double kappa = 0.21;
     bool have_gauge = false;
+    uint64_t gauge_hash = 0;   // FNV-1a of the bytes of the loaded host field
     DevMem U64, U32;
     bool have_zolo = false;
     Zolo zolo;
@@ -1229,6 +1230,10 @@ smpq_status smpq_load_gauge(smpq_ctx *c, const double *U, size_t n) {
         c->U32.ensure(sizeof(float) * V * 48);
         HIPCHK(hipMemcpy(c->U64.p, u64.data(), sizeof(double) * V * 72, hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(c->U32.p, u32.data(), sizeof(float) * V * 48, hipMemcpyHostToDevice));
+        uint64_t h = 0xcbf29ce484222325ull;   // FNV-1a, 64 bit
+        const unsigned char *bytes = reinterpret_cast<const unsigned char *>(U);
+        for (size_t i = 0; i < n * sizeof(double); ++i) h = (h ^ bytes[i]) * 0x100000001b3ull;
+        c->gauge_hash = h;
         c->have_gauge = true;
         drop_deflation(c);   // eigenvectors of the previous operator
         c->gen++;
@@ -1290,12 +1295,27 @@ smpq_status smpq_set_solver(smpq_ctx *c, smpq_precision prec, double tol, int ma
             throw Fail{SMPQ_EINVAL, "unknown precision"};
         if (!(tol > 0.0 && tol < 1.0)) throw Fail{SMPQ_EINVAL, "tol must be in (0, 1)"};
         if (max_iter < 1) throw Fail{SMPQ_EINVAL, "max_iter must be >= 1"};
-        if (reliable < 0) throw Fail{SMPQ_EINVAL, "reliable_interval must be >= 0"};
+        if (reliable < 0 || reliable % kGroup != 0)
+            throw Fail{SMPQ_EINVAL, "reliable_interval must be 0 or a positive multiple of " + std::to_string(kGroup) +
+                                        " (the solver runs in groups of that many iterations)"};
         c->prec = prec;
         c->tol = tol;
         c->max_iter = max_iter;
         c->reliable = reliable;
         c->gen++;
+    });
+}
+
+smpq_status smpq_get_settings(const smpq_ctx *cc, smpq_settings *out) {
+    smpq_ctx *c = const_cast<smpq_ctx *>(cc);
+    return guarded(c, [&] {
+        if (!out) throw Fail{SMPQ_EINVAL, "null output"};
+        out->kappa = c->kappa;
+        out->precision = (int)c->prec;
+        out->tol = c->tol;
+        out->max_iter = c->max_iter;
+        out->reliable_interval = c->reliable;
+        out->gauge_hash = c->have_gauge ? c->gauge_hash : 0;
     });
 }
 

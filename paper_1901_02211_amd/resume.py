@@ -5,7 +5,9 @@ temporary file, then a rename); a later call with the same file continues after 
 finished chunk, on this or another machine.  The classes of a scheme cover disjoint sites, so
 the partial maps add up to the whole map exactly.
 
-The file also records the lattice, the scheme's colouring and the Zolotarev coefficients;
+The file also records a fingerprint of everything the map depends on: the lattice, the
+scheme's colouring, the Zolotarev coefficients, kappa, the solver's precision, tolerance,
+iteration limit and reliable-update interval, and a hash of the gauge field the context loaded;
 resuming with anything different raises ValueError.
 
 Command line (a time-boxed job that can be run again until the map is complete):
@@ -31,10 +33,14 @@ from . import binding as smpq
 def _fingerprint(ctx):
     col = smpq.smpq_get_coloring(ctx)
     c0, c, q, _ = smpq.smpq_get_zolotarev(ctx)
+    s = smpq.smpq_get_settings(ctx)
     h = hashlib.sha256()
     h.update(np.asarray(ctx.dims, dtype=np.int64).tobytes())
     h.update(col.tobytes())
     h.update(np.array([c0, *c, *q], dtype=np.float64).tobytes())
+    h.update(np.array([s["kappa"], s["tol"]], dtype=np.float64).tobytes())
+    h.update(np.array([s["precision"], s["max_iter"], s["reliable_interval"]], dtype=np.int64).tobytes())
+    h.update(np.array([s["gauge_hash"]], dtype=np.uint64).tobytes())
     return h.hexdigest()
 
 
@@ -43,7 +49,8 @@ _KEYS = ("qx", "qx_imag", "done", "fingerprint", "seconds", "iters")
 
 def compute_qx_resumable(ctx, path, chunk=64, stop_after=None, deadline=None, log=None, extra=None):
     """q(x) of every class of the context's scheme, chunk classes per call of the library.
-    Needs the scheme and the Zolotarev coefficients set (they are part of the fingerprint).
+    Needs the gauge field, the scheme, the Zolotarev coefficients and the solver settings set
+    (they are part of the fingerprint).
     stop_after: return after that many new chunks; deadline: a time.monotonic() value after
     which no new chunk starts.  Either leaves the map incomplete and returns None.  Returns
     (qx, qx_imag, Q) when complete.  log(k, classes, seconds, stats) is called after each chunk;
@@ -54,7 +61,8 @@ def compute_qx_resumable(ctx, path, chunk=64, stop_after=None, deadline=None, lo
     if os.path.exists(path):
         st = np.load(path)
         if str(st["fingerprint"]) != fp:
-            raise ValueError(f"{path} belongs to another lattice, scheme or set of coefficients")
+            raise ValueError(f"{path} belongs to another lattice, scheme, set of coefficients, gauge field, "
+                             f"kappa or solver setting")
         qx, qi, done = st["qx"].copy(), st["qx_imag"].copy(), st["done"].copy()
         secs = float(st["seconds"]) if "seconds" in st.files else 0.0
         iters = int(st["iters"]) if "iters" in st.files else 0

@@ -104,6 +104,13 @@ def test_argument_errors():
         smpq.smpq_set_zolotarev(c, 0, 0.1, 1.0)
     with pytest.raises(smpq.SmpqError):
         smpq.smpq_set_solver(c, smpq.SMPQ_FP64, 0.0, 10, 0)
+    for rel in (7, 25, -10):     # the solver checks every 10 iterations
+        with pytest.raises(smpq.SmpqError) as e:
+            smpq.smpq_set_solver(c, smpq.SMPQ_MIXED_FP32, 1e-12, 10, rel)
+        assert e.value.status == -1
+    for rel in (0, 10, 50, 100):
+        smpq.smpq_set_solver(c, smpq.SMPQ_MIXED_FP32, 1e-12, 10, rel)
+        assert smpq.smpq_get_settings(c)["reliable_interval"] == rel
     with pytest.raises(smpq.SmpqError) as e:
         smpq.smpq_autotune(c, -1)
     assert e.value.status == -1
@@ -172,8 +179,9 @@ def test_binding_layouts_match_the_header():
     """The ctypes structures and constants of the binding are the header's, field by field."""
     import ctypes
     src = _header()
-    ctype = {"double": ctypes.c_double, "int64_t": ctypes.c_int64, "int": ctypes.c_int}
-    for struct, cls in (("smpq_stats", smpq.SmpqStats), ("smpq_tuning", smpq.SmpqTuning)):
+    ctype = {"double": ctypes.c_double, "int64_t": ctypes.c_int64, "int": ctypes.c_int, "uint64_t": ctypes.c_uint64}
+    for struct, cls in (("smpq_stats", smpq.SmpqStats), ("smpq_tuning", smpq.SmpqTuning),
+                        ("smpq_settings", smpq.SmpqSettings)):
         want = [(n, ctype[t]) for n, t in _struct_fields(src, struct)]
         assert [(n, t) for n, t in cls._fields_] == want, struct
     for name, value in _enum_values(src, "smpq_precision").items():
