@@ -16,6 +16,9 @@ Jobs (each writes tests/golden/<job>.npz):
   flux24x48_part  24^3 x 48 flux (1,1) + noise 0.15 (seed 5): SMP r = 6, class 5 (12 of 15552).
   noise32x64_dov  32^3 x 64 (eps 0.3, seed 8): D_ov applied to one SMP r = 8 source (class 0,
                   spin 0, colour 0), kept on the 512 sites of the class and 64 seeded sites.
+  rough8_smp4_part  8^4 noise 0.3 (seed 60) with a Haar-random 3^4 block (isolated low modes of
+                  H_W), undeflated, on the narrow fixed interval [0.07, 2.62] (k = 0.027, the
+                  smallest shift q_1 ~ 3e-5 lam_max^2): SMP r = 4, classes 0, 85 and 170.
 
 Every job uses kappa = 0.21, 14 Zolotarev poles and CG tolerance 1e-12.  Up to 16^3 x 32 the
 interval is [0.9 sqrt(theta_min), 1.02 sqrt(theta_max)] from 300 Lanczos steps of the oracle
@@ -60,9 +63,10 @@ JOBS = {
     "noise24_part": ("noise24", ("smp", 6), [777], False),
     "flux24x48_part": ("flux24x48", ("smp", 6), [5], False),
     "noise32x64_dov": ("noise32x64", ("dov", 8), [0], False),
+    "rough8_smp4_part": ("rough8", ("smp", 4), [0, 85, 170], False),
 }
 FIXED_INTERVAL = {"noise16": (0.15, 2.75), "noise24": (0.15, 2.75), "flux24x48": (0.15, 2.75),
-                  "noise32x64": (0.15, 2.75)}
+                  "noise32x64": (0.15, 2.75), "rough8": (0.07, 2.62)}
 DOV_SAMPLE_SEED, DOV_SAMPLE_N = 9, 64
 
 _G = {}
