@@ -248,9 +248,9 @@ def timed_maps(one_map, steps, clock, reserve, estimate_s=None):
 SMALL_MAP = {"workload": "noise4", "label": "4^4 near-identity SU(3) eps=0.3 seed 0, SMP normal mode r=2 "
                                          "(192 sources), interval [0.13, 2.62]",
              "dims": [4, 4, 4, 4], "r": 2, "lo": 0.13, "hi": 2.62}
-FP64_OVER_MIXED = 2.4      # expected FP64 / mixed map time, for planning only (measured: 2.25)
-CPU_LEG_S = 75.0           # time allowed for the CPU leg
-EXTRAS_S = 25.0            # standalone stencil, copy, small-map and slack
+FP64_OVER_MIXED = 2.4      # expected FP64 / mixed map time, for planning only (measured: 2.23)
+CPU_LEG_S = 50.0           # time allowed for the CPU leg (measured: 15 s on 16 cores)
+EXTRAS_S = 20.0            # standalone stencil, copy, small-map and slack
 
 
 def main():

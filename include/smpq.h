@@ -98,6 +98,12 @@ typedef struct {
     double max_true_resid;       /* mixed precision: largest FP64 true residual
                                     ||b - (H^2 + q_1) x_1|| / ||b|| of the base system over the
                                     sources, taken after the solve (0 in FP64)              */
+    /* per-shift check (smpq_set_shift_check; 0 when off) */
+    double max_shift_resid;      /* largest FP64 ||b - (H^2 + q_i) x_i|| / ||b|| over sources
+                                    and shifts, after the multi-shift solve                 */
+    double max_shift_resid_final;/* the same after the refinement solves                    */
+    int64_t n_refined;           /* (source, shift) systems refined                         */
+    int64_t refine_iters;        /* CG iterations of the refinement solves (sum over sources) */
 } smpq_stats;
 
 /* Environment: SMPQ_TRACE (any value) when a context is created makes it print one line per
@@ -167,6 +173,22 @@ typedef struct {
 } smpq_settings;
 
 smpq_status smpq_get_settings(const smpq_ctx *ctx, smpq_settings *out);
+
+/* Per-shift check of the shifted solves (section 2.1, Eqs. 6-8: every shifted system
+ * M_i v_i = b is solved, not only the base system that the reliable updates correct).  With
+ * enable = 1 every multi-shift solve also accumulates each shift's own solution x_i in FP64
+ * and, after the solve, evaluates r_i = b - (H^2 + q_i) x_i in FP64 for every source and
+ * shift (smpq_stats.max_shift_resid = max ||r_i|| / ||b||).  Where ||r_i|| / ||b|| >
+ * refine_tol > 0, one refinement solve (H^2 + q_i) e = r_i runs in the context's precision
+ * (reliable updates included) until its residual is below refine_tol ||b|| / 2, and
+ * x_i += e, y += c_i e (max_shift_resid_final, n_refined, refine_iters).  refine_tol <= 0
+ * checks without refining.  Applies to q(x), D_ov and the trace of D_W^-1 solves, not to
+ * the inner solves of smpq_deflate.  Costs (n_poles + 2) FP64 vectors of device memory per
+ * right-hand side (batches shrink accordingly), FP64 x_i traffic in the update and two FP64
+ * stencils per shift after each batch.  The 16-bit direction precisions are refused
+ * (EINVAL when a solve starts).  Default: off.  EINVAL: enable not 0/1, refine_tol >= 1 or
+ * not finite. */
+smpq_status smpq_set_shift_check(smpq_ctx *ctx, int enable, double refine_tol);
 
 /* Upper bound on the right-hand sides resident on the device at once (0: automatic,
  * from free device memory).  Rounded down to a multiple of 12 when >= 12. */
@@ -333,11 +355,15 @@ smpq_status smpq_bench_copy(smpq_ctx *ctx, size_t bytes, int launches, double *m
  * (nx <= 64; f32_nr = 4, 8 or 16); 3 = kind 1 with the plane's x and y links in LDS instead
  * of registers, at 3 waves per SIMD.  plane_band (kinds 1-3; 1, 2 or 4, dividing nz): the
  * blocks take the (z, t) planes in bands of that many z with t running inside a band, so the
- * +-t neighbours of a plane were read shortly before (1 = z fastest).  f64_lgr: the FP64
- * stencil interleaves 2^f64_lgr = 1, 2 or 4 right-hand sides over the lanes of a block.
- * Results do not depend on the variant beyond the rounding order of FP32 sums. */
+ * +-t neighbours of a plane were read shortly before (1 = z fastest).  FP64 stencil:
+ * f64_kind 0 interleaves 2^f64_lgr = 1, 2 or 4 right-hand sides over the lanes of a block;
+ * f64_kind 1 stages xy-tiles in LDS as FP32 kind 2 does (one halo row on each side unless the
+ * tile is the whole plane), f64_nr = 2, 4 or 8 right-hand sides per block, the links read as
+ * their first two rows with the third rebuilt (where a tile fits; plane_band applies too).
+ * Results do not depend on the variant beyond the rounding order of sums. */
 typedef struct {
     int f32_kind, f32_nr, f64_lgr, plane_band;
+    int f64_kind, f64_nr;
 } smpq_tuning;
 
 /* Choose the variants for this lattice by timing each on n_rhs right-hand sides as the solver
@@ -348,7 +374,7 @@ typedef struct {
  * the variants' order can change with the number of right-hand sides through L2 reuse.  The choice is kept by the context and written to
  * *chosen (may be NULL); on an error the previous choice is kept.  Without this call a
  * context uses kind 1 / 8 where the plane fits, else kind 2 / 8 where a tile fits, else kind
- * 0 / 4, with plane_band 1 and f64_lgr 1. */
+ * 0 / 4, with plane_band 1, f64_kind 0 and f64_lgr 1. */
 smpq_status smpq_autotune(smpq_ctx *ctx, int n_rhs, smpq_tuning *chosen);
 
 /* Select the variants explicitly.  SMPQ_EINVAL (previous choice kept) if a variant is not

@@ -18,7 +18,7 @@ __all__ = [
     "SMPQ_FP64", "SMPQ_MIXED_FP32", "SMPQ_MIXED_FP16DIR", "SMPQ_MIXED_BF16DIR", "SmpqError", "SmpqStats", "SmpqTuning", "LIB_PATH", "EXPORTS",
     "smpq_create", "smpq_destroy", "smpq_strerror", "smpq_last_error", "smpq_load_gauge",
     "smpq_set_kappa", "smpq_lanczos", "smpq_estimate_bounds", "smpq_set_zolotarev",
-    "smpq_get_zolotarev", "smpq_set_solver", "smpq_get_settings", "SmpqSettings", "smpq_set_batch", "smpq_set_scheme",
+    "smpq_get_zolotarev", "smpq_set_solver", "smpq_get_settings", "SmpqSettings", "smpq_set_shift_check", "smpq_set_batch", "smpq_set_scheme",
     "smpq_set_point_scheme", "smpq_get_coloring", "smpq_get_scheme_rmin", "smpq_apply_dw", "smpq_apply_dov",
     "smpq_compute_qx", "smpq_compute_qx_classes", "smpq_compute_trinv", "smpq_dov_locality", "smpq_deflate", "smpq_compute_qx_points", "smpq_prepare", "smpq_set_stream",
     "smpq_set_timing", "smpq_set_graphs", "smpq_bench_dslash", "smpq_bench_copy", "smpq_autotune",
@@ -35,7 +35,7 @@ _vp = ctypes.c_void_p
 
 
 class SmpqTuning(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_int) for n in ("f32_kind", "f32_nr", "f64_lgr", "plane_band")]
+    _fields_ = [(n, ctypes.c_int) for n in ("f32_kind", "f32_nr", "f64_lgr", "plane_band", "f64_kind", "f64_nr")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -56,7 +56,9 @@ class SmpqStats(ctypes.Structure):
                                               "n_reliable_updates", "shift_updates")] + \
                [("dslash_ms", ctypes.c_double), ("dslash_bytes", ctypes.c_double), ("dslash_launches", ctypes.c_int64),
                 ("update_ms", ctypes.c_double), ("update_bytes", ctypes.c_double), ("update_launches", ctypes.c_int64),
-                ("max_true_resid", ctypes.c_double)]
+                ("max_true_resid", ctypes.c_double), ("max_shift_resid", ctypes.c_double),
+                ("max_shift_resid_final", ctypes.c_double), ("n_refined", ctypes.c_int64),
+                ("refine_iters", ctypes.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -75,6 +77,7 @@ _SIG = {
     "smpq_get_zolotarev": (ctypes.c_int, [_vp, _c_int_p, _c_double_p, _c_double_p, _c_double_p, _c_double_p]),
     "smpq_set_solver": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int]),
     "smpq_get_settings": (ctypes.c_int, [_vp, ctypes.POINTER(SmpqSettings)]),
+    "smpq_set_shift_check": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_double]),
     "smpq_set_batch": (ctypes.c_int, [_vp, ctypes.c_int]),
     "smpq_set_scheme": (ctypes.c_int, [_vp, _c_int_p, ctypes.c_int, _c_int_p, _c_int_p]),
     "smpq_set_point_scheme": (ctypes.c_int, [_vp, _c_int_p, _c_int_p]),
@@ -218,6 +221,10 @@ def smpq_get_settings(ctx):
     out = SmpqSettings()
     _check(ctx, _lib.smpq_get_settings(ctx.ptr, ctypes.byref(out)))
     return out.as_dict()
+
+
+def smpq_set_shift_check(ctx, enable=True, refine_tol=0.0):
+    _check(ctx, _lib.smpq_set_shift_check(ctx.ptr, int(enable), float(refine_tol)))
 
 
 def smpq_set_batch(ctx, max_rhs):
@@ -368,8 +375,8 @@ def smpq_autotune(ctx, n_rhs=48):
     return t.as_dict()
 
 
-def smpq_set_tuning(ctx, f32_kind, f32_nr, f64_lgr, plane_band=1):
-    t = SmpqTuning(int(f32_kind), int(f32_nr), int(f64_lgr), int(plane_band))
+def smpq_set_tuning(ctx, f32_kind, f32_nr, f64_lgr, plane_band=1, f64_kind=0, f64_nr=4):
+    t = SmpqTuning(int(f32_kind), int(f32_nr), int(f64_lgr), int(plane_band), int(f64_kind), int(f64_nr))
     _check(ctx, _lib.smpq_set_tuning(ctx.ptr, ctypes.byref(t)))
 
 

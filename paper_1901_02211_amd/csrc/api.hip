@@ -72,7 +72,9 @@ struct DevMem {
 // Device workspace of one batch of right-hand sides.
 struct Workspace {
     int prec = -1, NS = 0, B = 0;
-    DevMem r, tmp, ap, p, ph, y, x0, tmp64, ap64, yacc, x0acc;
+    bool check = false;   // laid out for the per-shift check (xs, rres, ysave)
+    DevMem r, tmp, p, ph, y, x0, tmp64, ap64, yacc, x0acc;
+    DevMem xs, rres, ysave, sums, flags;   // per-shift check: x_i, residuals, saved y
     DevMem st_d;   // doubles of the MSState
     DevMem st_i;   // ints of the MSState
     DevMem st_l;   // long longs of the MSState
@@ -141,7 +143,7 @@ struct smpq_ctx {
         double c0 = 0.0, s0 = 0.0;
         const double *c = nullptr, *delta = nullptr;
     };
-    Coef coef_eps, coef_inv;
+    Coef coef_eps, coef_inv, coef_ref;   // coef_ref: one shift of a refinement solve
     const Coef *coef = &coef_eps;
     const Coef *graph_coef = nullptr;   // the set the captured graphs were built with
     DevMem inv_cd;                      // {1, 0}: c and delta of the unshifted system
@@ -168,6 +170,11 @@ struct smpq_ctx {
     DevMem qx, qxi, lz;
     bool timing = false;
     bool use_graphs = true;
+    // per-shift FP64 true-residual check and mixed refinement (smpq_set_shift_check)
+    bool shift_check = false;
+    double refine_tol = 0.0;
+    bool refining = false;          // inside a refinement solve, which has no check of its own
+    double2 *cur_xs = nullptr;      // x_i accumulators of the solve in progress (check mode)
     bool trace = std::getenv("SMPQ_TRACE") != nullptr;   // one line per batch on stderr
     // captured groups of kGroup CG iterations, one per accumulation variant; rebuilt when
     // anything they capture (workspace, links, coefficients, solver settings) changes
@@ -180,10 +187,10 @@ struct smpq_ctx {
     long long gen = 0;
     int *h_count = nullptr;     // pinned
     // stencil variant (see Geom); defaults: plane tile where the xy-plane has 256 sites
-    int f32_kind = 0, f32_nr = 4, f64_lgr = 1, band = 1;
+    int f32_kind = 0, f32_nr = 4, f64_lgr = 1, band = 1, f64_kind = 0, f64_nr = 4;
     Geom geom() const {
         return Geom{dims[0], dims[1], dims[2], dims[3], V, vs, f32_kind, f32_nr, f64_lgr, band,
-                    tile_rows(dims[0], dims[1])};
+                    tile_rows(dims[0], dims[1]), f64_kind, f64_nr};
     }
 };
 
@@ -257,9 +264,13 @@ inline int dir_store(int prec) { return prec == 2 ? kDirF16 : prec == 3 ? kDirBF
 
 size_t bytes_per_slot(const smpq_ctx *c, int prec, int NS) {
     const size_t v64 = 12 * 16 * c->vs, v32 = 6 * 16 * c->vs, v16 = v32 / 2;
-    if (prec == 0) return (3 + NS) * v64 + v64;
-    if (dir_store(prec) != kDirF32) return 6 * v32 + NS * v16 + 4 * v64;
-    return (5 + NS) * v32 + 4 * v64;
+    // per-shift check: x_i for every shift, the residual and the saved y (+ tmp64 and ap64 in FP64)
+    const size_t check = c->shift_check ? (NS + 2) * v64 + (prec == 0 ? 2 * v64 : 0) : 0;
+    // r, tmp, the NS directions and y (+ in the FP32 path the running sums of y and x0, and the
+    // FP64 x0, tmp64 and ap64 of the reliable updates)
+    if (prec == 0) return (2 + NS) * v64 + v64 + check;
+    if (dir_store(prec) != kDirF32) return 5 * v32 + NS * v16 + 4 * v64 + check;
+    return (4 + NS) * v32 + 4 * v64 + check;
 }
 
 // Device workspace for at least B right-hand sides of the given precision and shift count.
@@ -270,16 +281,17 @@ void ensure_workspace(smpq_ctx *c, int prec, int NS, int B) {
     const Geom g = c->geom();
     const size_t v64 = 12 * 16 * c->vs, v32 = 6 * 16 * c->vs;
     const size_t vt = prec == 0 ? v64 : v32;
-    if (w.prec == prec && w.NS == NS && w.B >= B && w.S.rr) return;
+    if (w.prec == prec && w.NS == NS && w.B >= B && w.check == c->shift_check && w.S.rr) return;
     c->gen++;
-    w.r.release(); w.tmp.release(); w.ap.release(); w.p.release(); w.ph.release(); w.y.release();
+    w.r.release(); w.tmp.release(); w.p.release(); w.ph.release(); w.y.release();
     w.x0.release(); w.tmp64.release(); w.ap64.release(); w.yacc.release(); w.x0acc.release();
+    w.xs.release(); w.rres.release(); w.ysave.release();
     w.prec = prec;
     w.NS = NS;
     w.B = B;
+    w.check = c->shift_check;
     w.r.ensure(vt * B);
     w.tmp.ensure(vt * B);
-    w.ap.ensure(vt * B);
     if (dir_store(prec) != kDirF32) {
         w.p.ensure(vt * B);              // base directions
         w.ph.ensure(v32 / 2 * B * NS);   // shifted directions, 16 bits
@@ -294,8 +306,17 @@ void ensure_workspace(smpq_ctx *c, int prec, int NS, int B) {
         w.yacc.ensure(v32 * B);
         w.x0acc.ensure(v32 * B);
     }
+    if (w.check) {
+        w.xs.ensure(v64 * B * NS);
+        w.rres.ensure(v64 * B);
+        w.ysave.ensure(v64 * B);
+        w.tmp64.ensure(v64 * B);
+        w.ap64.ensure(v64 * B);
+        w.sums.ensure(sizeof(double) * B);
+        w.flags.ensure(sizeof(int) * B);
+    }
     const size_t pstride = partial_stride(g);
-    w.st_d.ensure(sizeof(double) * ((size_t)B * (5 + 3 * NS + 3 * NS + 3 * NS)));
+    w.st_d.ensure(sizeof(double) * ((size_t)B * (5 + 3 * NS + 4 * NS + 3 * NS)));
     w.st_i.ensure(sizeof(int) * ((size_t)B * (2 * NS + 4 + 2 * NS) + 16));
     w.st_l.ensure(sizeof(long long) * (size_t)B * 4);
     w.partial.ensure(sizeof(double) * (size_t)B * pstride);
@@ -317,6 +338,7 @@ void ensure_workspace(smpq_ctx *c, int prec, int NS, int B) {
     S.upd_cy = d; d += (size_t)B * NS;
     S.upd_zeta = d; d += (size_t)B * NS;
     S.upd_beta = d; d += (size_t)B * NS;
+    S.upd_ax = d; d += (size_t)B * NS;
     S.sh_scale = d; d += (size_t)B * NS;
     S.upd_sold = d; d += (size_t)B * NS;
     S.upd_snew = d; d += (size_t)B * NS;
@@ -346,8 +368,9 @@ void ensure_workspace(smpq_ctx *c, int prec, int NS, int B) {
 // Free the right-hand-side vectors of the workspace (the next ensure_workspace lays it out again).
 void release_workspace(smpq_ctx *c) {
     Workspace &w = c->ws;
-    w.r.release(); w.tmp.release(); w.ap.release(); w.p.release(); w.ph.release(); w.y.release();
+    w.r.release(); w.tmp.release(); w.p.release(); w.ph.release(); w.y.release();
     w.x0.release(); w.tmp64.release(); w.ap64.release(); w.yacc.release(); w.x0acc.release();
+    w.xs.release(); w.rres.release(); w.ysave.release();
     w.prec = -1;
     w.B = 0;
     w.S.rr = nullptr;
@@ -356,8 +379,8 @@ void release_workspace(smpq_ctx *c) {
 
 size_t workspace_bytes(const smpq_ctx *c) {
     const Workspace &w = c->ws;
-    return (size_t)w.r.bytes + w.tmp.bytes + w.ap.bytes + w.p.bytes + w.ph.bytes + w.y.bytes + w.x0.bytes + w.tmp64.bytes +
-           w.ap64.bytes + w.yacc.bytes + w.x0acc.bytes;
+    return (size_t)w.r.bytes + w.tmp.bytes + w.p.bytes + w.ph.bytes + w.y.bytes + w.x0.bytes + w.tmp64.bytes +
+           w.ap64.bytes + w.yacc.bytes + w.x0acc.bytes + w.xs.bytes + w.rres.bytes + w.ysave.bytes;
 }
 
 int choose_batch(smpq_ctx *c, int prec, int NS, int total_slots, bool multiple_of_12) {
@@ -415,7 +438,10 @@ struct BatchResult {
 
 // One CG iteration for every active slot of the batch (capacity-sized launches; inactive
 // slots exit at once).  y64 / x64 select FP64 or FP32-running-sum accumulation (FP32 path).
-// With timers, events bracket the two stencil launches and the update launch.
+// The first stencil, tmp = D_W p, also sums <p, (H^2 + s0) p> = |tmp|^2 + s0 |p|^2, so alpha is
+// known before the second, which updates r -= alpha (D_W^dag tmp + s0 p) in place with the
+// partials of |r|^2 (the product itself is never stored).  With timers, events bracket the two
+// stencil launches and the update launch.
 void enqueue_iteration(smpq_ctx *c, int prec, const MSState &S, bool y64, bool x64, GroupTimers *tm,
                        bool captured) {
     Workspace &w = c->ws;
@@ -427,24 +453,22 @@ void enqueue_iteration(smpq_ctx *c, int prec, const MSState &S, bool y64, bool x
     // the base direction: one of NS per slot, or (16-bit shifted directions) the only one
     const size_t pst = dir == kDirF32 ? NS * rs : rs, pofs = dir == kDirF32 ? S.i0 * rs : 0;
     const void *U = vp == 0 ? c->U64.p : c->U32.p;
-    const int np_unit = unit_parts(vp, g), np_ds = dslash_partials(vp, g);
+    const int np_ds = dslash_partials(vp, g);
     const bool mixed = prec >= 1;
     const Slots act{S.list, S.count, 0};
+    const double s0 = c->coef->s0;
     if (tm) tm->dslash.record(s, captured);
-    launch_dslash(vp, false, 0, U, w.p.p, pst, pofs, w.tmp.p, rs, nullptr, 0, 0, g, c->kappa, 0.0, act, B, nullptr, s);
-    if (tm) {
-        tm->dslash.record(s, captured);
-        tm->dslash.record(s, captured);
-    }
-    launch_dslash(vp, true, 1, U, w.tmp.p, rs, 0, w.ap.p, rs, w.p.p, pst, pofs, g, c->kappa, c->coef->s0, act, B,
-                  S.partial, s);
+    launch_dslash(vp, false, 3, U, w.p.p, pst, pofs, w.tmp.p, rs, nullptr, 0, 0, g, c->kappa, s0, act, B, S.partial, s);
     if (tm) tm->dslash.record(s, captured);
     launch_scalars_alpha(S, np_ds, s);
-    launch_r_update(vp, g, S, w.r.p, w.ap.p, s);
-    launch_scalars_beta(S, np_unit, s);
+    if (tm) tm->dslash.record(s, captured);
+    launch_dslash(vp, true, 2, U, w.tmp.p, rs, 0, w.r.p, rs, w.p.p, pst, pofs, g, c->kappa, s0, act, B, S.partial, s,
+                  S.alpha, S.status);
+    if (tm) tm->dslash.record(s, captured);
+    launch_scalars_beta(S, np_ds, s);
     if (tm) tm->update.record(s, captured);
     launch_shift_update(vp, g, S, w.r.p, w.p.p, y64 ? w.y.p : w.yacc.p, y64,
-                        mixed ? (x64 ? w.x0.p : w.x0acc.p) : nullptr, x64, dir, w.ph.p, s);
+                        mixed ? (x64 ? w.x0.p : w.x0acc.p) : nullptr, x64, dir, w.ph.p, c->cur_xs, s);
     if (tm) tm->update.record(s, captured);
     launch_compact(S, s);
 }
@@ -516,10 +540,15 @@ GroupTimers *launch_group(smpq_ctx *c, int prec, const MSState &S, int it0) {
 
 // Multi-shift CG for the first nslots slots of the workspace, sources from src.
 // On return y[slot] = c_0 b + sum_i c_i x_i (Eq. 4 without the leading H).
+void check_shifts(smpq_ctx *c, int prec, int nslots, const Source &src, smpq_stats *st);
+
 BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq_stats *st) {
     Workspace &w = c->ws;
     MSState S = w.S;
     S.B = w.B;           // launches are sized for the workspace capacity; slots >= nslots start done
+    // a solve may use fewer shifts than the workspace holds (a refinement solves one)
+    if (c->coef->n > w.NS) throw Fail{SMPQ_ESTATE, "workspace laid out for fewer shifts than the solve"};
+    S.NS = c->coef->n;
     S.i0 = 0;            // q ascending: the smallest shift is the base system
     S.tol = c->tol;
     S.c = c->coef->c;
@@ -534,6 +563,13 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
     const Slots act{S.list, S.count, 0};
     const bool mixed = prec >= 1;
 
+    const bool check = c->shift_check && !c->refining;
+    if (check && !w.check) throw Fail{SMPQ_ESTATE, "workspace laid out without the per-shift check"};
+    if (check && dir != kDirF32)
+        throw Fail{SMPQ_EINVAL, "the per-shift check needs SMPQ_FP64 or SMPQ_MIXED_FP32"};
+    if (check) HIPCHK(hipMemsetAsync(w.xs.p, 0, (size_t)nslots * NS * rs64 * sizeof(double2), s));
+    // the graphs capture this pointer: a change of check mode or refinement bumps c->gen
+    c->cur_xs = check ? w.xs.as<double2>() : nullptr;
     launch_cg_init(vp, g, src, nslots, NS, c->coef->c0, w.r.p, w.p.p, w.y.as<double2>(), mixed ? w.yacc.p : nullptr,
                    mixed ? w.x0.as<double2>() : nullptr, mixed ? w.x0acc.p : nullptr, S.partial, dir, s);
     launch_scalars_init(S, np_unit, nslots, s);
@@ -595,6 +631,7 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
         for (int k = 0; k < nslots; ++k)
             res.max_true_resid = std::max(res.max_true_resid, std::sqrt(rr[k]) / bn[k]);
     }
+    c->cur_xs = nullptr;
     std::vector<int> status(nslots), iters(nslots);
     std::vector<long long> ent(nslots), pup(nslots), actv(nslots), bpup(nslots);
     HIPCHK(hipMemcpy(status.data(), S.status, sizeof(int) * nslots, hipMemcpyDeviceToHost));
@@ -620,11 +657,12 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
         // slot-iteration) is stored like r, 16-bit shifted directions take 4
         const double s_dir = dir == kDirF32 ? s_t : 4.0;
         const double V = c->V;
-        // algorithmic bytes: D_W reads links once and each input/output spinor once; the
-        // second stencil also reads p for the "+ s0 p" term.  Per active slot-iteration.
-        // every slot starts at iteration 0, so iterations_max launches carried work
+        // algorithmic bytes: each stencil reads the links once and each input spinor once; the
+        // first writes tmp, the second reads p for the "+ s0 p" term and reads and writes r.
+        // Six vector passes per active slot-iteration; every slot starts at iteration 0, so
+        // iterations_max launches carried work.
         const double launched = (double)res.iters_max;
-        st->dslash_bytes += launched * 2.0 * link_site * V + (double)res.active * V * 12.0 * s_t * 5.0;
+        st->dslash_bytes += launched * 2.0 * link_site * V + (double)res.active * V * 12.0 * s_t * 6.0;
         st->dslash_launches += 2LL * res.iters_max;
         // update kernel: r read, the running sum read+write and, in the FP32 path, the running
         // base solution read+write (both in the iteration precision), every listed p_i read,
@@ -651,7 +689,111 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
         st->max_true_resid = std::max(st->max_true_resid, res.max_true_resid);
         st->shift_updates += res.entries;
     }
+    if (check) check_shifts(c, prec, nslots, src, st);
     return res;
+}
+
+// Every shift's FP64 true residual ||b - (H^2 + q_i) x_i|| / ||b|| for the first nslots slots
+// of the solve just finished (x_i accumulated in FP64 beside y); shifts above refine_tol get one
+// refinement solve (H^2 + q_i) e = b - (H^2 + q_i) x_i in the solve's precision, from the FP64
+// residual, and x_i += e, y += c_i e.  Each shifted system of Eqs. 6-8 is thereby held to its
+// own FP64 residual, not only the base system of the reliable updates.
+void check_shifts(smpq_ctx *c, int prec, int nslots, const Source &src, smpq_stats *st) {
+    Workspace &w = c->ws;
+    const Geom g = c->geom();
+    hipStream_t s = c->stream;
+    const smpq_ctx::Coef coef = *c->coef;
+    const smpq_ctx::Coef *coef_ptr = c->coef;
+    const int NS = coef.n;
+    const size_t rs64 = 12 * c->vs;
+    const size_t vbytes = rs64 * sizeof(double2);
+    const size_t pstride = partial_stride(g);
+    const int np = unit_parts(0, g);
+    if (!c->inv_cd.p) {
+        const double cd[2] = {1.0, 0.0};
+        c->inv_cd.ensure(sizeof(cd));
+        HIPCHK(hipMemcpy(c->inv_cd.p, cd, sizeof(cd), hipMemcpyHostToDevice));
+    }
+    std::vector<double> ch(NS), dh(NS), bn(nslots);
+    HIPCHK(hipMemcpyAsync(ch.data(), coef.c, sizeof(double) * NS, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(dh.data(), coef.delta, sizeof(double) * NS, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(bn.data(), w.S.bnorm, sizeof(double) * nslots, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(w.ysave.p, w.y.p, vbytes * nslots, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const Slots all{nullptr, nullptr, nslots};
+    std::vector<double> rr(nslots);
+    auto resid = [&](int i, std::vector<double> &out) {
+        double2 *xi = w.xs.as<double2>() + (size_t)i * rs64;
+        launch_dslash(0, false, 0, c->U64.p, xi, NS * rs64, 0, w.tmp64.p, rs64, nullptr, 0, 0, g, c->kappa, 0.0, all,
+                      nslots, nullptr, s);
+        launch_dslash(0, true, 1, c->U64.p, w.tmp64.p, rs64, 0, w.ap64.p, rs64, xi, NS * rs64, 0, g, c->kappa,
+                      coef.s0 + dh[i], all, nslots, w.S.partial, s);
+        launch_resid64(g, nslots, src, w.ap64.as<double2>(), w.rres.as<double2>(), w.S.partial, pstride, s);
+        launch_slot_sums(nslots, w.S.partial, pstride, np, w.sums.as<double>(), s);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(rr.data(), w.sums.p, sizeof(double) * nslots, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        out.assign(nslots, 0.0);
+        for (int k = 0; k < nslots; ++k) out[k] = bn[k] > 0.0 ? std::sqrt(rr[k]) / bn[k] : 0.0;
+    };
+    const double tol_main = c->tol;
+    std::vector<double> before, after;
+    std::vector<int> flag(nslots);
+    for (int i = 0; i < NS; ++i) {
+        resid(i, before);
+        double mx = 0.0, rho = 0.0;
+        int nref = 0;
+        for (int k = 0; k < nslots; ++k) {
+            mx = std::max(mx, before[k]);
+            flag[k] = c->refine_tol > 0.0 && before[k] > c->refine_tol;
+            if (flag[k]) {
+                ++nref;
+                rho = std::max(rho, before[k]);
+            }
+        }
+        if (st) st->max_shift_resid = std::max(st->max_shift_resid, mx);
+        if (nref == 0) {
+            if (st) st->max_shift_resid_final = std::max(st->max_shift_resid_final, mx);
+            continue;
+        }
+        HIPCHK(hipMemcpyAsync(w.flags.p, flag.data(), sizeof(int) * nslots, hipMemcpyHostToDevice, s));
+        launch_zero_unflagged(g, nslots, w.flags.as<int>(), w.rres.as<double2>(), s);
+        // (H^2 + q_i) e = r_i: one shift of coefficient 1 and no constant term; the residual
+        // must fall below refine_tol |b|, i.e. by refine_tol / rho relative to r_i
+        c->coef_ref = smpq_ctx::Coef{1, 0.0, coef.s0 + dh[i], c->inv_cd.as<double>(), c->inv_cd.as<double>() + 1};
+        c->coef = &c->coef_ref;
+        c->tol = std::min(0.5, std::max(tol_main, 0.5 * c->refine_tol / rho));
+        c->refining = true;
+        c->gen++;
+        const Source rsrc{nullptr, nullptr, nullptr, w.rres.as<double2>()};
+        smpq_stats rst{};
+        BatchResult rb;
+        try {
+            rb = run_batch(c, prec, nslots, rsrc, &rst);
+        } catch (...) {
+            c->coef = coef_ptr;
+            c->tol = tol_main;
+            c->refining = false;
+            c->gen++;
+            throw;
+        }
+        c->coef = coef_ptr;
+        c->tol = tol_main;
+        c->refining = false;
+        c->gen++;
+        launch_refine_acc(g, nslots, w.y.as<double2>(), ch[i], w.ysave.as<double2>(),
+                          w.xs.as<double2>() + (size_t)i * rs64, NS * rs64, s);
+        resid(i, after);
+        double mf = 0.0;
+        for (int k = 0; k < nslots; ++k) mf = std::max(mf, after[k]);
+        if (st) {
+            st->max_shift_resid_final = std::max(st->max_shift_resid_final, mf);
+            st->n_refined += nref;
+            st->refine_iters += rb.iters_sum;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(w.y.p, w.ysave.p, vbytes * nslots, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
 }
 
 void ensure_scheme_device(smpq_ctx *c) {
@@ -812,14 +954,17 @@ void deflate(smpq_ctx *c, int k, int steps, double *theta_out, double *tmax_out,
         smpq_ctx *c;
         smpq_precision prec;
         double tol;
+        bool check;
         ~Keep() {
             c->prec = prec;
             c->tol = tol;
+            c->shift_check = check;
             use_coef(c, false);
         }
-    } keep{c, c->prec, c->tol};
+    } keep{c, c->prec, c->tol, c->shift_check};
     c->prec = SMPQ_FP64;
     c->tol = 1e-14;
+    c->shift_check = false;   // the inner solves are single-shift FP64 solves to 1e-14
     use_coef(c, true);
     ensure_workspace(c, 0, 1, c->ws.prec == 0 && c->ws.NS == 1 ? c->ws.B : 1);
     auto inverse = [&](const double2 *q, double2 *o) {
@@ -1032,43 +1177,81 @@ std::vector<int> class_list(const smpq_ctx *c, const int32_t *classes, int n) {
     return cls;
 }
 
+// Buffers of the stencil timings: n_sets disjoint (input, output[, aux]) sets of n_rhs vectors
+// and link copies, allocated and cleared once and kept while the layout (precision, sets,
+// right-hand sides, pair) stays the same, so that an autotuning sweep does not allocate per
+// candidate.
+struct StencilBench {
+    int p = -1, n_rhs = 0, n_sets = 0;
+    bool pair = false;
+    std::vector<DevMem> vecs, links;
+    DevMem part, alpha, status;   // pair: the partials, alpha = 0 and status OK per right-hand side
+};
+
 // Mean duration of the stencil (D_W, epilogue 0) on n_rhs right-hand sides, rotating through
 // n_sets disjoint input/output/link sets; *bytes = algorithmic bytes per launch.  With pair, one
-// timed unit is the solver's pair D_W then D_W^dag + sigma (epilogue 1, with its partial sums),
-// and *bytes covers both launches.
-double time_dslash(smpq_ctx *c, int p, int n_rhs, int n_sets, int launches, double *bytes, bool pair = false) {
+// timed unit is the solver's pair: D_W with the <p, (H^2 + sigma) p> partials (epilogue 3), then
+// D_W^dag + sigma with the in-place residual update (epilogue 2, alpha = 0 so r keeps its
+// values but is read and written), and *bytes covers both launches.  n_rhs is lowered where the
+// buffers would take more than half of the free device memory.
+double time_dslash(smpq_ctx *c, StencilBench &tb, int p, int n_rhs, int n_sets, int launches, double *bytes,
+                   bool pair = false) {
     const Geom g = c->geom();
     const size_t units = p == 0 ? 12 : 6;
     const size_t vbytes = units * 16 * c->vs;
     const size_t lbytes = (size_t)c->V * (p == 0 ? 72 * 8 : 48 * 4);
-    const int nvec = pair ? 3 : 2;
-    // at most half of the free device memory: fewer right-hand sides if need be
-    size_t freeb = 0, totalb = 0;
-    HIPCHK(hipMemGetInfo(&freeb, &totalb));
-    const size_t per_rhs = nvec * vbytes * n_sets + (pair ? sizeof(double) * partial_stride(g) : 0);
-    if (freeb / 2 < lbytes * n_sets + per_rhs) throw Fail{SMPQ_ENOMEM, "not enough device memory to time the stencil"};
-    n_rhs = (int)std::min<size_t>(n_rhs, (freeb / 2 - lbytes * n_sets) / per_rhs);
-    std::vector<DevMem> vecs((size_t)nvec * n_sets), links(n_sets);
-    DevMem part;
-    if (pair) part.ensure(sizeof(double) * partial_stride(g) * n_rhs);
-    for (int k = 0; k < n_sets; ++k) {
-        for (int v = 0; v < nvec; ++v) {
-            vecs[(size_t)k * nvec + v].ensure(vbytes * n_rhs);
-            HIPCHK(hipMemsetAsync(vecs[(size_t)k * nvec + v].p, 0, vbytes * n_rhs, c->stream));
+    const int nvec = pair ? 3 : 2;   // pair: p, tmp, r
+    if (!(tb.p == p && tb.n_sets == n_sets && tb.pair == pair && tb.n_rhs > 0 && tb.n_rhs <= n_rhs)) {
+        tb.vecs.clear();
+        tb.links.clear();
+        tb.part.release();
+        tb.alpha.release();
+        tb.status.release();
+        tb.p = -1;
+        size_t freeb = 0, totalb = 0;
+        HIPCHK(hipMemGetInfo(&freeb, &totalb));
+        const size_t per_rhs = nvec * vbytes * n_sets + (pair ? sizeof(double) * partial_stride(g) : 0);
+        if (freeb / 2 < lbytes * n_sets + per_rhs)
+            throw Fail{SMPQ_ENOMEM, "not enough device memory to time the stencil"};
+        const int fit = (int)std::min<size_t>(n_rhs, (freeb / 2 - lbytes * n_sets) / per_rhs);
+        tb.vecs = std::vector<DevMem>((size_t)nvec * n_sets);
+        tb.links = std::vector<DevMem>(n_sets);
+        if (pair) {
+            tb.part.ensure(sizeof(double) * partial_stride(g) * fit);
+            tb.alpha.ensure(sizeof(double) * fit);
+            tb.status.ensure(sizeof(int) * fit);
+            HIPCHK(hipMemsetAsync(tb.alpha.p, 0, sizeof(double) * fit, c->stream));
+            HIPCHK(hipMemsetAsync(tb.status.p, 0, sizeof(int) * fit, c->stream));   // kStatusOK
         }
-        links[k].ensure(lbytes);
-        HIPCHK(hipMemcpyAsync(links[k].p, p == 0 ? c->U64.p : c->U32.p, lbytes, hipMemcpyDeviceToDevice, c->stream));
+        for (int k = 0; k < n_sets; ++k) {
+            for (int v = 0; v < nvec; ++v) {
+                tb.vecs[(size_t)k * nvec + v].ensure(vbytes * fit);
+                HIPCHK(hipMemsetAsync(tb.vecs[(size_t)k * nvec + v].p, 0, vbytes * fit, c->stream));
+            }
+            tb.links[k].ensure(lbytes);
+            HIPCHK(hipMemcpyAsync(tb.links[k].p, p == 0 ? c->U64.p : c->U32.p, lbytes, hipMemcpyDeviceToDevice,
+                                  c->stream));
+        }
+        tb.p = p;
+        tb.n_rhs = fit;
+        tb.n_sets = n_sets;
+        tb.pair = pair;
     }
+    n_rhs = std::min(n_rhs, tb.n_rhs);
     Slots sl{nullptr, nullptr, n_rhs};
     const size_t st = units * c->vs;
     auto one = [&](int i) {
         const int k = i % n_sets;
-        void *a = vecs[(size_t)k * nvec].p, *b = vecs[(size_t)k * nvec + 1].p;
-        launch_dslash(p, false, 0, links[k].p, a, st, 0, b, st, nullptr, 0, 0, g, c->kappa, 0.0, sl, n_rhs, nullptr,
-                      c->stream);
-        if (pair)
-            launch_dslash(p, true, 1, links[k].p, b, st, 0, vecs[(size_t)k * nvec + 2].p, st, a, st, 0, g, c->kappa,
-                          0.1, sl, n_rhs, part.as<double>(), c->stream);
+        void *a = tb.vecs[(size_t)k * nvec].p, *b = tb.vecs[(size_t)k * nvec + 1].p;
+        if (!pair) {
+            launch_dslash(p, false, 0, tb.links[k].p, a, st, 0, b, st, nullptr, 0, 0, g, c->kappa, 0.0, sl, n_rhs,
+                          nullptr, c->stream);
+            return;
+        }
+        launch_dslash(p, false, 3, tb.links[k].p, a, st, 0, b, st, nullptr, 0, 0, g, c->kappa, 0.1, sl, n_rhs,
+                      tb.part.as<double>(), c->stream);
+        launch_dslash(p, true, 2, tb.links[k].p, b, st, 0, tb.vecs[(size_t)k * nvec + 2].p, st, a, st, 0, g, c->kappa,
+                      0.1, sl, n_rhs, tb.part.as<double>(), c->stream, tb.alpha.as<double>(), tb.status.as<int>());
     };
     for (int i = 0; i < n_sets; ++i) one(i);   // warm-up
     hipEvent_t e0, e1;
@@ -1085,7 +1268,7 @@ double time_dslash(smpq_ctx *c, int p, int n_rhs, int n_sets, int launches, doub
     HIPCHK(hipGetLastError());
     const double u = p == 0 ? 16.0 : 8.0;
     *bytes = (double)c->V * ((double)lbytes / c->V + (double)n_rhs * 24.0 * u);
-    if (pair) *bytes = 2.0 * *bytes + (double)c->V * n_rhs * 24.0 * u;
+    if (pair) *bytes = 2.0 * *bytes + (double)c->V * n_rhs * 2.0 * 24.0 * u;
     return t / launches;
 }
 
@@ -1316,6 +1499,17 @@ smpq_status smpq_get_settings(const smpq_ctx *cc, smpq_settings *out) {
         out->max_iter = c->max_iter;
         out->reliable_interval = c->reliable;
         out->gauge_hash = c->have_gauge ? c->gauge_hash : 0;
+    });
+}
+
+smpq_status smpq_set_shift_check(smpq_ctx *c, int enable, double refine_tol) {
+    return guarded(c, [&] {
+        if (enable != 0 && enable != 1) throw Fail{SMPQ_EINVAL, "enable must be 0 or 1"};
+        if (!std::isfinite(refine_tol) || refine_tol >= 1.0)
+            throw Fail{SMPQ_EINVAL, "refine_tol must be finite and below 1 (<= 0: check only)"};
+        c->shift_check = enable == 1;
+        c->refine_tol = refine_tol;
+        c->gen++;
     });
 }
 
@@ -1791,7 +1985,8 @@ smpq_status smpq_bench_dslash(smpq_ctx *c, smpq_precision prec, int n_rhs, int n
         if (prec != SMPQ_FP64 && prec != SMPQ_MIXED_FP32) throw Fail{SMPQ_EINVAL, "unknown precision"};
         need_device(c);
         if (!c->have_gauge) throw Fail{SMPQ_ESTATE, "no gauge field loaded"};
-        *ms = time_dslash(c, prec == SMPQ_FP64 ? 0 : 1, n_rhs, n_sets, launches, bytes);
+        StencilBench tb;
+        *ms = time_dslash(c, tb, prec == SMPQ_FP64 ? 0 : 1, n_rhs, n_sets, launches, bytes);
     });
 }
 
@@ -1828,12 +2023,16 @@ smpq_status smpq_set_tuning(smpq_ctx *c, const smpq_tuning *t) {
         g.f32_nr = t->f32_nr;
         g.f64_lgr = t->f64_lgr;
         g.band = t->plane_band;
+        g.f64_kind = t->f64_kind;
+        g.f64_nr = t->f64_nr;
         if (!valid_tuning(0, g) || !valid_tuning(1, g))
             throw Fail{SMPQ_EINVAL, "unsupported stencil variant for this lattice"};
         c->f32_kind = t->f32_kind;
         c->f32_nr = t->f32_nr;
         c->f64_lgr = t->f64_lgr;
         c->band = t->plane_band;
+        c->f64_kind = t->f64_kind;
+        c->f64_nr = t->f64_nr;
         c->gen++;
     });
 }
@@ -1841,7 +2040,7 @@ smpq_status smpq_set_tuning(smpq_ctx *c, const smpq_tuning *t) {
 smpq_status smpq_get_tuning(smpq_ctx *c, smpq_tuning *t) {
     return guarded(c, [&] {
         if (!t) throw Fail{SMPQ_EINVAL, "null tuning"};
-        *t = smpq_tuning{c->f32_kind, c->f32_nr, c->f64_lgr, c->band};
+        *t = smpq_tuning{c->f32_kind, c->f32_nr, c->f64_lgr, c->band, c->f64_kind, c->f64_nr};
     });
 }
 
@@ -1867,16 +2066,17 @@ smpq_status smpq_autotune(smpq_ctx *c, int n_rhs, smpq_tuning *chosen) {
                 for (int band : {1, 2, 4})
                     if (c->dims[2] % band == 0) cand.push_back({kind, nr, band});
         }
-        const smpq_tuning keep{c->f32_kind, c->f32_nr, c->f64_lgr, c->band};
+        const smpq_tuning keep{c->f32_kind, c->f32_nr, c->f64_lgr, c->band, c->f64_kind, c->f64_nr};
         double best = INFINITY;
         Cand pick{keep.f32_kind, keep.f32_nr, keep.plane_band};
+        StencilBench tb;   // one set of timing buffers per precision for the whole sweep
         try {
             for (const Cand &k : cand) {
                 c->f32_kind = k.kind;
                 c->f32_nr = k.nr;
                 c->band = k.band;
-                const double t = std::min(time_dslash(c, 1, n_rhs, 2, 10, &by, true),
-                                          time_dslash(c, 1, n_rhs, 2, 10, &by, true));
+                const double t = std::min(time_dslash(c, tb, 1, n_rhs, 2, 10, &by, true),
+                                          time_dslash(c, tb, 1, n_rhs, 2, 10, &by, true));
                 if (t < best) {
                     best = t;
                     pick = k;
@@ -1885,27 +2085,41 @@ smpq_status smpq_autotune(smpq_ctx *c, int n_rhs, smpq_tuning *chosen) {
             c->f32_kind = pick.kind;
             c->f32_nr = pick.nr;
             c->band = pick.band;
+            // FP64: lanes interleaving 1, 2 or 4 right-hand sides; xy-tiles with 2, 4 or 8 per
+            // block (same plane order band as the FP32 choice) where a tile fits
             best = INFINITY;
-            int lpick = keep.f64_lgr;
-            for (int l = 0; l <= 2; ++l) {
-                c->f64_lgr = l;
-                const double t = std::min(time_dslash(c, 0, n_rhs, 2, 10, &by, true),
-                                          time_dslash(c, 0, n_rhs, 2, 10, &by, true));
+            struct Cand64 {
+                int kind, lgr, nr;
+            };
+            std::vector<Cand64> c64 = {{0, 0, 4}, {0, 1, 4}, {0, 2, 4}};
+            if (g0.tile_y > 0 && c->dims[2] % c->band == 0)
+                for (int nr : {2, 4, 8}) c64.push_back({1, keep.f64_lgr, nr});
+            Cand64 p64{keep.f64_kind, keep.f64_lgr, keep.f64_nr};
+            for (const Cand64 &k : c64) {
+                c->f64_kind = k.kind;
+                c->f64_lgr = k.lgr;
+                c->f64_nr = k.nr;
+                const double t = std::min(time_dslash(c, tb, 0, n_rhs, 2, 10, &by, true),
+                                          time_dslash(c, tb, 0, n_rhs, 2, 10, &by, true));
                 if (t < best) {
                     best = t;
-                    lpick = l;
+                    p64 = k;
                 }
             }
-            c->f64_lgr = lpick;
+            c->f64_kind = p64.kind;
+            c->f64_lgr = p64.lgr;
+            c->f64_nr = p64.nr;
         } catch (...) {
             c->f32_kind = keep.f32_kind;
             c->f32_nr = keep.f32_nr;
             c->f64_lgr = keep.f64_lgr;
             c->band = keep.plane_band;
+            c->f64_kind = keep.f64_kind;
+            c->f64_nr = keep.f64_nr;
             throw;
         }
         c->gen++;   // captured graphs used the previous variants
-        if (chosen) *chosen = smpq_tuning{c->f32_kind, c->f32_nr, c->f64_lgr, c->band};
+        if (chosen) *chosen = smpq_tuning{c->f32_kind, c->f32_nr, c->f64_lgr, c->band, c->f64_kind, c->f64_nr};
     });
 }
 

@@ -21,8 +21,11 @@ struct Geom {
     // thread, 1: 16x16 xy-plane per block in LDS, 2: xy-tile of tile_y rows with y-halos in
     // LDS), FP32 right-hand sides per thread, log2 of the right-hand sides interleaved over the
     // lanes of an FP64 block, and the z-band of the plane order of kinds 1 and 2;
-    // tile_y = tile_rows(nx, ny) (0 when no tile fits)
+    // tile_y = tile_rows(nx, ny) (0 when no tile fits); FP64 kernel kind (0: right-hand sides
+    // interleaved over the lanes, 2^f64_lgr per block; 1: xy-tiles in LDS like the FP32 kind 2,
+    // f64_nr right-hand sides per block, links read per right-hand side)
     int f32_kind, f32_nr, f64_lgr, band, tile_y;
+    int f64_kind, f64_nr;
 };
 
 // Right-hand-side addressing: slot k of a launch uses offset (slot * slot_stride + extra)
@@ -44,6 +47,7 @@ struct MSState {
     int *done, *iters, *status;
     int *upd_n, *upd_idx, *upd_pupd;
     double *upd_cy, *upd_zeta, *upd_beta;
+    double *upd_ax;      // alpha^i of each update-list entry (0 for a converged base entry)
     // 16-bit shifted directions: p_i is stored as p_i / sh_scale[slot NS + i]; per update-list
     // entry the scale that decodes the stored direction and the reciprocal of the new one
     double *sh_scale, *upd_sold, *upd_snew;
@@ -69,14 +73,19 @@ struct Source {
 
 enum { kStatusOK = 0, kStatusBreakdown = 1 };
 
-// out = in - kappa * hop(in)  [epi = 0]
-// out = in - kappa * hop(in) + sigma * aux, partial[slot][block] = Re <aux, out>  [epi = 1]
-// prec: 0 = FP64, 1 = FP32.  dag selects D_W^dag.  The kernel variant comes from g's tuning
-// fields; the epilogue writes dslash_partials(prec, g) partials per slot.
+// With d = in - kappa * hop(in) (D_W in, or D_W^dag in when dag):
+//   epi 0: out = d
+//   epi 1: out = d + sigma * aux, partial[slot][block] = Re <aux, out>
+//   epi 3: out = d, partial = |d|^2 + sigma |in|^2   (= <in, (H^2 + sigma) in> when dag = 0)
+//   epi 2: out holds r; r -= alpha[slot] (d + sigma * aux) unless status[slot] is not OK;
+//          partial = |r|^2 (the product d + sigma aux is not stored)
+// prec: 0 = FP64, 1 = FP32 (FP32: epi 0 both ways, epi 3 with dag = 0, epi 1 and 2 with
+// dag = 1).  The kernel variant comes from g's tuning fields; epilogues 1-3 write
+// dslash_partials(prec, g) partials per slot.
 void launch_dslash(int prec, bool dag, int epi, const void *U, const void *in, size_t in_stride,
                    size_t in_extra, void *out, size_t out_stride, const void *aux, size_t aux_stride,
                    size_t aux_extra, const Geom &g, double kappa, double sigma, Slots sl, int max_slots,
-                   double *partial, hipStream_t st);
+                   double *partial, hipStream_t st, const double *alpha = nullptr, const int *status = nullptr);
 __host__ __device__ int site_blocks(const Geom &g);   // blocks of 256 sites
 int dslash_partials(int prec, const Geom &g);         // partials per slot of the stencil epilogue
 bool plane_tileable(const Geom &g);
@@ -102,13 +111,14 @@ void launch_cg_init(int prec, const Geom &g, const Source &src, int nslots, int 
 void launch_dir16_init(const Geom &g, const MSState &s, int nslots, const void *r, int dir, void *ph, hipStream_t st);
 void launch_scalars_init(const MSState &s, int npart, int nslots, hipStream_t st);
 void launch_scalars_alpha(const MSState &s, int npart, hipStream_t st);
-void launch_r_update(int prec, const Geom &g, const MSState &s, void *r, const void *ap, hipStream_t st);
 void launch_scalars_beta(const MSState &s, int npart, hipStream_t st);
 // Shift update.  yt receives sum_i c_i alpha^i p_i: the FP64 y when y64, else a running sum in
 // the storage precision of p.  xt (FP32 path only, else null) receives alpha p_base: the FP64
-// x0 when x64, else a running sum.  The FP64 path always uses y64 (and no xt).
+// x0 when x64, else a running sum.  The FP64 path always uses y64 (and no xt).  xs (null, or
+// FP64 vectors [slot][NS][12][vs], FP32 directions only) receives every shift's own solution,
+// x_i += alpha^i p_i, for the per-shift true-residual check.
 void launch_shift_update(int prec, const Geom &g, const MSState &s, const void *r, void *p, void *yt, bool y64,
-                         void *xt, bool x64, int dir, void *ph, hipStream_t st);
+                         void *xt, bool x64, int dir, void *ph, double2 *xs, hipStream_t st);
 // FP32 path: y += yacc, yacc = 0 (and x0 += x0acc, x0acc = 0 when x0acc is not null)
 void launch_fold(const Geom &g, Slots sl, int max_slots, double2 *y, void *yacc, double2 *x0, void *x0acc,
                  hipStream_t st);
@@ -116,6 +126,18 @@ void launch_compact(const MSState &s, hipStream_t st);
 void launch_reliable(int prec, const Geom &g, const MSState &s, const Source &src, const double2 *ap64,
                      void *r, hipStream_t st);
 void launch_scalars_rr(const MSState &s, int npart, hipStream_t st);
+
+// Per-shift check (FP64 vectors, slot stride 12 vs, the first nslots slots):
+// resid64: out = b - ap64 (b from src), partial[slot][block] = |out|^2 (unit_parts(0, g) blocks);
+// slot_sums: sums[slot] = sum of the slot's npart partials (fixed order);
+// zero_unflagged: v[slot] = 0 where flag[slot] == 0;
+// refine_acc: ysave[slot] += c e[slot], xsi[slot] += e[slot] (xsi slot stride xs_stride units).
+void launch_resid64(const Geom &g, int nslots, const Source &src, const double2 *ap64, double2 *out,
+                    double *partial, size_t pstride, hipStream_t st);
+void launch_slot_sums(int nslots, const double *partial, size_t pstride, int npart, double *sums, hipStream_t st);
+void launch_zero_unflagged(const Geom &g, int nslots, const int *flag, double2 *v, hipStream_t st);
+void launch_refine_acc(const Geom &g, int nslots, const double2 *e, double c, double2 *ysave, double2 *xsi,
+                       size_t xs_stride, hipStream_t st);
 
 // Low-mode deflation helpers (FP64 vectors [12][vs]).  multi_dot: out[i] = <q_i, w> for
 // q_i = Q + i qstride, i < nq (partial: 2 nq unit_parts doubles); multi_axpy: w -= sum h_i q_i,

@@ -8,8 +8,10 @@
 //                  k_dslash_f32_tile: xy-tiles of any width <= 64 with halo rows); all take an
 //                  optional epilogue "+ sigma aux" with a fused <aux, out> partial for
 //                  H^2 + sigma (Eq. 4).
-//  k_cg_init ...   multi-shift CG for (D_W^dag D_W + q_i) x_i = b (Eqs. 6-8): residual
-//                  update, fused update of every active shift's search direction plus the
+//  k_cg_init ...   multi-shift CG for (D_W^dag D_W + q_i) x_i = b (Eqs. 6-8): the stencil
+//                  epilogues sum <p, A p> = |D_W p|^2 + s0 |p|^2 in the first stencil and
+//                  update the residual in place in the second; fused update of every active
+//                  shift's search direction plus the
 //                  running rational sum y = c_0 b + sum_i c_i x_i, scalar recurrences on the
 //                  device (one wave per right-hand side), FP64 residual replacement.
 //  k_contract      q(x) += 1/2 [gamma5 D_ov phi](x, alpha, a) on the probed sites (Eq. 16), or
@@ -26,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include <stdexcept>
+#include <type_traits>
 
 #include "kernels.h"
 #include "wilson_site.h"
@@ -51,6 +54,15 @@ struct Store<double> {
     __device__ static __forceinline__ void store(double2 *p, size_t vs, int s, const cpx<double> v[12]) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) p[c * vs + s] = make_double2(v[c].re, v[c].im);
+    }
+    // a vector read once by the kernel (non-temporal)
+    __device__ static __forceinline__ void load_stream(const double2 *p, size_t vs, int s, cpx<double> v[12]) {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const d2 t = __builtin_nontemporal_load(reinterpret_cast<const d2 *>(p + c * vs + s));
+            v[c] = {t.x, t.y};
+        }
     }
     // the stencil's output: written once, read by the next kernel (non-temporal)
     __device__ static __forceinline__ void store_stream(double2 *p, size_t vs, int s, const cpx<double> v[12]) {
@@ -80,6 +92,16 @@ struct Store<float> {
 #pragma unroll
         for (int k = 0; k < 6; ++k)
             p[k * vs + s] = make_float4(v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im);
+    }
+    // a vector read once by the kernel (non-temporal)
+    __device__ static __forceinline__ void load_stream(const float4 *p, size_t vs, int s, cpx<float> v[12]) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const f4 t = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(p + k * vs + s));
+            v[2 * k] = {t.x, t.y};
+            v[2 * k + 1] = {t.z, t.w};
+        }
     }
     // the stencil's output: written once, read by the next kernel (non-temporal)
     __device__ static __forceinline__ void store_stream(float4 *p, size_t vs, int s, const cpx<float> v[12]) {
@@ -159,6 +181,96 @@ __device__ __forceinline__ double wave_sum_partials(const double *p, int n) {
 __device__ __forceinline__ int slot_of(const Slots &sl, int k) { return sl.list ? sl.list[k] : k; }
 __device__ __forceinline__ int slot_count(const Slots &sl) { return sl.count ? *sl.count : sl.n; }
 
+// One storage unit of a spinor: FP64 one complex (double2), FP32 two complexes (float4).
+__device__ __forceinline__ void unit_load(const double2 *p, size_t vs, int k, int s, cpx<double> v[1]) {
+    const double2 t = p[k * vs + s];
+    v[0] = {t.x, t.y};
+}
+__device__ __forceinline__ void unit_load(const float4 *p, size_t vs, int k, int s, cpx<float> v[2]) {
+    const float4 t = p[k * vs + s];
+    v[0] = {t.x, t.y};
+    v[1] = {t.z, t.w};
+}
+__device__ __forceinline__ void unit_load_stream(const double2 *p, size_t vs, int k, int s, cpx<double> v[1]) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 t = __builtin_nontemporal_load(reinterpret_cast<const d2 *>(p + k * vs + s));
+    v[0] = {t.x, t.y};
+}
+__device__ __forceinline__ void unit_load_stream(const float4 *p, size_t vs, int k, int s, cpx<float> v[2]) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 t = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(p + k * vs + s));
+    v[0] = {t.x, t.y};
+    v[1] = {t.z, t.w};
+}
+__device__ __forceinline__ void unit_store_stream(double2 *p, size_t vs, int k, int s, const cpx<double> v[1]) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 t = {v[0].re, v[0].im};
+    __builtin_nontemporal_store(t, reinterpret_cast<d2 *>(p + k * vs + s));
+}
+__device__ __forceinline__ void unit_store_stream(float4 *p, size_t vs, int k, int s, const cpx<float> v[2]) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 t = {v[0].re, v[0].im, v[1].re, v[1].im};
+    __builtin_nontemporal_store(t, reinterpret_cast<f4 *>(p + k * vs + s));
+}
+
+// ------------------------------------------------------------------ stencil epilogues
+// At one site, d = [D in](s) (D_W, or D_W^dag) and self = in(s):
+//   EPI 0  out = d
+//   EPI 1  out = d + sigma aux;                         returns Re <aux, out>(s)
+//   EPI 3  out = d;                                     returns |d|^2 + sigma |self|^2
+//   EPI 2  a = d + sigma aux, not stored; out, which holds the residual r, becomes r - alpha a;
+//          returns |r - alpha a|^2 (a slot whose status is not OK keeps r: alpha is taken as 0)
+// In a CG iteration on H^2 + sigma (D_W^dag D_W + sigma) the first stencil D_W p with EPI 3
+// yields <p, (H^2 + sigma) p> = |D_W p|^2 + sigma |p|^2, so alpha is known before the second
+// stencil, which with EPI 2 updates r directly and never writes (H^2 + sigma) p.  The vectors
+// are read and written one storage unit at a time, so that few extra registers are live.
+template <class T, int EPI>
+__device__ __forceinline__ double stencil_epilogue(cpx<T> d[12], const cpx<T> self[12],
+                                                   const typename Store<T>::vec *aux,
+                                                   typename Store<T>::vec *out, size_t vs, int s, T sigma,
+                                                   T alpha, bool ok) {
+    constexpr int UN = Store<T>::units, CU = 12 / UN;   // units per spinor, complexes per unit
+    double acc = 0.0;
+    if constexpr (EPI == 2) {
+        if (!ok) alpha = T(0);   // a broken-down slot keeps its residual (written back unchanged)
+    }
+#pragma unroll
+    for (int k = 0; k < UN; ++k) {
+        cpx<T> *dk = d + k * CU;
+        if constexpr (EPI == 1 || EPI == 2) {
+            cpx<T> a[CU];
+            unit_load(aux, vs, k, s, a);
+#pragma unroll
+            for (int j = 0; j < CU; ++j) {
+                dk[j] = dk[j] + sigma * a[j];
+                if constexpr (EPI == 1)
+                    acc += (double)a[j].re * (double)dk[j].re + (double)a[j].im * (double)dk[j].im;
+            }
+        }
+        if constexpr (EPI == 2) {
+            cpx<T> r[CU];
+            unit_load_stream(out, vs, k, s, r);
+#pragma unroll
+            for (int j = 0; j < CU; ++j) {
+                r[j] = r[j] - alpha * dk[j];
+                acc += (double)r[j].re * (double)r[j].re + (double)r[j].im * (double)r[j].im;
+            }
+            unit_store_stream(out, vs, k, s, r);
+        } else {
+            if constexpr (EPI == 3) {
+#pragma unroll
+                for (int j = 0; j < CU; ++j) {
+                    const cpx<T> e = self[k * CU + j];
+                    acc += (double)dk[j].re * (double)dk[j].re + (double)dk[j].im * (double)dk[j].im +
+                           (double)sigma * ((double)e.re * (double)e.re + (double)e.im * (double)e.im);
+                }
+            }
+            unit_store_stream(out, vs, k, s, dk);
+        }
+    }
+    return acc;
+}
+
 // ------------------------------------------------------------------ Wilson stencil
 // One right-hand side per thread.  A block of 256 threads covers 256/R consecutive sites
 // times R right-hand sides, with the right-hand side in the low bits of the thread index:
@@ -199,7 +311,8 @@ __global__ __launch_bounds__(kBlock) void k_dslash(const typename Store<T>::link
                                                    size_t out_stride, const typename Store<T>::vec *__restrict__ aux,
                                                    size_t aux_stride, size_t aux_extra, Geom g, T kappa, T sigma,
                                                    Slots sl, int lgR, int nsb, double *__restrict__ partial,
-                                                   size_t pstride) {
+                                                   size_t pstride, const double *__restrict__ alpha,
+                                                   const int *__restrict__ status) {
     const int R = 1 << lgR;
     const int L = xcd_swizzle(blockIdx.x, gridDim.x);
     const int sb = L % nsb, rg = L / nsb;
@@ -214,22 +327,15 @@ __global__ __launch_bounds__(kBlock) void k_dslash(const typename Store<T>::link
         const auto *src = in + slot * in_stride + in_extra;
         cpx<T> acc[12];
         hop_site<T, DAG ? -1 : 1>(U, g, src, s, acc);
-        cpx<T> v[12];
-        Store<T>::load(src, g.vs, s, v);
+        cpx<T> self[12], v[12];
+        Store<T>::load(src, g.vs, s, self);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) v[c] = v[c] - kappa * acc[c];
-        if constexpr (EPI == 1) {
-            cpx<T> a[12];
-            Store<T>::load(aux + slot * aux_stride + aux_extra, g.vs, s, a);
-#pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                v[c] = v[c] + sigma * a[c];
-                dot += (double)a[c].re * (double)v[c].re + (double)a[c].im * (double)v[c].im;
-            }
-        }
-        Store<T>::store_stream(out + slot * out_stride, g.vs, s, v);
+        for (int c = 0; c < 12; ++c) v[c] = self[c] - kappa * acc[c];
+        dot = stencil_epilogue<T, EPI>(v, self, aux + slot * aux_stride + aux_extra, out + slot * out_stride, g.vs, s,
+                                       sigma, EPI == 2 ? (T)alpha[slot] : T(0),
+                                       EPI == 2 ? status[slot] == kStatusOK : true);
     }
-    if constexpr (EPI == 1) {
+    if constexpr (EPI != 0) {
         // lanes with equal (lane mod R) hold the same right-hand side
         for (int off = 32; off >= R; off >>= 1) dot += __shfl_xor(dot, off);
         __shared__ double lds[kBlock / 64][8];
@@ -258,7 +364,8 @@ __global__ __launch_bounds__(kBlock) void k_dslash_f32(const float4 *__restrict_
                                                        size_t out_stride, const float4 *__restrict__ aux,
                                                        size_t aux_stride, size_t aux_extra, Geom g, float kappa,
                                                        float sigma, Slots sl, int nsb, double *__restrict__ partial,
-                                                       size_t pstride) {
+                                                       size_t pstride, const double *__restrict__ alpha,
+                                                       const int *__restrict__ status) {
     constexpr int SF = DAG ? -1 : 1;
     const int L = xcd_swizzle(blockIdx.x, gridDim.x);
     const int sb = L % nsb, rg = L / nsb;
@@ -309,22 +416,14 @@ __global__ __launch_bounds__(kBlock) void k_dslash_f32(const float4 *__restrict_
         SMPQ_HOP(3)
 #undef SMPQ_HOP
         cpx<float> v[12];
-        Store<float>::load(src, g.vs, sv, v);
+        Store<float>::load(src, g.vs, sv, p);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) v[c] = v[c] - kappa * acc[c];
-        if constexpr (EPI == 1) {
-            Store<float>::load(aux + slot * aux_stride + aux_extra, g.vs, sv, p);
-            double d = 0.0;
-#pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                v[c] = v[c] + sigma * p[c];
-                d += (double)p[c].re * (double)v[c].re + (double)p[c].im * (double)v[c].im;
-            }
-            dot[r] = d;
-        }
-        Store<float>::store_stream(out + slot * out_stride, g.vs, sv, v);
+        for (int c = 0; c < 12; ++c) v[c] = p[c] - kappa * acc[c];
+        dot[r] = stencil_epilogue<float, EPI>(v, p, aux + slot * aux_stride + aux_extra, out + slot * out_stride, g.vs,
+                                              sv, sigma, EPI == 2 ? (float)alpha[slot] : 0.f,
+                                              EPI == 2 ? status[slot] == kStatusOK : true);
     }
-    if constexpr (EPI == 1) {
+    if constexpr (EPI != 0) {
         __shared__ double lds[NR][kBlock / 64];
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -354,7 +453,8 @@ __global__ __launch_bounds__(kBlock) void k_dslash_f32_tile(const float4 *__rest
                                                             const float4 *__restrict__ aux, size_t aux_stride,
                                                             size_t aux_extra, Geom g, float kappa, float sigma,
                                                             Slots sl, int nsb, double *__restrict__ partial,
-                                                            size_t pstride) {
+                                                            size_t pstride, const double *__restrict__ alpha,
+                                                            const int *__restrict__ status) {
     constexpr int SF = DAG ? -1 : 1;
     constexpr int kTileSites = kBlock + 2 * 64;
     __shared__ float4 tile[6][kTileSites];
@@ -443,23 +543,15 @@ __global__ __launch_bounds__(kBlock) void k_dslash_f32_tile(const float4 *__rest
         SMPQ_TILE_HOP(1, yf, yb)
 #undef SMPQ_TILE_HOP
         cpx<float> v[12];
-        SMPQ_TILE_LOAD(me, v)
+        SMPQ_TILE_LOAD(me, p)
 #undef SMPQ_TILE_LOAD
 #pragma unroll
-        for (int c = 0; c < 12; ++c) v[c] = v[c] - kappa * acc[c];
-        if constexpr (EPI == 1) {
-            Store<float>::load(aux + slot * aux_stride + aux_extra, g.vs, s, p);
-            double d = 0.0;
-#pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                v[c] = v[c] + sigma * p[c];
-                d += (double)p[c].re * (double)v[c].re + (double)p[c].im * (double)v[c].im;
-            }
-            dot[r] = d;
-        }
-        Store<float>::store_stream(out + slot * out_stride, g.vs, s, v);
+        for (int c = 0; c < 12; ++c) v[c] = p[c] - kappa * acc[c];
+        dot[r] = stencil_epilogue<float, EPI>(v, p, aux + slot * aux_stride + aux_extra, out + slot * out_stride, g.vs,
+                                              s, sigma, EPI == 2 ? (float)alpha[slot] : 0.f,
+                                              EPI == 2 ? status[slot] == kStatusOK : true);
     }
-    if constexpr (EPI == 1) {
+    if constexpr (EPI != 0) {
         __shared__ double lds[NR][kBlock / 64];
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         const int nw = blockDim.x >> 6;
@@ -484,7 +576,8 @@ __device__ __forceinline__ void dslash_f32_plane_body(const float4 *__restrict__
                                                              const float4 *__restrict__ aux, size_t aux_stride,
                                                              size_t aux_extra, Geom g, float kappa, float sigma,
                                                              Slots sl, int nsb, double *__restrict__ partial,
-                                                             size_t pstride) {
+                                                             size_t pstride, const double *__restrict__ alpha,
+                                                             const int *__restrict__ status) {
     constexpr int SF = DAG ? -1 : 1;
     __shared__ float4 tile[6][kBlock];
     // XYL: the plane's x and y links in LDS (the backward ones are the neighbours' forward
@@ -513,7 +606,7 @@ __device__ __forceinline__ void dslash_f32_plane_body(const float4 *__restrict__
     const int xf = nb.fwd[0] - base, xb = nb.bwd[0] - base, yf = nb.fwd[1] - base, yb = nb.bwd[1] - base;
     // EPI 1: per right-hand side, the block's <aux, out> is summed per wave at once and the
     // wave sums kept in LDS (no accumulators held across the loop)
-    __shared__ double ldsdot[EPI == 1 ? NR : 1][kBlock / 64];
+    __shared__ double ldsdot[EPI != 0 ? NR : 1][kBlock / 64];
     [[maybe_unused]] const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll 1
     for (int r = 0; r < NR; ++r) {
@@ -566,24 +659,19 @@ __device__ __forceinline__ void dslash_f32_plane_body(const float4 *__restrict__
         SMPQ_TILE_HOP(1, yf, yb)
 #undef SMPQ_TILE_HOP
         cpx<float> v[12];
-        SMPQ_TILE_LOAD(threadIdx.x, v)
+        SMPQ_TILE_LOAD(threadIdx.x, p)
 #undef SMPQ_TILE_LOAD
 #pragma unroll
-        for (int c = 0; c < 12; ++c) v[c] = v[c] - kappa * acc[c];
-        if constexpr (EPI == 1) {
-            Store<float>::load(aux + slot * aux_stride + aux_extra, g.vs, s, p);
-            double d = 0.0;
-#pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                v[c] = v[c] + sigma * p[c];
-                d += (double)p[c].re * (double)v[c].re + (double)p[c].im * (double)v[c].im;
-            }
+        for (int c = 0; c < 12; ++c) v[c] = p[c] - kappa * acc[c];
+        double d = stencil_epilogue<float, EPI>(v, p, aux + slot * aux_stride + aux_extra, out + slot * out_stride,
+                                                g.vs, s, sigma, EPI == 2 ? (float)alpha[slot] : 0.f,
+                                                EPI == 2 ? status[slot] == kStatusOK : true);
+        if constexpr (EPI != 0) {
             d = wave_sum(d);
             if (lane == 0) ldsdot[r][wv] = d;
         }
-        Store<float>::store_stream(out + slot * out_stride, g.vs, s, v);
     }
-    if constexpr (EPI == 1) {
+    if constexpr (EPI != 0) {
         __syncthreads();
         if ((int)threadIdx.x < NR && k0 + (int)threadIdx.x < cnt) {
             double t = 0.0;
@@ -602,9 +690,10 @@ __global__ __launch_bounds__(kBlock) void k_dslash_f32_plane(const float4 *__res
                                                              const float4 *__restrict__ aux, size_t aux_stride,
                                                              size_t aux_extra, Geom g, float kappa, float sigma,
                                                              Slots sl, int nsb, double *__restrict__ partial,
-                                                             size_t pstride) {
+                                                             size_t pstride, const double *__restrict__ alpha,
+                                                             const int *__restrict__ status) {
     dslash_f32_plane_body<NR, DAG, EPI, false>(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra,
-                                               g, kappa, sigma, sl, nsb, partial, pstride);
+                                               g, kappa, sigma, sl, nsb, partial, pstride, alpha, status);
 }
 
 // The same with the x and y links in LDS, at 3 waves per SIMD.
@@ -612,9 +701,146 @@ template <int NR, bool DAG, int EPI>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_dslash_f32_plane_xyl(
     const float4 *__restrict__ U, const float4 *__restrict__ in, size_t in_stride, size_t in_extra,
     float4 *__restrict__ out, size_t out_stride, const float4 *__restrict__ aux, size_t aux_stride, size_t aux_extra,
-    Geom g, float kappa, float sigma, Slots sl, int nsb, double *__restrict__ partial, size_t pstride) {
+    Geom g, float kappa, float sigma, Slots sl, int nsb, double *__restrict__ partial, size_t pstride,
+    const double *__restrict__ alpha, const int *__restrict__ status) {
     dslash_f32_plane_body<NR, DAG, EPI, true>(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra,
-                                              g, kappa, sigma, sl, nsb, partial, pstride);
+                                              g, kappa, sigma, sl, nsb, partial, pstride, alpha, status);
+}
+
+// FP64 stencil on xy-tiles, the data flow of the FP32 tile kernel in FP64: a block of nx * ty
+// threads (ty = g.tile_y rows of one (z, t) plane, one site per thread) stages, per right-hand
+// side, its rows of the input in LDS (with one halo row on each side, unless the tile is the
+// whole plane and y wraps inside it), so that the +-x and +-y neighbours come from LDS and only
+// +-z and +-t from global memory.  Links: the first two rows of each FP64 link (96 bytes), the
+// third rebuilt as conj(row0 x row1) (exact for SU(3) up to rounding); they are read for every
+// right-hand side and stay in L2 across the block's NR right-hand sides.
+__device__ __forceinline__ void load_link64_rows(const double2 *U, int V, int mu, int s, cpx<double> u[9]) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double2 t = U[(size_t)(mu * 9 + k) * V + s];
+        u[k] = {t.x, t.y};
+    }
+    const cpx<double> r0 = cmul(u[1], u[5]) - cmul(u[2], u[4]);
+    const cpx<double> r1 = cmul(u[2], u[3]) - cmul(u[0], u[5]);
+    const cpx<double> r2 = cmul(u[0], u[4]) - cmul(u[1], u[3]);
+    u[6] = {r0.re, -r0.im};
+    u[7] = {r1.re, -r1.im};
+    u[8] = {r2.re, -r2.im};
+}
+
+template <int NR, bool DAG, int EPI>
+__global__ __launch_bounds__(kBlock) void k_dslash_f64_tile(const double2 *__restrict__ U,
+                                                            const double2 *__restrict__ in, size_t in_stride,
+                                                            size_t in_extra, double2 *__restrict__ out,
+                                                            size_t out_stride, const double2 *__restrict__ aux,
+                                                            size_t aux_stride, size_t aux_extra, Geom g, double kappa,
+                                                            double sigma, Slots sl, int nsb,
+                                                            double *__restrict__ partial, size_t pstride,
+                                                            const double *__restrict__ alpha,
+                                                            const int *__restrict__ status) {
+    constexpr int SF = DAG ? -1 : 1;
+    extern __shared__ double2 tile64[];   // [12][tsites]
+    const int L = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int sb = L % nsb, rg = L / nsb;
+    const int cnt = slot_count(sl);
+    const int k0 = rg * NR;
+    if (k0 >= cnt) return;  // uniform over the block
+    const int nx = g.nx, ny = g.ny, ty = g.tile_y;
+    const bool whole = ty == ny;             // the tile is the plane: y wraps inside it
+    const int rows = whole ? ty : ty + 2;    // tile rows held in LDS
+    const int tsites = rows * nx;
+    const int tiles_per_plane = ny / ty;
+    const int pl = plane_order(sb / tiles_per_plane, g), y0 = (sb % tiles_per_plane) * ty;
+    const int x = threadIdx.x % nx, yl = threadIdx.x / nx;
+    const int plane0 = pl * nx * ny;
+    const int s = plane0 + (y0 + yl) * nx + x;   // every site is valid: V is a multiple of the tile
+    const Nbr nb = neighbours(s, nx, ny, g.nz, g.nt);
+    // LDS row of tile row yl: shifted by the lower halo row when there is one
+    const int off = whole ? 0 : 1;
+    const int me = (yl + off) * nx + x;
+    const int xf = (yl + off) * nx + (x == nx - 1 ? 0 : x + 1);
+    const int xb = (yl + off) * nx + (x == 0 ? nx - 1 : x - 1);
+    const int yf = whole ? ((yl + 1) % ty) * nx + x : me + nx;
+    const int yb = whole ? ((yl + ty - 1) % ty) * nx + x : me - nx;
+    const bool halo = !whole && (int)threadIdx.x < 2 * nx;
+    const int hrow = threadIdx.x < (unsigned)nx ? 0 : ty + 1;
+    const int hy = threadIdx.x < (unsigned)nx ? (y0 + ny - 1) % ny : (y0 + ty) % ny;
+    const int hsite = plane0 + hy * nx + x;
+    const int hl = hrow * nx + x;
+    __shared__ double ldsdot[EPI != 0 ? NR : 1][kBlock / 64];
+    [[maybe_unused]] const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+#pragma unroll 1
+    for (int r = 0; r < NR; ++r) {
+        const int k = k0 + r;
+        if (k >= cnt) break;  // uniform over the block
+        const int slot = slot_of(sl, k);
+        const double2 *src = in + slot * in_stride + in_extra;
+        // the links are re-read for every right-hand side: kept across the loop (as the compiler
+        // would hoist them) eight FP64 links need 192 registers; an empty asm makes the base
+        // pointer opaque in each iteration
+        const double2 *Ur = U;
+        asm volatile("" : "+s"(Ur));
+        __syncthreads();  // the previous right-hand side is done with the tile
+#pragma unroll
+        for (int j = 0; j < 12; ++j) tile64[j * tsites + me] = src[j * g.vs + s];
+        if (halo) {
+#pragma unroll
+            for (int j = 0; j < 12; ++j) tile64[j * tsites + hl] = src[j * g.vs + hsite];
+        }
+        __builtin_amdgcn_sched_barrier(0);   // the staging loads are not held across the hops
+        cpx<double> acc[12], u[9], p[12], h[6], w[6];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) acc[c] = {0.0, 0.0};
+#define SMPQ_HOP64(MU, LOADF, LOADB)                                                 \
+        load_link64_rows(Ur, g.V, MU, s, u);                                         \
+        LOADF                                                                        \
+        project<MU, SF>(p, h);                                                       \
+        su3_mul(u, h, w);                                                            \
+        accumulate<MU, SF>(acc, w);                                                  \
+        load_link64_rows(Ur, g.V, MU, nb.bwd[MU], u);                                \
+        LOADB                                                                        \
+        project<MU, -SF>(p, h);                                                      \
+        su3_dag_mul(u, h, w);                                                        \
+        accumulate<MU, -SF>(acc, w);
+#define SMPQ_G64(S_) Store<double>::load(src, g.vs, S_, p);
+#define SMPQ_T64(L_)                                                                 \
+        _Pragma("unroll") for (int j = 0; j < 12; ++j) {                             \
+            const double2 t_ = tile64[j * tsites + (L_)];                            \
+            p[j] = {t_.x, t_.y};                                                     \
+        }
+        // one direction at a time: loads of later directions hoisted above earlier ones would hold
+        // more FP64 links and spinors in registers than two waves per SIMD allow
+        SMPQ_HOP64(2, SMPQ_G64(nb.fwd[2]), SMPQ_G64(nb.bwd[2]))
+        __builtin_amdgcn_sched_barrier(0);
+        SMPQ_HOP64(3, SMPQ_G64(nb.fwd[3]), SMPQ_G64(nb.bwd[3]))
+        __syncthreads();  // the tile is complete
+        SMPQ_HOP64(0, SMPQ_T64(xf), SMPQ_T64(xb))
+        __builtin_amdgcn_sched_barrier(0);
+        SMPQ_HOP64(1, SMPQ_T64(yf), SMPQ_T64(yb))
+        cpx<double> v[12];
+        SMPQ_T64(me)
+#undef SMPQ_T64
+#undef SMPQ_G64
+#undef SMPQ_HOP64
+#pragma unroll
+        for (int c = 0; c < 12; ++c) v[c] = p[c] - kappa * acc[c];
+        double d = stencil_epilogue<double, EPI>(v, p, aux + slot * aux_stride + aux_extra, out + slot * out_stride,
+                                                 g.vs, s, sigma, EPI == 2 ? alpha[slot] : 0.0,
+                                                 EPI == 2 ? status[slot] == kStatusOK : true);
+        if constexpr (EPI != 0) {
+            d = wave_sum(d);
+            if (lane == 0) ldsdot[r][wv] = d;
+        }
+    }
+    if constexpr (EPI != 0) {
+        __syncthreads();
+        if ((int)threadIdx.x < NR && k0 + (int)threadIdx.x < cnt) {
+            double t = 0.0;
+            for (int i = 0; i < nw; ++i) t += ldsdot[threadIdx.x][i];
+            partial[(size_t)slot_of(sl, k0 + threadIdx.x) * pstride + sb] = t;
+        }
+    }
 }
 
 __host__ __device__ int site_blocks(const Geom &g) { return (g.V + kBlock - 1) / kBlock; }
@@ -632,12 +858,17 @@ int tile_rows(int nx, int ny) {
 static int tile_blocks(const Geom &g) { return g.V / (g.nx * g.tile_y); }
 
 int dslash_partials(int prec, const Geom &g) {
-    if (prec == 0) return fp64_parts(g);
+    if (prec == 0) return g.f64_kind == 1 ? tile_blocks(g) : fp64_parts(g);
     return g.f32_kind == 2 ? tile_blocks(g) : site_blocks(g);
 }
 
 bool valid_tuning(int prec, const Geom &g) {
-    if (prec == 0) return g.f64_lgr >= 0 && g.f64_lgr <= 2;
+    if (prec == 0) {
+        if (g.f64_kind == 1)
+            return g.tile_y > 0 && g.tile_y == tile_rows(g.nx, g.ny) && g.band >= 1 && g.nz % g.band == 0 &&
+                   (g.f64_nr == 2 || g.f64_nr == 4 || g.f64_nr == 8);
+        return g.f64_kind == 0 && g.f64_lgr >= 0 && g.f64_lgr <= 2;
+    }
     const bool nr_tile = g.f32_nr == 4 || g.f32_nr == 8 || g.f32_nr == 16;
     if (g.f32_kind == 1 || g.f32_kind == 3) return plane_tileable(g) && nr_tile && g.band >= 1 && g.nz % g.band == 0;
     const bool tiled = g.tile_y > 0 && g.tile_y == tile_rows(g.nx, g.ny);
@@ -646,55 +877,86 @@ bool valid_tuning(int prec, const Geom &g) {
     return g.f32_kind == 0 && (g.f32_nr == 2 || g.f32_nr == 4 || g.f32_nr == 8);
 }
 
+template <int NR, bool DAG, int EPI>
+static void launch_f64_tile(const void *U, const void *in, size_t in_stride, size_t in_extra, void *out,
+                            size_t out_stride, const void *aux, size_t aux_stride, size_t aux_extra, const Geom &g,
+                            double kappa, double sigma, Slots sl, int max_slots, double *partial, const double *alpha,
+                            const int *status, hipStream_t st) {
+    const int nsb = tile_blocks(g);
+    const int ngr = (max_slots + NR - 1) / NR;
+    const int rows = g.tile_y == g.ny ? g.tile_y : g.tile_y + 2;
+    const size_t lds = (size_t)rows * g.nx * 12 * sizeof(double2);
+    hipLaunchKernelGGL((k_dslash_f64_tile<NR, DAG, EPI>), dim3(nsb * ngr), dim3(g.nx * g.tile_y), lds, st,
+                       (const double2 *)U, (const double2 *)in, in_stride, in_extra, (double2 *)out, out_stride,
+                       (const double2 *)aux, aux_stride, aux_extra, g, kappa, sigma, sl, nsb, partial,
+                       partial_stride(g), alpha, status);
+}
+
 template <class T, bool DAG, int EPI>
 static void launch_dslash_t(const void *U, const void *in, size_t in_stride, size_t in_extra, void *out,
                             size_t out_stride, const void *aux, size_t aux_stride, size_t aux_extra, const Geom &g,
-                            double kappa, double sigma, Slots sl, int max_slots, double *partial, hipStream_t st) {
+                            double kappa, double sigma, Slots sl, int max_slots, double *partial, const double *alpha,
+                            const int *status, hipStream_t st) {
     using vec = typename Store<T>::vec;
     using link = typename Store<T>::link;
+    if constexpr (std::is_same<T, double>::value) {
+        if (g.f64_kind == 1) {
+#define SMPQ_F64T(NR)                                                                                             \
+    launch_f64_tile<NR, DAG, EPI>(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra, g, kappa, \
+                                  sigma, sl, max_slots, partial, alpha, status, st)
+            if (g.f64_nr == 2) SMPQ_F64T(2);
+            else if (g.f64_nr == 8) SMPQ_F64T(8);
+            else SMPQ_F64T(4);
+#undef SMPQ_F64T
+            return;
+        }
+    }
     const int lgR = g.f64_lgr;
     const int R = 1 << lgR;
     const int nsb = fp64_parts(g);
     const int ngr = (max_slots + R - 1) / R;
     hipLaunchKernelGGL((k_dslash<T, DAG, EPI>), dim3(nsb * ngr), dim3(kBlock), 0, st, (const link *)U,
                        (const vec *)in, in_stride, in_extra, (vec *)out, out_stride, (const vec *)aux, aux_stride,
-                       aux_extra, g, (T)kappa, (T)sigma, sl, lgR, nsb, partial, partial_stride(g));
+                       aux_extra, g, (T)kappa, (T)sigma, sl, lgR, nsb, partial, partial_stride(g), alpha, status);
 }
 
 template <int NR, bool DAG, int EPI, int KIND>
 static void launch_f32(const void *U, const void *in, size_t in_stride, size_t in_extra, void *out, size_t out_stride,
                        const void *aux, size_t aux_stride, size_t aux_extra, const Geom &g, double kappa, double sigma,
-                       Slots sl, int max_slots, double *partial, hipStream_t st) {
+                       Slots sl, int max_slots, double *partial, const double *alpha, const int *status,
+                       hipStream_t st) {
     const int nsb = KIND == 2 ? tile_blocks(g) : site_blocks(g);
     const int ngr = (max_slots + NR - 1) / NR;
     if constexpr (KIND == 2)
         hipLaunchKernelGGL((k_dslash_f32_tile<NR, DAG, EPI>), dim3(nsb * ngr), dim3(g.nx * g.tile_y), 0, st,
                            (const float4 *)U, (const float4 *)in, in_stride, in_extra, (float4 *)out, out_stride,
                            (const float4 *)aux, aux_stride, aux_extra, g, (float)kappa, (float)sigma, sl, nsb, partial,
-                           partial_stride(g));
+                           partial_stride(g), alpha, status);
     else if constexpr (KIND == 3)
         hipLaunchKernelGGL((k_dslash_f32_plane_xyl<NR, DAG, EPI>), dim3(nsb * ngr), dim3(kBlock), 0, st,
                            (const float4 *)U, (const float4 *)in, in_stride, in_extra, (float4 *)out, out_stride,
                            (const float4 *)aux, aux_stride, aux_extra, g, (float)kappa, (float)sigma, sl, nsb, partial,
-                           partial_stride(g));
+                           partial_stride(g), alpha, status);
     else if constexpr (KIND == 1)
         hipLaunchKernelGGL((k_dslash_f32_plane<NR, DAG, EPI>), dim3(nsb * ngr), dim3(kBlock), 0, st,
                            (const float4 *)U, (const float4 *)in, in_stride, in_extra, (float4 *)out, out_stride,
                            (const float4 *)aux, aux_stride, aux_extra, g, (float)kappa, (float)sigma, sl, nsb, partial,
-                           partial_stride(g));
+                           partial_stride(g), alpha, status);
     else
         hipLaunchKernelGGL((k_dslash_f32<NR, DAG, EPI>), dim3(nsb * ngr), dim3(kBlock), 0, st, (const float4 *)U,
                            (const float4 *)in, in_stride, in_extra, (float4 *)out, out_stride, (const float4 *)aux,
-                           aux_stride, aux_extra, g, (float)kappa, (float)sigma, sl, nsb, partial, partial_stride(g));
+                           aux_stride, aux_extra, g, (float)kappa, (float)sigma, sl, nsb, partial, partial_stride(g),
+                           alpha, status);
 }
 
 template <bool DAG, int EPI>
 static void launch_f32_tuned(const void *U, const void *in, size_t in_stride, size_t in_extra, void *out,
                              size_t out_stride, const void *aux, size_t aux_stride, size_t aux_extra, const Geom &g,
-                             double kappa, double sigma, Slots sl, int max_slots, double *partial, hipStream_t st) {
+                             double kappa, double sigma, Slots sl, int max_slots, double *partial,
+                             const double *alpha, const int *status, hipStream_t st) {
 #define SMPQ_F32(NR, PL)                                                                                       \
     launch_f32<NR, DAG, EPI, PL>(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra, g, kappa, \
-                                 sigma, sl, max_slots, partial, st)
+                                 sigma, sl, max_slots, partial, alpha, status, st)
     if (g.f32_kind == 2) {
         if (g.f32_nr == 4) SMPQ_F32(4, 2);
         else if (g.f32_nr == 16) SMPQ_F32(16, 2);
@@ -717,18 +979,26 @@ static void launch_f32_tuned(const void *U, const void *in, size_t in_stride, si
 
 void launch_dslash(int prec, bool dag, int epi, const void *U, const void *in, size_t in_stride, size_t in_extra,
                    void *out, size_t out_stride, const void *aux, size_t aux_stride, size_t aux_extra, const Geom &g,
-                   double kappa, double sigma, Slots sl, int max_slots, double *partial, hipStream_t st) {
+                   double kappa, double sigma, Slots sl, int max_slots, double *partial, hipStream_t st,
+                   const double *alpha, const int *status) {
     using Fn = void (*)(const void *, const void *, size_t, size_t, void *, size_t, const void *, size_t, size_t,
-                        const Geom &, double, double, Slots, int, double *, hipStream_t);
+                        const Geom &, double, double, Slots, int, double *, const double *, const int *, hipStream_t);
     if (!valid_tuning(prec, g)) throw std::invalid_argument("stencil variant does not fit this lattice");
-    static const Fn table[2][2][2] = {
-        {{launch_dslash_t<double, false, 0>, launch_dslash_t<double, false, 1>},
-         {launch_dslash_t<double, true, 0>, launch_dslash_t<double, true, 1>}},
-        {{launch_f32_tuned<false, 0>, launch_f32_tuned<false, 1>},
-         {launch_f32_tuned<true, 0>, launch_f32_tuned<true, 1>}}};
-    table[prec == 0 ? 0 : 1][dag ? 1 : 0][epi == 1 ? 1 : 0](U, in, in_stride, in_extra, out, out_stride, aux,
-                                                            aux_stride, aux_extra, g, kappa, sigma, sl, max_slots,
-                                                            partial, st);
+    if (epi < 0 || epi > 3) throw std::invalid_argument("unknown stencil epilogue");
+    if (epi == 2 && (!alpha || !status)) throw std::invalid_argument("the residual epilogue needs alpha and status");
+    // [precision][dagger][epilogue]; the FP32 stencil is built for the combinations the solver,
+    // the autotuner and smpq_apply_dw use
+    static const Fn table[2][2][4] = {
+        {{launch_dslash_t<double, false, 0>, launch_dslash_t<double, false, 1>, launch_dslash_t<double, false, 2>,
+          launch_dslash_t<double, false, 3>},
+         {launch_dslash_t<double, true, 0>, launch_dslash_t<double, true, 1>, launch_dslash_t<double, true, 2>,
+          launch_dslash_t<double, true, 3>}},
+        {{launch_f32_tuned<false, 0>, nullptr, nullptr, launch_f32_tuned<false, 3>},
+         {launch_f32_tuned<true, 0>, launch_f32_tuned<true, 1>, launch_f32_tuned<true, 2>, nullptr}}};
+    const Fn f = table[prec == 0 ? 0 : 1][dag ? 1 : 0][epi];
+    if (!f) throw std::invalid_argument("stencil epilogue not built for this precision and direction");
+    f(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra, g, kappa, sigma, sl, max_slots, partial,
+      alpha, status, st);
 }
 
 // ------------------------------------------------------------------ element-wise kernels
@@ -1014,41 +1284,6 @@ void launch_scalars_alpha(const MSState &s, int npart, hipStream_t st) {
     hipLaunchKernelGGL(k_scalars_alpha, dim3(s.B), dim3(64), 0, st, s, npart);
 }
 
-// r -= alpha A p ; partial |r|^2
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_r_update(Geom g, MSState S, typename Store<T>::vec *r,
-                                                     const typename Store<T>::vec *ap) {
-    constexpr int C = Unit<T>::C;
-    if ((int)blockIdx.y >= *S.count) return;
-    const int slot = S.list[blockIdx.y];
-    const int nsb = site_blocks(g);
-    const int u = blockIdx.x / nsb;
-    const int s = (blockIdx.x % nsb) * kBlock + threadIdx.x;
-    const size_t rs = Store<T>::units * g.vs;
-    double nrm = 0.0;
-    if (s < g.V && S.status[slot] == kStatusOK) {
-        const T a = (T)S.alpha[slot];
-        cpx<T> rv[C], av[C];
-        Unit<T>::load_stream(r + slot * rs, g.vs, u, s, rv);
-        Unit<T>::load_stream(ap + slot * rs, g.vs, u, s, av);
-#pragma unroll
-        for (int i = 0; i < C; ++i) {
-            rv[i] = rv[i] - a * av[i];
-            nrm += (double)rv[i].re * rv[i].re + (double)rv[i].im * rv[i].im;
-        }
-        Unit<T>::store_stream(r + slot * rs, g.vs, u, s, rv);
-    }
-    block_partial(nrm, S.partial, (size_t)slot * S.pstride + blockIdx.x);
-}
-
-void launch_r_update(int prec, const Geom &g, const MSState &s, void *r, const void *ap, hipStream_t st) {
-    dim3 grid(unit_parts(prec, g), s.B);
-    if (prec == 0)
-        hipLaunchKernelGGL(k_r_update<double>, grid, dim3(kBlock), 0, st, g, s, (double2 *)r, (const double2 *)ap);
-    else
-        hipLaunchKernelGGL(k_r_update<float>, grid, dim3(kBlock), 0, st, g, s, (float4 *)r, (const float4 *)ap);
-}
-
 // beta_k = |r_{k+1}|^2/|r_k|^2; per active shift: alpha^i, beta^i, convergence
 // (zeta^i_{k+1} |r_{k+1}| <= tol |b|); build this iteration's update list.  The base
 // shift's direction keeps being updated while any shift of the slot is active.
@@ -1077,6 +1312,7 @@ __global__ void k_scalars_beta(MSState S, int npart) {
             const bool conv = zn * rn <= lim;
             S.upd_idx[u] = i;
             S.upd_cy[u] = S.c[i] * a * ratio;
+            S.upd_ax[u] = a * ratio;
             S.upd_zeta[u] = zn;
             S.upd_beta[u] = b * ratio * ratio;
             S.upd_pupd[u] = (!conv || i == S.i0) ? 1 : 0;
@@ -1092,6 +1328,7 @@ __global__ void k_scalars_beta(MSState S, int npart) {
         } else if (i == S.i0) {
             S.upd_idx[u] = i;
             S.upd_cy[u] = 0.0;
+            S.upd_ax[u] = 0.0;
             S.upd_zeta[u] = 1.0;
             S.upd_beta[u] = b;
             S.upd_pupd[u] = 1;
@@ -1139,9 +1376,11 @@ void launch_scalars_beta(const MSState &s, int npart, hipStream_t st) {
 // storage precision of p, which k_fold adds to FP64 every few iterations.  The FP64 path
 // always accumulates into y directly.  D: storage of the shifted directions (kDirF32: all NS
 // directions in p; 16-bit: the base in p, slot stride one vector, the others scaled in ph).
-template <class T, bool Y64, bool X64, int D>
+// XS: also x_i += alpha^i p_i in FP64 for every listed shift (xs [slot][NS][12][vs]).
+template <class T, bool Y64, bool X64, int D, bool XS>
 __global__ __launch_bounds__(kBlock) void k_shift_update(Geom g, MSState S, const typename Store<T>::vec *r,
-                                                         typename Store<T>::vec *p, void *yt, void *xt, void *ph) {
+                                                         typename Store<T>::vec *p, void *yt, void *xt, void *ph,
+                                                         double2 *xs) {
     using vec = typename Store<T>::vec;
     constexpr int C = Unit<T>::C;
     if ((int)blockIdx.y >= *S.count) return;
@@ -1178,6 +1417,16 @@ __global__ __launch_bounds__(kBlock) void k_shift_update(Geom g, MSState S, cons
             if (full) Unit<T>::load_stream(pp, g.vs, u, s, pv);
             else load_dir16<D>(static_cast<typename Dir16<D>::v *>(ph) + ((size_t)slot * S.NS + i) * rs, g.vs, u, s,
                                (float)S.upd_sold[k], pv);
+        }
+        if constexpr (XS) {
+            const double ax = S.upd_ax[k];
+            if (ax != 0.0) {
+                double2 *xp = xs + ((size_t)slot * S.NS + i) * r64;
+#pragma unroll
+                for (int j = 0; j < C; ++j)
+                    st64_stream(xp, g.vs, u * C + j, s,
+                                ld64_stream(xp, g.vs, u * C + j, s) + ax * cpx<double>{(double)pv[j].re, (double)pv[j].im});
+            }
         }
         if (cy != 0.0) {
 #pragma unroll
@@ -1230,28 +1479,35 @@ __global__ __launch_bounds__(kBlock) void k_shift_update(Geom g, MSState S, cons
 }
 
 void launch_shift_update(int prec, const Geom &g, const MSState &s, const void *r, void *p, void *yt, bool y64,
-                         void *xt, bool x64, int dir, void *ph, hipStream_t st) {
+                         void *xt, bool x64, int dir, void *ph, double2 *xs, hipStream_t st) {
     dim3 grid(unit_parts(prec, g), s.B);
+    if (xs && dir != kDirF32) throw std::invalid_argument("the per-shift check needs FP32 or FP64 directions");
     if (prec == 0) {
         if (dir != kDirF32) throw std::invalid_argument("16-bit directions need the FP32 path");
-        hipLaunchKernelGGL((k_shift_update<double, true, true, kDirF32>), grid, dim3(kBlock), 0, st, g, s,
-                           (const double2 *)r, (double2 *)p, yt, xt, ph);
+        if (xs)
+            hipLaunchKernelGGL((k_shift_update<double, true, true, kDirF32, true>), grid, dim3(kBlock), 0, st, g, s,
+                               (const double2 *)r, (double2 *)p, yt, xt, ph, xs);
+        else
+            hipLaunchKernelGGL((k_shift_update<double, true, true, kDirF32, false>), grid, dim3(kBlock), 0, st, g, s,
+                               (const double2 *)r, (double2 *)p, yt, xt, ph, xs);
         return;
     }
-#define SMPQ_SU(Y, X, D)                                                                                          \
-    hipLaunchKernelGGL((k_shift_update<float, Y, X, D>), grid, dim3(kBlock), 0, st, g, s, (const float4 *)r,        \
-                       (float4 *)p, yt, xt, ph)
-#define SMPQ_SU_D(D)                     \
-    if (y64 && x64) SMPQ_SU(true, true, D); \
-    else if (y64) SMPQ_SU(true, false, D);  \
-    else if (x64) SMPQ_SU(false, true, D);  \
-    else SMPQ_SU(false, false, D)
+#define SMPQ_SU(Y, X, D, XS)                                                                                      \
+    hipLaunchKernelGGL((k_shift_update<float, Y, X, D, XS>), grid, dim3(kBlock), 0, st, g, s, (const float4 *)r,   \
+                       (float4 *)p, yt, xt, ph, xs)
+#define SMPQ_SU_D(D, XS)                         \
+    if (y64 && x64) SMPQ_SU(true, true, D, XS);  \
+    else if (y64) SMPQ_SU(true, false, D, XS);   \
+    else if (x64) SMPQ_SU(false, true, D, XS);   \
+    else SMPQ_SU(false, false, D, XS)
     if (dir == kDirF16) {
-        SMPQ_SU_D(kDirF16);
+        SMPQ_SU_D(kDirF16, false);
     } else if (dir == kDirBF16) {
-        SMPQ_SU_D(kDirBF16);
+        SMPQ_SU_D(kDirBF16, false);
+    } else if (xs) {
+        SMPQ_SU_D(kDirF32, true);
     } else {
-        SMPQ_SU_D(kDirF32);
+        SMPQ_SU_D(kDirF32, false);
     }
 #undef SMPQ_SU_D
 #undef SMPQ_SU
@@ -1348,6 +1604,72 @@ __global__ void k_scalars_rr(MSState S, int npart) {
 
 void launch_scalars_rr(const MSState &s, int npart, hipStream_t st) {
     hipLaunchKernelGGL(k_scalars_rr, dim3(s.B), dim3(64), 0, st, s, npart);
+}
+
+// ------------------------------------------------------------------ per-shift check
+// out = b - ap64 in FP64 for the first nslots slots; partial |out|^2 per block.
+__global__ __launch_bounds__(kBlock) void k_resid64(Geom g, Source src, const double2 *ap64, double2 *out,
+                                                    double *partial, size_t pstride) {
+    const int slot = blockIdx.y;
+    const int nsb = site_blocks(g);
+    const int u = blockIdx.x / nsb;
+    const int s = (blockIdx.x % nsb) * kBlock + threadIdx.x;
+    double nrm = 0.0;
+    if (s < g.V) {
+        const size_t o = (size_t)slot * 12 * g.vs;
+        const cpx<double> d = source_entry(src, slot, u, s, g.vs) - ld64(ap64 + o, g.vs, u, s);
+        st64(out + o, g.vs, u, s, d);
+        nrm = d.re * d.re + d.im * d.im;
+    }
+    block_partial(nrm, partial, (size_t)slot * pstride + blockIdx.x);
+}
+
+void launch_resid64(const Geom &g, int nslots, const Source &src, const double2 *ap64, double2 *out,
+                    double *partial, size_t pstride, hipStream_t st) {
+    hipLaunchKernelGGL(k_resid64, dim3(unit_parts(0, g), nslots), dim3(kBlock), 0, st, g, src, ap64, out, partial,
+                       pstride);
+}
+
+__global__ void k_slot_sums(const double *partial, size_t pstride, int npart, double *sums) {
+    const double v = wave_sum_partials(partial + (size_t)blockIdx.x * pstride, npart);
+    if (threadIdx.x == 0) sums[blockIdx.x] = v;
+}
+
+void launch_slot_sums(int nslots, const double *partial, size_t pstride, int npart, double *sums, hipStream_t st) {
+    hipLaunchKernelGGL(k_slot_sums, dim3(nslots), dim3(64), 0, st, partial, pstride, npart, sums);
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_unflagged(Geom g, const int *flag, double2 *v) {
+    const int slot = blockIdx.y;
+    if (flag[slot]) return;
+    const int nsb = site_blocks(g);
+    const int u = blockIdx.x / nsb;
+    const int s = (blockIdx.x % nsb) * kBlock + threadIdx.x;
+    if (s < g.V) st64(v + (size_t)slot * 12 * g.vs, g.vs, u, s, {0.0, 0.0});
+}
+
+void launch_zero_unflagged(const Geom &g, int nslots, const int *flag, double2 *v, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_unflagged, dim3(unit_parts(0, g), nslots), dim3(kBlock), 0, st, g, flag, v);
+}
+
+__global__ __launch_bounds__(kBlock) void k_refine_acc(Geom g, const double2 *e, double c, double2 *ysave,
+                                                       double2 *xsi, size_t xs_stride) {
+    const int slot = blockIdx.y;
+    const int nsb = site_blocks(g);
+    const int u = blockIdx.x / nsb;
+    const int s = (blockIdx.x % nsb) * kBlock + threadIdx.x;
+    if (s >= g.V) return;
+    const size_t o = (size_t)slot * 12 * g.vs;
+    const cpx<double> ev = ld64(e + o, g.vs, u, s);
+    st64(ysave + o, g.vs, u, s, ld64(ysave + o, g.vs, u, s) + c * ev);
+    double2 *xp = xsi + (size_t)slot * xs_stride;
+    st64(xp, g.vs, u, s, ld64(xp, g.vs, u, s) + ev);
+}
+
+void launch_refine_acc(const Geom &g, int nslots, const double2 *e, double c, double2 *ysave, double2 *xsi,
+                       size_t xs_stride, hipStream_t st) {
+    hipLaunchKernelGGL(k_refine_acc, dim3(unit_parts(0, g), nslots), dim3(kBlock), 0, st, g, e, c, ysave, xsi,
+                       xs_stride);
 }
 
 // ------------------------------------------------------------------ contraction (Eq. 16)

@@ -108,6 +108,12 @@ def test_argument_errors():
         with pytest.raises(smpq.SmpqError) as e:
             smpq.smpq_set_solver(c, smpq.SMPQ_MIXED_FP32, 1e-12, 10, rel)
         assert e.value.status == -1
+    for en, rt in ((2, 1e-10), (1, 1.0), (1, float("nan"))):
+        with pytest.raises(smpq.SmpqError) as e:
+            smpq.smpq_set_shift_check(c, en, rt)
+        assert e.value.status == -1
+    smpq.smpq_set_shift_check(c, 1, 1e-10)
+    smpq.smpq_set_shift_check(c, 0, 0.0)
     for rel in (0, 10, 50, 100):
         smpq.smpq_set_solver(c, smpq.SMPQ_MIXED_FP32, 1e-12, 10, rel)
         assert smpq.smpq_get_settings(c)["reliable_interval"] == rel
