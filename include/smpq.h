@@ -224,6 +224,19 @@ smpq_status smpq_get_coloring(const smpq_ctx *ctx, int32_t *colour);
 smpq_status smpq_apply_dw(smpq_ctx *ctx, const double *in, double *out, int n_rhs, int dagger,
                           smpq_precision prec);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): smpq_apply_dw without any allocation.  Same
+ * arguments, results and errors as smpq_apply_dw (the same stencil kernels); the host layout
+ * is converted on the device.  Device memory comes from one fixed scratch array of 256 MiB per
+ * GPU in the library (taken when the first context on that GPU is created and held until the
+ * process ends); a call needs n_rhs * (192 V + 384 V_pad) bytes of it in FP64 and
+ * n_rhs * (192 V + 576 V_pad) in FP32 (V_pad = V rounded up to 256), and EDIM is returned,
+ * before any device work, when that exceeds 256 MiB (16^3 x 32: 2 right-hand sides in FP32).
+ * Every call on one GPU uses the same array and leaves it holding its data: calls that
+ * overlap on one GPU (from several threads or contexts) race. */
+smpq_status smpq_apply_dw_noalloc(smpq_ctx *ctx, const double *in, double *out, int n_rhs, int dagger,
+                                  smpq_precision prec);
+
 /* out = D_ov in = in + gamma5 eps_Z(H_W) in (Eq. 3) for n_rhs spinors, through the
  * multi-shift CG of the solver settings.  Needs a gauge field and Zolotarev coefficients. */
 smpq_status smpq_apply_dov(smpq_ctx *ctx, const double *in, double *out, int n_rhs);

@@ -19,7 +19,7 @@ __all__ = [
     "smpq_create", "smpq_destroy", "smpq_strerror", "smpq_last_error", "smpq_load_gauge",
     "smpq_set_kappa", "smpq_lanczos", "smpq_estimate_bounds", "smpq_set_zolotarev",
     "smpq_get_zolotarev", "smpq_set_solver", "smpq_get_settings", "SmpqSettings", "smpq_set_shift_check", "smpq_set_batch", "smpq_set_scheme",
-    "smpq_set_point_scheme", "smpq_get_coloring", "smpq_get_scheme_rmin", "smpq_apply_dw", "smpq_apply_dov",
+    "smpq_set_point_scheme", "smpq_get_coloring", "smpq_get_scheme_rmin", "smpq_apply_dw", "smpq_apply_dw_noalloc", "smpq_apply_dov",
     "smpq_compute_qx", "smpq_compute_qx_classes", "smpq_compute_trinv", "smpq_dov_locality", "smpq_deflate", "smpq_compute_qx_points", "smpq_prepare", "smpq_set_stream",
     "smpq_set_timing", "smpq_set_graphs", "smpq_bench_dslash", "smpq_bench_copy", "smpq_autotune",
     "smpq_set_tuning", "smpq_get_tuning", "smpq_set_memory_limit", "smpq_compute_qx_multi",
@@ -84,6 +84,8 @@ _SIG = {
     "smpq_get_coloring": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32)]),
     "smpq_get_scheme_rmin": (ctypes.c_int, [_vp, _c_double_p, _c_int_p]),
     "smpq_apply_dw": (ctypes.c_int, [_vp, _c_double_p, _c_double_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "smpq_apply_dw_noalloc": (ctypes.c_int, [_vp, _c_double_p, _c_double_p, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_int]),
     "smpq_apply_dov": (ctypes.c_int, [_vp, _c_double_p, _c_double_p, ctypes.c_int]),
     "smpq_compute_qx": (ctypes.c_int, [_vp, _c_double_p, _c_double_p, _c_double_p, ctypes.POINTER(SmpqStats)]),
     "smpq_compute_qx_classes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int, _c_double_p,
@@ -271,6 +273,19 @@ def smpq_apply_dw(ctx, psi, dagger=False, precision=SMPQ_FP64):
     out = np.empty_like(psi)
     _check(ctx, _lib.smpq_apply_dw(ctx.ptr, _dp(psi.view(np.float64)), _dp(out.view(np.float64)), psi.shape[0],
                                    int(bool(dagger)), int(precision)))
+    return out
+
+
+def smpq_apply_dw_noalloc(ctx, psi, dagger=False, precision=SMPQ_FP64, out=None):
+    """smpq_apply_dw through the library's fixed scratch (no device allocation); `out` may be a
+    preallocated complex128 array of psi's shape."""
+    psi = _spinors(ctx, psi)
+    if out is None:
+        out = np.empty_like(psi)
+    elif out.shape != psi.shape or out.dtype != np.complex128 or not out.flags.c_contiguous:
+        raise ValueError("out must be a C-contiguous complex128 array of the input's shape")
+    _check(ctx, _lib.smpq_apply_dw_noalloc(ctx.ptr, _dp(psi.view(np.float64)), _dp(out.view(np.float64)),
+                                           psi.shape[0], int(bool(dagger)), int(precision)))
     return out
 
 

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -21,7 +22,33 @@
 
 using namespace smpq;
 
+// Device scratch of smpq_apply_dw_noalloc: a fixed array in the library's code object, one copy
+// per GPU, held until the process ends.  In host code its name is only a stand-in for the
+// symbol; kernels get the device address that hipGetSymbolAddress returns, taken once per device
+// when the first context on that device is created.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's scratch (the device must be current); nullptr if it cannot be had.
+void *scratch_address(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        scratch_ptr[device] = p;
+    }
+    return scratch_ptr[device];
+}
 
 struct Fail {
     smpq_status st;
@@ -1322,7 +1349,7 @@ smpq_status smpq_create(const int dims[4], int device, smpq_ctx **out) {
             return SMPQ_EDEVICE;
         }
         if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess ||
-            hipHostMalloc((void **)&c->h_count, sizeof(int) * 4) != hipSuccess) {
+            hipHostMalloc((void **)&c->h_count, sizeof(int) * 4) != hipSuccess || !scratch_address(device)) {
             (void)hipGetLastError();
             delete c;
             return SMPQ_EDEVICE;
@@ -1627,6 +1654,54 @@ smpq_status smpq_apply_dw(smpq_ctx *c, const double *in, double *out, int n, int
         HIPCHK(hipMemcpyAsync(stage.data(), b.p, v64 * n, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         spinor_from_device(c, stage, n, out);
+    });
+}
+
+// The same as smpq_apply_dw without allocating: host input and output go through the device's
+// fixed scratch array (the host layout is converted on the device), and the staging vectors
+// live there too.  Calls that overlap on one GPU share that array and race.
+static size_t noalloc_dw_bytes_per_rhs(const smpq_ctx *c, smpq_precision prec) {
+    const size_t aos = (size_t)c->V * 12 * sizeof(double2), v64 = 12 * 16 * c->vs, v32 = 6 * 16 * c->vs;
+    return aos + 2 * v64 + (prec == SMPQ_FP64 ? 0 : 2 * v32);
+}
+
+smpq_status smpq_apply_dw_noalloc(smpq_ctx *c, const double *in, double *out, int n, int dagger,
+                                  smpq_precision prec) {
+    return guarded(c, [&] {
+        if (!in || !out || n < 1) throw Fail{SMPQ_EINVAL, "need input, output and n_rhs >= 1"};
+        if (prec != SMPQ_FP64 && prec != SMPQ_MIXED_FP32) throw Fail{SMPQ_EINVAL, "unknown precision"};
+        const size_t per = noalloc_dw_bytes_per_rhs(c, prec);
+        if ((size_t)n > kScratchBytes / per)
+            throw Fail{SMPQ_EDIM, std::to_string(n) + " right-hand sides of " + std::to_string(per) +
+                                      " bytes each exceed the allocation-free call's scratch of " +
+                                      std::to_string(kScratchBytes >> 20) + " MiB (at most " +
+                                      std::to_string(kScratchBytes / per) + " here)"};
+        need_device(c);
+        if (!c->have_gauge) throw Fail{SMPQ_ESTATE, "no gauge field loaded"};
+        unsigned char *base = static_cast<unsigned char *>(scratch_ptr[c->device]);
+        if (!base) throw Fail{SMPQ_EDEVICE, "no scratch address for this device"};
+        const Geom g = c->geom();
+        const size_t aos = (size_t)c->V * 12 * sizeof(double2), v64 = 12 * 16 * c->vs, v32 = 6 * 16 * c->vs;
+        double2 *h = reinterpret_cast<double2 *>(base);                  // host layout, in and out
+        double2 *a = reinterpret_cast<double2 *>(base + n * aos);        // [slot][12][vs] FP64
+        double2 *b = reinterpret_cast<double2 *>(base + n * (aos + v64));
+        void *a32 = base + n * (aos + 2 * v64), *b32 = base + n * (aos + 2 * v64 + v32);
+        HIPCHK(hipMemcpyAsync(h, in, aos * n, hipMemcpyHostToDevice, c->stream));
+        launch_layout(true, g, h, a, n, c->stream);
+        Slots sl{nullptr, nullptr, n};
+        if (prec == SMPQ_FP64) {
+            launch_dslash(0, dagger != 0, 0, c->U64.p, a, 12 * c->vs, 0, b, 12 * c->vs, nullptr, 0, 0, g, c->kappa,
+                          0.0, sl, n, nullptr, c->stream);
+        } else {
+            launch_convert(1, g, a, a32, n, c->stream);
+            launch_dslash(1, dagger != 0, 0, c->U32.p, a32, 6 * c->vs, 0, b32, 6 * c->vs, nullptr, 0, 0, g, c->kappa,
+                          0.0, sl, n, nullptr, c->stream);
+            launch_convert(0, g, b32, b, n, c->stream);
+        }
+        launch_layout(false, g, b, h, n, c->stream);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(out, h, aos * n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
     });
 }
 

@@ -170,5 +170,7 @@ void launch_lanczos_update(const Geom &g, double2 *w, const double2 *v, const do
 void launch_scale(const Geom &g, double2 *dst, const double2 *src, double f, hipStream_t st);
 // layout conversion between FP64 (double2 x 12) and FP32 (float4 x 6) spinors, n slots
 void launch_convert(int to_prec, const Geom &g, const void *src, void *dst, int nslots, hipStream_t st);
+// host spinor layout [slot][site][12] double2 (V sites per slot) <-> device [slot][12][vs]
+void launch_layout(bool to_soa, const Geom &g, const double2 *src, double2 *dst, int nslots, hipStream_t st);
 
 }  // namespace smpq

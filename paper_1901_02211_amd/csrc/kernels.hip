@@ -1983,6 +1983,33 @@ __global__ __launch_bounds__(kBlock) void k_to_f64(Geom g, const float4 *src, do
     dp[(2 * u + 1) * g.vs + s] = make_double2(t.z, t.w);
 }
 
+// Host spinor layout [rhs][site][spin*3 + colour] complex128 <-> device [rhs][unit][site] double2.
+__global__ __launch_bounds__(kBlock) void k_aos_to_soa(Geom g, const double2 *aos, double2 *soa) {
+    const int slot = blockIdx.y;
+    const int nsb = site_blocks(g);
+    const int u = blockIdx.x / nsb;
+    const int s = (blockIdx.x % nsb) * kBlock + threadIdx.x;
+    if (s >= g.V) return;
+    soa[((size_t)slot * 12 + u) * g.vs + s] = aos[((size_t)slot * g.V + s) * 12 + u];
+}
+
+__global__ __launch_bounds__(kBlock) void k_soa_to_aos(Geom g, const double2 *soa, double2 *aos) {
+    const int slot = blockIdx.y;
+    const int nsb = site_blocks(g);
+    const int u = blockIdx.x / nsb;
+    const int s = (blockIdx.x % nsb) * kBlock + threadIdx.x;
+    if (s >= g.V) return;
+    aos[((size_t)slot * g.V + s) * 12 + u] = soa[((size_t)slot * 12 + u) * g.vs + s];
+}
+
+void launch_layout(bool to_soa, const Geom &g, const double2 *src, double2 *dst, int nslots, hipStream_t st) {
+    dim3 grid(unit_parts(0, g), nslots);
+    if (to_soa)
+        hipLaunchKernelGGL(k_aos_to_soa, grid, dim3(kBlock), 0, st, g, src, dst);
+    else
+        hipLaunchKernelGGL(k_soa_to_aos, grid, dim3(kBlock), 0, st, g, src, dst);
+}
+
 void launch_convert(int to_prec, const Geom &g, const void *src, void *dst, int nslots, hipStream_t st) {
     dim3 grid(unit_parts(1, g), nslots);
     if (to_prec == 1)

@@ -142,6 +142,15 @@ def test_argument_errors():
         smpq.smpq_compute_qx_points(c, [0])
     assert e.value.status == -4
     assert smpq.smpq_strerror(-5) == "solver did not converge"
+    # the allocation-free stencil refuses batches beyond its 256 MiB scratch before device work
+    big = smpq.smpq_create((16, 16, 16, 32), -1)
+    psi = np.zeros((3, 16 * 16 * 16 * 32, 4, 3), dtype=complex)
+    with pytest.raises(smpq.SmpqError) as e:
+        smpq.smpq_apply_dw_noalloc(big, psi, precision=smpq.SMPQ_MIXED_FP32)
+    assert e.value.status == -2 and "256 MiB" in str(e.value)
+    with pytest.raises(smpq.SmpqError) as e:      # two fit: only the device is missing
+        smpq.smpq_apply_dw_noalloc(big, psi[:2], precision=smpq.SMPQ_MIXED_FP32)
+    assert e.value.status == -4
 
 
 def test_multi_context_argument_errors():
