@@ -379,6 +379,11 @@ def main():
     print("bench: standalone stencil", file=sys.stderr, flush=True)
     copy_ms = smpq.smpq_bench_copy(ctx, 1 << 31, 20)
     copy_GBs = 2.0 * (1 << 31) / (copy_ms * 1e-3) / 1e9
+    stream_GBs = {}
+    if hasattr(smpq, "smpq_bench_stream"):
+        for nt in (False, True):
+            ms = smpq.smpq_bench_stream(ctx, 1 << 31, 20, nt)
+            stream_GBs["nontemporal" if nt else "cached"] = round(2.0 * (1 << 31) / (ms * 1e-3) / 1e9, 1)
     ms32, by32 = smpq.smpq_bench_dslash(ctx, smpq.SMPQ_MIXED_FP32, 24, 4, 50)
     ms64, by64 = smpq.smpq_bench_dslash(ctx, smpq.SMPQ_FP64, 24, 4, 50)
     dslash = {"insitu_GBs": round(ds_insitu, 1), "insitu_frac": round(ds_insitu / HBM_PEAK_GBS, 4),
@@ -458,12 +463,17 @@ def main():
                    "stencil_variants": {"f32_kind": ["site", "plane", "xy-tile", "plane, xy links in LDS"][tuning["f32_kind"]],
                                         "f32_rhs_per_thread": tuning["f32_nr"],
                                         "plane_band": tuning["plane_band"],
-                                        "f64_rhs_per_block": 1 << tuning["f64_lgr"]}},
+                                        "f64_kind": ["lanes", "xy-tile"][tuning.get("f64_kind", 0)],
+                                        "f64_rhs_per_block": (tuning["f64_nr"] if tuning.get("f64_kind", 0) == 1
+                                                              else 1 << tuning["f64_lgr"])}},
         "steps_requested": args.steps, "warmup_requested": args.warmup, "budget_s": args.budget_s,
         "speedup_vs_fp64": round(fp64["s_per_map"] / (ms_per_step / 1000.0), 3),
         "roofline": roofline, "dslash": dslash, "fp64": fp64, "accuracy": accuracy,
         "bandwidth_context": {"device_copy_GBs": round(copy_GBs, 1),
                               "device_copy_note": "hipMemcpyAsync device to device, 2 GiB, read + write bytes",
+                              "stream_copy_GBs": stream_GBs or None,
+                              "stream_copy_note": "the library's float4 copy kernel (cached / non-temporal loads and "
+                                                  "stores), 2 GiB, read + write bytes",
                               "map_stencil_and_update_GBs": round(map_GBs, 1),
                               "map_note": "stencil + shift-update algorithmic bytes over the whole solve time"},
         "step_s": [round(t * scale, 3) for t in times],

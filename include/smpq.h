@@ -70,7 +70,16 @@ typedef enum {
                             1e-4 (FP16) to 1e-3 (BF16) against the FP64 oracle on small
                             maps, against 1e-7 for SMPQ_MIXED_FP32.  An evaluated option,
                             not a recommended one                                     */
-    SMPQ_MIXED_BF16DIR = 3  /* the same with BF16 storage (8-bit significand)           */
+    SMPQ_MIXED_BF16DIR = 3, /* the same with BF16 storage (8-bit significand)          */
+    SMPQ_MIXED_FP16VEC = 4, /* SMPQ_MIXED_FP32 with the vectors the FP32 stencil reads, the
+                            base search direction p and D_W p, rounded to FP16 where they are
+                            stored (each divided by its right-hand side's scale
+                            |r| / sqrt(24 V), which keeps the entries near 1), the rest of the
+                            path unchanged.  An evaluation of 16-bit storage of the stencil's
+                            inputs: the values carry exactly the rounding of 16-bit storage but
+                            stay in FP32 words, so the bytes and the time are those of
+                            SMPQ_MIXED_FP32                                              */
+    SMPQ_MIXED_BF16VEC = 5  /* the same rounded to BF16 (no scale needed)                 */
 } smpq_precision;
 
 typedef struct {
@@ -361,12 +370,21 @@ smpq_status smpq_compute_qx_multi(smpq_ctx *const *ctxs, int n_ctx, const int32_
  * bandwidth ceiling (2 * bytes / time) beside the roofline figures. */
 smpq_status smpq_bench_copy(smpq_ctx *ctx, size_t bytes, int launches, double *ms_per_copy);
 
+/* A hand-written streaming copy of `bytes` bytes (rounded down to 16) between two buffers of the
+ * device, alternating direction, with cached (nontemporal = 0) or non-temporal (1) loads and
+ * stores; mean duration per copy over `launches`.  A kernel of known size (bytes read and bytes
+ * written per launch) for scaling hardware byte counters, and a bandwidth ceiling beside
+ * smpq_bench_copy's library copy. */
+smpq_status smpq_bench_stream(smpq_ctx *ctx, size_t bytes, int launches, int nontemporal, double *ms_per_copy);
+
 /* Stencil variants.  f32_kind: 0 = one site per thread (f32_nr = 2, 4 or 8 right-hand sides
  * per thread, links held in registers across them); 1 = one 16x16 xy-plane per block staged
  * in LDS (nx*ny = 256; f32_nr = 4, 8 or 16); 2 = xy-tiles of ty rows plus one halo row on
  * each side staged in LDS, ty the largest divisor of ny with nx*ty <= 256 and a multiple of 64
  * (nx <= 64; f32_nr = 4, 8 or 16); 3 = kind 1 with the plane's x and y links in LDS instead
- * of registers, at 3 waves per SIMD.  plane_band (kinds 1-3; 1, 2 or 4, dividing nz): the
+ * of registers, at 3 waves per SIMD; 4 = kind 2's tiles with the links read for every
+ * right-hand side instead of held in registers (f32_nr = 2, 4 or 8; 3-4 waves per SIMD), the
+ * tile without halo rows when it is the whole plane.  plane_band (kinds 1-4; 1, 2 or 4, dividing nz): the
  * blocks take the (z, t) planes in bands of that many z with t running inside a band, so the
  * +-t neighbours of a plane were read shortly before (1 = z fastest).  FP64 stencil:
  * f64_kind 0 interleaves 2^f64_lgr = 1, 2 or 4 right-hand sides over the lanes of a block;

@@ -15,13 +15,14 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 __all__ = [
-    "SMPQ_FP64", "SMPQ_MIXED_FP32", "SMPQ_MIXED_FP16DIR", "SMPQ_MIXED_BF16DIR", "SmpqError", "SmpqStats", "SmpqTuning", "LIB_PATH", "EXPORTS",
+    "SMPQ_FP64", "SMPQ_MIXED_FP32", "SMPQ_MIXED_FP16DIR", "SMPQ_MIXED_BF16DIR", "SMPQ_MIXED_FP16VEC",
+    "SMPQ_MIXED_BF16VEC", "SmpqError", "SmpqStats", "SmpqTuning", "LIB_PATH", "EXPORTS",
     "smpq_create", "smpq_destroy", "smpq_strerror", "smpq_last_error", "smpq_load_gauge",
     "smpq_set_kappa", "smpq_lanczos", "smpq_estimate_bounds", "smpq_set_zolotarev",
     "smpq_get_zolotarev", "smpq_set_solver", "smpq_get_settings", "SmpqSettings", "smpq_set_shift_check", "smpq_set_batch", "smpq_set_scheme",
     "smpq_set_point_scheme", "smpq_get_coloring", "smpq_get_scheme_rmin", "smpq_apply_dw", "smpq_apply_dw_noalloc", "smpq_apply_dov",
     "smpq_compute_qx", "smpq_compute_qx_classes", "smpq_compute_trinv", "smpq_dov_locality", "smpq_deflate", "smpq_compute_qx_points", "smpq_prepare", "smpq_set_stream",
-    "smpq_set_timing", "smpq_set_graphs", "smpq_bench_dslash", "smpq_bench_copy", "smpq_autotune",
+    "smpq_set_timing", "smpq_set_graphs", "smpq_bench_dslash", "smpq_bench_copy", "smpq_bench_stream", "smpq_autotune",
     "smpq_set_tuning", "smpq_get_tuning", "smpq_set_memory_limit", "smpq_compute_qx_multi",
 ]
 
@@ -29,6 +30,8 @@ SMPQ_FP64 = 0
 SMPQ_MIXED_FP32 = 1
 SMPQ_MIXED_FP16DIR = 2   # FP32 body, shifted search directions stored in FP16 (scaled)
 SMPQ_MIXED_BF16DIR = 3   # the same in BF16
+SMPQ_MIXED_FP16VEC = 4   # FP32 body, the stencil's inputs (p and D_W p) rounded to FP16 (scaled)
+SMPQ_MIXED_BF16VEC = 5   # the same rounded to BF16
 _c_int_p = ctypes.POINTER(ctypes.c_int)
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p
@@ -104,6 +107,7 @@ _SIG = {
                                          _c_double_p]),
     "smpq_autotune": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(SmpqTuning)]),
     "smpq_bench_copy": (ctypes.c_int, [_vp, ctypes.c_size_t, ctypes.c_int, _c_double_p]),
+    "smpq_bench_stream": (ctypes.c_int, [_vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, _c_double_p]),
     "smpq_set_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(SmpqTuning)]),
     "smpq_get_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(SmpqTuning)]),
     "smpq_set_memory_limit": (ctypes.c_int, [_vp, ctypes.c_size_t]),
@@ -442,4 +446,11 @@ def smpq_bench_copy(ctx, nbytes, launches=20):
     """Mean ms of one device-to-device copy of nbytes."""
     ms = ctypes.c_double()
     _check(ctx, _lib.smpq_bench_copy(ctx.ptr, int(nbytes), int(launches), ctypes.byref(ms)))
+    return ms.value
+
+
+def smpq_bench_stream(ctx, nbytes, launches=20, nontemporal=False):
+    """Mean ms per launch of the library's streaming copy of nbytes (cached or non-temporal)."""
+    ms = ctypes.c_double()
+    _check(ctx, _lib.smpq_bench_stream(ctx.ptr, int(nbytes), int(launches), int(bool(nontemporal)), ctypes.byref(ms)))
     return ms.value

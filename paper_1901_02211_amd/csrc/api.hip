@@ -287,6 +287,8 @@ constexpr int kDirectY = 30;   // a multiple of kGroup
 // the shifted search directions stored in FP16 / BF16.  vec_prec is the precision of the
 // residual, the stencil and every other vector; dir_store the storage of the shifted directions.
 inline int vec_prec(int prec) { return prec == 0 ? 0 : 1; }
+// precisions 4 / 5: the stencil's input vectors rounded to FP16 / BF16 after they are written
+inline int vec16_mode(int prec) { return prec == 4 ? 1 : prec == 5 ? 2 : 0; }
 inline int dir_store(int prec) { return prec == 2 ? kDirF16 : prec == 3 ? kDirBF16 : kDirF32; }
 
 size_t bytes_per_slot(const smpq_ctx *c, int prec, int NS) {
@@ -487,6 +489,8 @@ void enqueue_iteration(smpq_ctx *c, int prec, const MSState &S, bool y64, bool x
     if (tm) tm->dslash.record(s, captured);
     launch_dslash(vp, false, 3, U, w.p.p, pst, pofs, w.tmp.p, rs, nullptr, 0, 0, g, c->kappa, s0, act, B, S.partial, s);
     if (tm) tm->dslash.record(s, captured);
+    const int m16 = vec16_mode(prec);
+    if (m16) launch_round16(g, S, w.tmp.p, rs, 0, m16, s);   // D_W p as 16-bit storage would hold it
     launch_scalars_alpha(S, np_ds, s);
     if (tm) tm->dslash.record(s, captured);
     launch_dslash(vp, true, 2, U, w.tmp.p, rs, 0, w.r.p, rs, w.p.p, pst, pofs, g, c->kappa, s0, act, B, S.partial, s,
@@ -497,6 +501,7 @@ void enqueue_iteration(smpq_ctx *c, int prec, const MSState &S, bool y64, bool x
     launch_shift_update(vp, g, S, w.r.p, w.p.p, y64 ? w.y.p : w.yacc.p, y64,
                         mixed ? (x64 ? w.x0.p : w.x0acc.p) : nullptr, x64, dir, w.ph.p, c->cur_xs, s);
     if (tm) tm->update.record(s, captured);
+    if (m16) launch_round16(g, S, w.p.p, pst, pofs, m16, s);   // the new base direction
     launch_compact(S, s);
 }
 
@@ -602,6 +607,8 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
     launch_scalars_init(S, np_unit, nslots, s);
     if (dir != kDirF32) launch_dir16_init(g, S, nslots, w.r.p, dir, w.ph.p, s);
     launch_compact(S, s);
+    if (vec16_mode(prec))   // the first base direction, b, with the scale |b|
+        launch_round16(g, S, w.p.p, dir == kDirF32 ? NS * rs64 / 2 : rs64 / 2, 0, vec16_mode(prec), s);
     HIPCHK(hipGetLastError());
 
     BatchResult res;
@@ -1295,7 +1302,7 @@ double time_dslash(smpq_ctx *c, StencilBench &tb, int p, int n_rhs, int n_sets, 
     HIPCHK(hipGetLastError());
     const double u = p == 0 ? 16.0 : 8.0;
     *bytes = (double)c->V * ((double)lbytes / c->V + (double)n_rhs * 24.0 * u);
-    if (pair) *bytes = 2.0 * *bytes + (double)c->V * n_rhs * 2.0 * 24.0 * u;
+    if (pair) *bytes = 2.0 * *bytes + (double)c->V * n_rhs * 24.0 * u;   // + aux and the r read
     return t / launches;
 }
 
@@ -1501,8 +1508,7 @@ smpq_status smpq_get_zolotarev(const smpq_ctx *cc, int *n, double *c0, double *c
 
 smpq_status smpq_set_solver(smpq_ctx *c, smpq_precision prec, double tol, int max_iter, int reliable) {
     return guarded(c, [&] {
-        if (prec != SMPQ_FP64 && prec != SMPQ_MIXED_FP32 && prec != SMPQ_MIXED_FP16DIR && prec != SMPQ_MIXED_BF16DIR)
-            throw Fail{SMPQ_EINVAL, "unknown precision"};
+        if (prec < SMPQ_FP64 || prec > SMPQ_MIXED_BF16VEC) throw Fail{SMPQ_EINVAL, "unknown precision"};
         if (!(tol > 0.0 && tol < 1.0)) throw Fail{SMPQ_EINVAL, "tol must be in (0, 1)"};
         if (max_iter < 1) throw Fail{SMPQ_EINVAL, "max_iter must be >= 1"};
         if (reliable < 0 || reliable % kGroup != 0)
@@ -2090,6 +2096,35 @@ smpq_status smpq_bench_copy(smpq_ctx *c, size_t bytes, int launches, double *ms)
     });
 }
 
+smpq_status smpq_bench_stream(smpq_ctx *c, size_t bytes, int launches, int nontemporal, double *ms) {
+    return guarded(c, [&] {
+        if (bytes < 16 || launches < 1 || !ms || (nontemporal != 0 && nontemporal != 1))
+            throw Fail{SMPQ_EINVAL, "need bytes >= 16, launches >= 1, nontemporal 0 or 1 and an output"};
+        need_device(c);
+        const size_t n = bytes / 16;
+        DevMem a, b;
+        a.ensure(n * 16);
+        b.ensure(n * 16);
+        HIPCHK(hipMemsetAsync(a.p, 0, n * 16, c->stream));
+        HIPCHK(hipMemsetAsync(b.p, 0, n * 16, c->stream));
+        launch_stream_copy(nontemporal == 1, a.p, b.p, n, c->stream);   // warm-up
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, c->stream));
+        for (int i = 0; i < launches; ++i)
+            launch_stream_copy(nontemporal == 1, i % 2 ? b.p : a.p, i % 2 ? a.p : b.p, n, c->stream);
+        HIPCHK(hipEventRecord(e1, c->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        HIPCHK(hipGetLastError());
+        *ms = t / launches;
+    });
+}
+
 smpq_status smpq_set_tuning(smpq_ctx *c, const smpq_tuning *t) {
     return guarded(c, [&] {
         if (!t) throw Fail{SMPQ_EINVAL, "null tuning"};
@@ -2135,9 +2170,9 @@ smpq_status smpq_autotune(smpq_ctx *c, int n_rhs, smpq_tuning *chosen) {
         };
         std::vector<Cand> cand = {{0, 2, 1}, {0, 4, 1}, {0, 8, 1}};
         const Geom g0 = c->geom();
-        for (int kind = 1; kind <= 3; ++kind) {
-            if (kind == 2 ? g0.tile_y == 0 : !plane_tileable(g0)) continue;
-            for (int nr : {4, 8, 16})
+        for (int kind = 1; kind <= 4; ++kind) {
+            if (kind == 2 || kind == 4 ? g0.tile_y == 0 : !plane_tileable(g0)) continue;
+            for (int nr : kind == 4 ? std::vector<int>{2, 4, 8} : std::vector<int>{4, 8, 16})
                 for (int band : {1, 2, 4})
                     if (c->dims[2] % band == 0) cand.push_back({kind, nr, band});
         }
@@ -2152,6 +2187,10 @@ smpq_status smpq_autotune(smpq_ctx *c, int n_rhs, smpq_tuning *chosen) {
                 c->band = k.band;
                 const double t = std::min(time_dslash(c, tb, 1, n_rhs, 2, 10, &by, true),
                                           time_dslash(c, tb, 1, n_rhs, 2, 10, &by, true));
+                if (c->trace)
+                    std::fprintf(stderr, "smpq: autotune FP32 kind %d, %d per block/thread, band %d: %.3f ms per pair "
+                                 "(%.0f GB/s) on %d right-hand sides\n", k.kind, k.nr, k.band, t, by / t * 1e-6,
+                                 std::min(n_rhs, tb.n_rhs));
                 if (t < best) {
                     best = t;
                     pick = k;
@@ -2176,6 +2215,10 @@ smpq_status smpq_autotune(smpq_ctx *c, int n_rhs, smpq_tuning *chosen) {
                 c->f64_nr = k.nr;
                 const double t = std::min(time_dslash(c, tb, 0, n_rhs, 2, 10, &by, true),
                                           time_dslash(c, tb, 0, n_rhs, 2, 10, &by, true));
+                if (c->trace)
+                    std::fprintf(stderr, "smpq: autotune FP64 kind %d, lanes 2^%d / %d per block: %.3f ms per pair "
+                                 "(%.0f GB/s) on %d right-hand sides\n", k.kind, k.lgr, k.nr, t, by / t * 1e-6,
+                                 std::min(n_rhs, tb.n_rhs));
                 if (t < best) {
                     best = t;
                     p64 = k;

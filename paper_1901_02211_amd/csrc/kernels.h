@@ -123,6 +123,11 @@ void launch_shift_update(int prec, const Geom &g, const MSState &s, const void *
 void launch_fold(const Geom &g, Slots sl, int max_slots, double2 *y, void *yacc, double2 *x0, void *x0acc,
                  hipStream_t st);
 void launch_compact(const MSState &s, hipStream_t st);
+// Evaluated precision: FP32 vectors of the listed slots (v + slot * slot_stride + extra, in
+// float4 units) rounded in place to FP16 (mode 1, scaled by sqrt(|r|^2 / (24 V)) of the slot)
+// or BF16 (mode 2).
+void launch_round16(const Geom &g, const MSState &s, void *v, size_t slot_stride, size_t extra, int mode,
+                    hipStream_t st);
 void launch_reliable(int prec, const Geom &g, const MSState &s, const Source &src, const double2 *ap64,
                      void *r, hipStream_t st);
 void launch_scalars_rr(const MSState &s, int npart, hipStream_t st);
@@ -168,6 +173,9 @@ void launch_contract(const Geom &g, const double2 *U64, const double2 *y, double
 void launch_lanczos_update(const Geom &g, double2 *w, const double2 *v, const double2 *vprev, double alpha,
                            double beta, double *partial, hipStream_t st);
 void launch_scale(const Geom &g, double2 *dst, const double2 *src, double f, hipStream_t st);
+// dst = src over n float4 with cached (nontemporal = false) or non-temporal loads and stores:
+// kernels of known size for scaling hardware byte counters
+void launch_stream_copy(bool nontemporal, const void *src, void *dst, size_t n_float4, hipStream_t st);
 // layout conversion between FP64 (double2 x 12) and FP32 (float4 x 6) spinors, n slots
 void launch_convert(int to_prec, const Geom &g, const void *src, void *dst, int nslots, hipStream_t st);
 // host spinor layout [slot][site][12] double2 (V sites per slot) <-> device [slot][12][vs]

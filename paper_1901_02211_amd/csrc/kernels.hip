@@ -27,6 +27,7 @@
 // right-hand side), so every FP64 result is bitwise reproducible from run to run.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <stdexcept>
 #include <type_traits>
 
@@ -707,13 +708,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 8))) 
                                               g, kappa, sigma, sl, nsb, partial, pstride, alpha, status);
 }
 
-// FP64 stencil on xy-tiles, the data flow of the FP32 tile kernel in FP64: a block of nx * ty
-// threads (ty = g.tile_y rows of one (z, t) plane, one site per thread) stages, per right-hand
-// side, its rows of the input in LDS (with one halo row on each side, unless the tile is the
-// whole plane and y wraps inside it), so that the +-x and +-y neighbours come from LDS and only
-// +-z and +-t from global memory.  Links: the first two rows of each FP64 link (96 bytes), the
-// third rebuilt as conj(row0 x row1) (exact for SU(3) up to rounding); they are read for every
-// right-hand side and stay in L2 across the block's NR right-hand sides.
+// Stencil on xy-tiles with the links read for every right-hand side (FP64 kind 1, FP32 kind 4):
+// a block of nx * ty threads (ty = g.tile_y rows of one (z, t) plane, one site per thread)
+// stages, per right-hand side, its rows of the input in LDS (with one halo row on each side,
+// unless the tile is the whole plane and y wraps inside it), so that the +-x and +-y neighbours
+// come from LDS and only +-z and +-t from global memory.  Links: their first two rows (FP64
+// 96 bytes, FP32 48), the third rebuilt as conj(row0 x row1) (exact for SU(3) up to rounding),
+// read for every right-hand side from L2 rather than held in registers across them, which
+// leaves registers for two (FP64) or more (FP32) waves per SIMD.
 __device__ __forceinline__ void load_link64_rows(const double2 *U, int V, int mu, int s, cpx<double> u[9]) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
@@ -727,19 +729,45 @@ __device__ __forceinline__ void load_link64_rows(const double2 *U, int V, int mu
     u[7] = {r1.re, -r1.im};
     u[8] = {r2.re, -r2.im};
 }
+__device__ __forceinline__ void load_link_rows(const double2 *U, int V, int mu, int s, cpx<double> u[9]) {
+    load_link64_rows(U, V, mu, s, u);
+}
+__device__ __forceinline__ void load_link_rows(const float4 *U, int V, int mu, int s, cpx<float> u[9]) {
+    load_link<float>(U, V, mu, s, u);
+}
+// the spinor at LDS position l of a tile held as [unit][tsites]
+__device__ __forceinline__ void tile_read(const double2 *tile, int tsites, int l, cpx<double> p[12]) {
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+        const double2 t = tile[j * tsites + l];
+        p[j] = {t.x, t.y};
+    }
+}
+__device__ __forceinline__ void tile_read(const float4 *tile, int tsites, int l, cpx<float> p[12]) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const float4 t = tile[j * tsites + l];
+        p[2 * j] = {t.x, t.y};
+        p[2 * j + 1] = {t.z, t.w};
+    }
+}
 
-template <int NR, bool DAG, int EPI>
-__global__ __launch_bounds__(kBlock) void k_dslash_f64_tile(const double2 *__restrict__ U,
-                                                            const double2 *__restrict__ in, size_t in_stride,
-                                                            size_t in_extra, double2 *__restrict__ out,
-                                                            size_t out_stride, const double2 *__restrict__ aux,
-                                                            size_t aux_stride, size_t aux_extra, Geom g, double kappa,
-                                                            double sigma, Slots sl, int nsb,
-                                                            double *__restrict__ partial, size_t pstride,
-                                                            const double *__restrict__ alpha,
-                                                            const int *__restrict__ status) {
+template <class T, int NR, bool DAG, int EPI>
+__global__ __launch_bounds__(kBlock) void k_dslash_tile_rl(const typename Store<T>::link *__restrict__ U,
+                                                           const typename Store<T>::vec *__restrict__ in,
+                                                           size_t in_stride, size_t in_extra,
+                                                           typename Store<T>::vec *__restrict__ out, size_t out_stride,
+                                                           const typename Store<T>::vec *__restrict__ aux,
+                                                           size_t aux_stride, size_t aux_extra, Geom g, T kappa,
+                                                           T sigma, Slots sl, int nsb, double *__restrict__ partial,
+                                                           size_t pstride, const double *__restrict__ alpha,
+                                                           const int *__restrict__ status) {
+    using vec = typename Store<T>::vec;
+    using link = typename Store<T>::link;
     constexpr int SF = DAG ? -1 : 1;
-    extern __shared__ double2 tile64[];   // [12][tsites]
+    constexpr int UN = Store<T>::units;
+    extern __shared__ __align__(16) unsigned char tile_raw[];
+    vec *tile = reinterpret_cast<vec *>(tile_raw);   // [UN][tsites]
     const int L = xcd_swizzle(blockIdx.x, gridDim.x);
     const int sb = L % nsb, rg = L / nsb;
     const int cnt = slot_count(sl);
@@ -775,59 +803,55 @@ __global__ __launch_bounds__(kBlock) void k_dslash_f64_tile(const double2 *__res
         const int k = k0 + r;
         if (k >= cnt) break;  // uniform over the block
         const int slot = slot_of(sl, k);
-        const double2 *src = in + slot * in_stride + in_extra;
-        // the links are re-read for every right-hand side: kept across the loop (as the compiler
-        // would hoist them) eight FP64 links need 192 registers; an empty asm makes the base
-        // pointer opaque in each iteration
-        const double2 *Ur = U;
+        const vec *src = in + slot * in_stride + in_extra;
+        // the links are re-read for every right-hand side: an empty asm makes the base pointer
+        // opaque in each iteration, so that the compiler does not hoist all eight links out of
+        // the loop into registers
+        const link *Ur = U;
         asm volatile("" : "+s"(Ur));
         __syncthreads();  // the previous right-hand side is done with the tile
 #pragma unroll
-        for (int j = 0; j < 12; ++j) tile64[j * tsites + me] = src[j * g.vs + s];
+        for (int j = 0; j < UN; ++j) tile[j * tsites + me] = src[j * g.vs + s];
         if (halo) {
 #pragma unroll
-            for (int j = 0; j < 12; ++j) tile64[j * tsites + hl] = src[j * g.vs + hsite];
+            for (int j = 0; j < UN; ++j) tile[j * tsites + hl] = src[j * g.vs + hsite];
         }
         __builtin_amdgcn_sched_barrier(0);   // the staging loads are not held across the hops
-        cpx<double> acc[12], u[9], p[12], h[6], w[6];
+        cpx<T> acc[12], u[9], p[12], h[6], w[6];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) acc[c] = {0.0, 0.0};
-#define SMPQ_HOP64(MU, LOADF, LOADB)                                                 \
-        load_link64_rows(Ur, g.V, MU, s, u);                                         \
+        for (int c = 0; c < 12; ++c) acc[c] = {T(0), T(0)};
+#define SMPQ_HOPT(MU, LOADF, LOADB)                                                  \
+        load_link_rows(Ur, g.V, MU, s, u);                                           \
         LOADF                                                                        \
         project<MU, SF>(p, h);                                                       \
         su3_mul(u, h, w);                                                            \
         accumulate<MU, SF>(acc, w);                                                  \
-        load_link64_rows(Ur, g.V, MU, nb.bwd[MU], u);                                \
+        load_link_rows(Ur, g.V, MU, nb.bwd[MU], u);                                  \
         LOADB                                                                        \
         project<MU, -SF>(p, h);                                                      \
         su3_dag_mul(u, h, w);                                                        \
         accumulate<MU, -SF>(acc, w);
-#define SMPQ_G64(S_) Store<double>::load(src, g.vs, S_, p);
-#define SMPQ_T64(L_)                                                                 \
-        _Pragma("unroll") for (int j = 0; j < 12; ++j) {                             \
-            const double2 t_ = tile64[j * tsites + (L_)];                            \
-            p[j] = {t_.x, t_.y};                                                     \
-        }
+#define SMPQ_GT(S_) Store<T>::load(src, g.vs, S_, p);
+#define SMPQ_TT(L_) tile_read(tile, tsites, L_, p);
         // one direction at a time: loads of later directions hoisted above earlier ones would hold
-        // more FP64 links and spinors in registers than two waves per SIMD allow
-        SMPQ_HOP64(2, SMPQ_G64(nb.fwd[2]), SMPQ_G64(nb.bwd[2]))
+        // more links and spinors in registers than the occupancy target allows
+        SMPQ_HOPT(2, SMPQ_GT(nb.fwd[2]), SMPQ_GT(nb.bwd[2]))
         __builtin_amdgcn_sched_barrier(0);
-        SMPQ_HOP64(3, SMPQ_G64(nb.fwd[3]), SMPQ_G64(nb.bwd[3]))
+        SMPQ_HOPT(3, SMPQ_GT(nb.fwd[3]), SMPQ_GT(nb.bwd[3]))
         __syncthreads();  // the tile is complete
-        SMPQ_HOP64(0, SMPQ_T64(xf), SMPQ_T64(xb))
+        SMPQ_HOPT(0, SMPQ_TT(xf), SMPQ_TT(xb))
         __builtin_amdgcn_sched_barrier(0);
-        SMPQ_HOP64(1, SMPQ_T64(yf), SMPQ_T64(yb))
-        cpx<double> v[12];
-        SMPQ_T64(me)
-#undef SMPQ_T64
-#undef SMPQ_G64
-#undef SMPQ_HOP64
+        SMPQ_HOPT(1, SMPQ_TT(yf), SMPQ_TT(yb))
+        cpx<T> v[12];
+        SMPQ_TT(me)
+#undef SMPQ_TT
+#undef SMPQ_GT
+#undef SMPQ_HOPT
 #pragma unroll
         for (int c = 0; c < 12; ++c) v[c] = p[c] - kappa * acc[c];
-        double d = stencil_epilogue<double, EPI>(v, p, aux + slot * aux_stride + aux_extra, out + slot * out_stride,
-                                                 g.vs, s, sigma, EPI == 2 ? alpha[slot] : 0.0,
-                                                 EPI == 2 ? status[slot] == kStatusOK : true);
+        double d = stencil_epilogue<T, EPI>(v, p, aux + slot * aux_stride + aux_extra, out + slot * out_stride, g.vs, s,
+                                            sigma, EPI == 2 ? (T)alpha[slot] : T(0),
+                                            EPI == 2 ? status[slot] == kStatusOK : true);
         if constexpr (EPI != 0) {
             d = wave_sum(d);
             if (lane == 0) ldsdot[r][wv] = d;
@@ -859,7 +883,7 @@ static int tile_blocks(const Geom &g) { return g.V / (g.nx * g.tile_y); }
 
 int dslash_partials(int prec, const Geom &g) {
     if (prec == 0) return g.f64_kind == 1 ? tile_blocks(g) : fp64_parts(g);
-    return g.f32_kind == 2 ? tile_blocks(g) : site_blocks(g);
+    return g.f32_kind == 2 || g.f32_kind == 4 ? tile_blocks(g) : site_blocks(g);
 }
 
 bool valid_tuning(int prec, const Geom &g) {
@@ -874,22 +898,25 @@ bool valid_tuning(int prec, const Geom &g) {
     const bool tiled = g.tile_y > 0 && g.tile_y == tile_rows(g.nx, g.ny);
     const bool band_ok = g.band >= 1 && g.nz % g.band == 0;
     if (g.f32_kind == 2) return tiled && nr_tile && band_ok;
+    if (g.f32_kind == 4) return tiled && band_ok && (g.f32_nr == 2 || g.f32_nr == 4 || g.f32_nr == 8);
     return g.f32_kind == 0 && (g.f32_nr == 2 || g.f32_nr == 4 || g.f32_nr == 8);
 }
 
-template <int NR, bool DAG, int EPI>
-static void launch_f64_tile(const void *U, const void *in, size_t in_stride, size_t in_extra, void *out,
-                            size_t out_stride, const void *aux, size_t aux_stride, size_t aux_extra, const Geom &g,
-                            double kappa, double sigma, Slots sl, int max_slots, double *partial, const double *alpha,
-                            const int *status, hipStream_t st) {
+template <class T, int NR, bool DAG, int EPI>
+static void launch_tile_rl(const void *U, const void *in, size_t in_stride, size_t in_extra, void *out,
+                           size_t out_stride, const void *aux, size_t aux_stride, size_t aux_extra, const Geom &g,
+                           double kappa, double sigma, Slots sl, int max_slots, double *partial, const double *alpha,
+                           const int *status, hipStream_t st) {
+    using vec = typename Store<T>::vec;
+    using link = typename Store<T>::link;
     const int nsb = tile_blocks(g);
     const int ngr = (max_slots + NR - 1) / NR;
     const int rows = g.tile_y == g.ny ? g.tile_y : g.tile_y + 2;
-    const size_t lds = (size_t)rows * g.nx * 12 * sizeof(double2);
-    hipLaunchKernelGGL((k_dslash_f64_tile<NR, DAG, EPI>), dim3(nsb * ngr), dim3(g.nx * g.tile_y), lds, st,
-                       (const double2 *)U, (const double2 *)in, in_stride, in_extra, (double2 *)out, out_stride,
-                       (const double2 *)aux, aux_stride, aux_extra, g, kappa, sigma, sl, nsb, partial,
-                       partial_stride(g), alpha, status);
+    const size_t lds = (size_t)rows * g.nx * Store<T>::units * sizeof(vec);
+    hipLaunchKernelGGL((k_dslash_tile_rl<T, NR, DAG, EPI>), dim3(nsb * ngr), dim3(g.nx * g.tile_y), lds, st,
+                       (const link *)U, (const vec *)in, in_stride, in_extra, (vec *)out, out_stride, (const vec *)aux,
+                       aux_stride, aux_extra, g, (T)kappa, (T)sigma, sl, nsb, partial, partial_stride(g), alpha,
+                       status);
 }
 
 template <class T, bool DAG, int EPI>
@@ -902,8 +929,8 @@ static void launch_dslash_t(const void *U, const void *in, size_t in_stride, siz
     if constexpr (std::is_same<T, double>::value) {
         if (g.f64_kind == 1) {
 #define SMPQ_F64T(NR)                                                                                             \
-    launch_f64_tile<NR, DAG, EPI>(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra, g, kappa, \
-                                  sigma, sl, max_slots, partial, alpha, status, st)
+    launch_tile_rl<double, NR, DAG, EPI>(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra, g, \
+                                         kappa, sigma, sl, max_slots, partial, alpha, status, st)
             if (g.f64_nr == 2) SMPQ_F64T(2);
             else if (g.f64_nr == 8) SMPQ_F64T(8);
             else SMPQ_F64T(4);
@@ -957,7 +984,15 @@ static void launch_f32_tuned(const void *U, const void *in, size_t in_stride, si
 #define SMPQ_F32(NR, PL)                                                                                       \
     launch_f32<NR, DAG, EPI, PL>(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra, g, kappa, \
                                  sigma, sl, max_slots, partial, alpha, status, st)
-    if (g.f32_kind == 2) {
+    if (g.f32_kind == 4) {
+#define SMPQ_F32RL(NR)                                                                                            \
+    launch_tile_rl<float, NR, DAG, EPI>(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra, g, \
+                                        kappa, sigma, sl, max_slots, partial, alpha, status, st)
+        if (g.f32_nr == 2) SMPQ_F32RL(2);
+        else if (g.f32_nr == 8) SMPQ_F32RL(8);
+        else SMPQ_F32RL(4);
+#undef SMPQ_F32RL
+    } else if (g.f32_kind == 2) {
         if (g.f32_nr == 4) SMPQ_F32(4, 2);
         else if (g.f32_nr == 16) SMPQ_F32(16, 2);
         else SMPQ_F32(8, 2);
@@ -1548,6 +1583,35 @@ void launch_fold(const Geom &g, Slots sl, int max_slots, double2 *y, void *yacc,
     hipLaunchKernelGGL(k_fold, grid, dim3(kBlock), 0, st, g, sl, y, (float4 *)yacc, x0, (float4 *)x0acc);
 }
 
+// Evaluated precision: an FP32 vector of every listed slot rounded in place to what 16-bit
+// storage would hold, FP16 after division by the slot's scale sqrt(|r|^2 / (24 V)) (entries of
+// a vector of norm ~|r| then lie near 1) or BF16 (FP32's exponent range); round to nearest
+// even.  Applied to the vectors the stencil reads (the base direction and D_W p) after the
+// kernels that write them, so that those compute in FP32 and only storage is emulated.
+__global__ __launch_bounds__(kBlock) void k_round16(Geom g, MSState S, float4 *v, size_t slot_stride, size_t extra,
+                                                    int mode) {
+    if ((int)blockIdx.y >= *S.count) return;
+    const int slot = S.list[blockIdx.y];
+    const int nsb = site_blocks(g);
+    const int u = blockIdx.x / nsb;
+    const int s = (blockIdx.x % nsb) * kBlock + threadIdx.x;
+    if (s >= g.V) return;
+    float4 *p = v + slot * slot_stride + extra + (size_t)u * g.vs + s;
+    const float scale = mode == 1 ? (float)sqrt(S.rr[slot] / (24.0 * (double)g.V)) : 1.f;
+    const float sc = scale > 0.f ? scale : 1.f, inv = 1.f / sc;
+    const float4 t = *p;
+    float x[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[i] = mode == 1 ? (float)(_Float16)(x[i] * inv) * sc : (float)(__bf16)x[i];
+    *p = make_float4(x[0], x[1], x[2], x[3]);
+}
+
+void launch_round16(const Geom &g, const MSState &s, void *v, size_t slot_stride, size_t extra, int mode,
+                    hipStream_t st) {
+    dim3 grid(unit_parts(1, g), s.B);
+    hipLaunchKernelGGL(k_round16, grid, dim3(kBlock), 0, st, g, s, (float4 *)v, slot_stride, extra, mode);
+}
+
 // Ordered list of the slots still iterating.
 __global__ void k_compact(MSState S) {
     if (threadIdx.x != 0) return;
@@ -2016,6 +2080,32 @@ void launch_convert(int to_prec, const Geom &g, const void *src, void *dst, int 
         hipLaunchKernelGGL(k_to_f32, grid, dim3(kBlock), 0, st, g, (const double2 *)src, (float4 *)dst);
     else
         hipLaunchKernelGGL(k_to_f64, grid, dim3(kBlock), 0, st, g, (const float4 *)src, (double2 *)dst);
+}
+
+// ------------------------------------------------------------------ calibration
+// dst = src over n float4 (grid-stride), with cached or non-temporal loads and stores: kernels of
+// known size (n * 16 bytes read and written) for scaling hardware byte counters.
+template <bool NT>
+__global__ __launch_bounds__(kBlock) void k_stream_copy(const float4 *__restrict__ src, float4 *__restrict__ dst,
+                                                        size_t n) {
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+        if constexpr (NT) {
+            const f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(src + i));
+            __builtin_nontemporal_store(t, reinterpret_cast<f32x4 *>(dst + i));
+        } else {
+            dst[i] = src[i];
+        }
+    }
+}
+
+void launch_stream_copy(bool nontemporal, const void *src, void *dst, size_t n_float4, hipStream_t st) {
+    const size_t blocks = std::min<size_t>((n_float4 + kBlock - 1) / kBlock, 8192);
+    if (nontemporal)
+        hipLaunchKernelGGL(k_stream_copy<true>, dim3((unsigned)blocks), dim3(kBlock), 0, st, (const float4 *)src,
+                           (float4 *)dst, n_float4);
+    else
+        hipLaunchKernelGGL(k_stream_copy<false>, dim3((unsigned)blocks), dim3(kBlock), 0, st, (const float4 *)src,
+                           (float4 *)dst, n_float4);
 }
 
 }  // namespace smpq

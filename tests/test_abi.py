@@ -120,10 +120,11 @@ def test_argument_errors():
     with pytest.raises(smpq.SmpqError) as e:
         smpq.smpq_autotune(c, -1)
     assert e.value.status == -1
-    for bad in (4, 5, -1):
+    for bad in (6, 7, -1):
         with pytest.raises(smpq.SmpqError):
             smpq.smpq_set_solver(c, bad, 1e-12, 10, 0)
-    for ok in (smpq.SMPQ_MIXED_FP16DIR, smpq.SMPQ_MIXED_BF16DIR, smpq.SMPQ_FP64):
+    for ok in (smpq.SMPQ_MIXED_FP16DIR, smpq.SMPQ_MIXED_BF16DIR, smpq.SMPQ_MIXED_FP16VEC, smpq.SMPQ_MIXED_BF16VEC,
+               smpq.SMPQ_FP64):
         smpq.smpq_set_solver(c, ok, 1e-12, 10, 0)
     V = 4 * 4 * 4 * 6
     U = np.zeros((V, 4, 3, 3), dtype=complex)

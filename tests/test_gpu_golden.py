@@ -141,6 +141,38 @@ def test_flux8_dir16_storage(prec, bound, qbound):
     assert np.abs(o16 - o32).max() < 10 * bound * np.abs(o32).max()
 
 
+def test_flux8_stencil_inputs_in_16_bits():
+    """The evaluated precisions that store the stencil's inputs (the base search direction and
+    D_W p) in 16 bits.  FP16 (scaled per right-hand side): the FP64 reliable updates still bring
+    every base system to the tolerance, in more iterations, but q(x) carries the storage's
+    rounding through the shifted solutions, which no residual replacement corrects (measured:
+    max |dq| 2.3e-4, dQ 1.8e-2, 23 % more iterations: outside the mixed path's 1e-5 / 1e-4).
+    BF16 (8-bit significand): the perturbed operator products break CG down (<p, A p> <= 0),
+    or, should a rounding order avoid that, leave errors beyond the mixed tolerances."""
+    print("flux8 SMP r=2 full map, stencil inputs in 16 bits", flush=True)
+    g = _golden("flux8_smp2")
+    ref = _ctx("flux8", smpq.SMPQ_MIXED_FP32)
+    smpq.smpq_set_scheme(ref, (2, 2, 2, 2), 0)
+    _, _, _, st32 = smpq.smpq_compute_qx(ref)
+    c = _ctx("flux8", smpq.SMPQ_MIXED_FP16VEC)
+    smpq.smpq_set_scheme(c, (2, 2, 2, 2), 0)
+    q, qi, Q, st = smpq.smpq_compute_qx(c)
+    err = float(np.abs(q - g["qx"]).max())
+    print(f"FP16 stencil inputs: max |dq| {err:.3e}, dQ {Q - g['qx'].sum():.3e}, iterations "
+          f"{st['total_iters']} (FP32 {st32['total_iters']}), base true residual {st['max_true_resid']:.2e}",
+          flush=True)
+    assert 0.0 < st["max_true_resid"] <= 10 * TOL
+    assert np.isfinite(err) and 1e-5 < err < 0.1 and st["total_iters"] > st32["total_iters"]
+    smpq.smpq_set_solver(c, smpq.SMPQ_MIXED_BF16VEC, TOL, 10000, 50)
+    try:
+        q16 = smpq.smpq_compute_qx(c)[0]
+        print(f"BF16 stencil inputs: max |dq| {np.abs(q16 - g['qx']).max():.3e}", flush=True)
+        assert np.abs(q16 - g["qx"]).max() > 1e-5
+    except smpq.SmpqError as e:
+        print(f"BF16 stencil inputs: {e}", flush=True)
+        assert e.status == -7
+
+
 def test_flux8_point_subset():
     print("flux8 point sources on the 64-site subset", flush=True)
     g = _golden("flux8_point")

@@ -38,6 +38,8 @@ SITE_VARIANTS = [(0, nr, lgr) for nr, lgr in ((2, 0), (4, 1), (8, 2))]
 PLANE_VARIANTS = [(k, nr, lgr) for k in (1, 3) for nr, lgr in ((4, 0), (8, 1), (16, 2))]
 TILE_VARIANTS = [(2, nr, lgr) for nr, lgr in ((4, 0), (8, 1), (16, 2))]
 F64_TILE_NR = (2, 4, 8)       # FP64 xy-tile kernel (f64_kind 1): right-hand sides per block
+# FP32 xy-tiles with the links read per right-hand side (kind 4): 2, 4, 8 right-hand sides per block
+RL_VARIANTS = [(4, nr, lgr) for nr, lgr in ((2, 0), (4, 1), (8, 2))]
 
 
 @pytest.mark.parametrize("dims", [(6, 4, 4, 6), (5, 3, 4, 7), (4, 4, 4, 4)])
@@ -77,7 +79,7 @@ def test_dslash_parity_plane_tiled(dims, nrhs):
     c = _ctx(dims, U)
     for dag in (False, True):
         ref = np.stack([apply_dw(U, lat, KAPPA, p, dagger=dag) for p in psi])
-        for tune in PLANE_VARIANTS + TILE_VARIANTS:
+        for tune in PLANE_VARIANTS + TILE_VARIANTS + RL_VARIANTS:
             for band in (1, 2, 4):
                 if dims[2] % band:
                     continue
@@ -105,7 +107,8 @@ def test_autotune_picks_a_valid_variant_and_keeps_parity():
     c = _ctx(dims, U)
     t = smpq.smpq_autotune(c, 8)
     assert smpq.smpq_get_tuning(c) == t
-    assert (t["f32_kind"], t["f32_nr"]) in [(k, n) for k, n, _ in SITE_VARIANTS + PLANE_VARIANTS + TILE_VARIANTS]
+    assert (t["f32_kind"], t["f32_nr"]) in [(k, n) for k, n, _ in SITE_VARIANTS + PLANE_VARIANTS + TILE_VARIANTS
+                                            + RL_VARIANTS]
     assert t["f64_lgr"] in (0, 1, 2) and t["plane_band"] in (1, 2)
     assert (t["f64_kind"], t["f64_nr"]) in [(0, t["f64_nr"])] + [(1, n) for n in F64_TILE_NR]
     ref = np.stack([apply_dw(U, lat, KAPPA, p) for p in psi])
@@ -120,7 +123,8 @@ def test_autotune_picks_a_valid_variant_and_keeps_parity():
     smpq.smpq_set_scheme(c, (2, 2, 2, 2), 0)
     smpq.smpq_set_zolotarev(c, 14, 0.15, 2.75)
     t0 = smpq.smpq_autotune(c, 0)
-    assert (t0["f32_kind"], t0["f32_nr"]) in [(k, n) for k, n, _ in SITE_VARIANTS + PLANE_VARIANTS + TILE_VARIANTS]
+    assert (t0["f32_kind"], t0["f32_nr"]) in [(k, n) for k, n, _ in SITE_VARIANTS + PLANE_VARIANTS + TILE_VARIANTS
+                                              + RL_VARIANTS]
     out32 = smpq.smpq_apply_dw(c, psi, precision=smpq.SMPQ_MIXED_FP32)
     assert np.abs(out32 - ref).max() <= 2e-6 * np.abs(ref).max()
 
@@ -140,7 +144,7 @@ def test_dslash_parity_xy_tiles(dims, nrhs):
             smpq.smpq_set_tuning(c, kind, 8, 1)
     for dag in (False, True):
         ref = np.stack([apply_dw(U, lat, KAPPA, p, dagger=dag) for p in psi])
-        for tune in TILE_VARIANTS:
+        for tune in TILE_VARIANTS + RL_VARIANTS:
             for band in (1, 2, 4):
                 if dims[2] % band:
                     continue
@@ -159,7 +163,7 @@ def test_dslash_parity_xy_tiles(dims, nrhs):
 
 
 @pytest.mark.parametrize("dims,kind,band", [((16, 16, 2, 2), 1, 1), ((16, 16, 2, 2), 2, 2), ((24, 16, 2, 2), 2, 2),
-                                             ((16, 16, 2, 2), 3, 2)])
+                                             ((16, 16, 2, 2), 3, 2), ((16, 16, 2, 2), 4, 1), ((24, 16, 2, 2), 4, 2)])
 def test_qx_plane_tiled_mixed(dims, kind, band):
     lat = Lattice(dims)
     U = si.near_identity_su3(dims, 0.3, 13)
