@@ -76,6 +76,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+# names of the FP32 stencil variants, by the tuning's kind number
+F32_KINDS = ("site", "plane", "xy-tile", "plane, xy links in LDS", "xy-tile, links read per right-hand side")
+
+
 def measured_traffic(kernel, workload):
     """Counter-measured HBM bytes / algorithmic bytes of a kernel, from the committed summary,
     if it was measured on the current kernel source and this workload."""
@@ -460,12 +464,14 @@ def main():
                                 + DIR_STORAGE[args.dir_storage][1],
                    "classes": len(classes), "classes_per_map": ncls,
                    "extrapolated": scale != 1.0,
-                   "stencil_variants": {"f32_kind": ["site", "plane", "xy-tile", "plane, xy links in LDS"][tuning["f32_kind"]],
+                   "stencil_variants": {"f32_kind": F32_KINDS[tuning["f32_kind"]],
                                         "f32_rhs_per_thread": tuning["f32_nr"],
                                         "plane_band": tuning["plane_band"],
                                         "f64_kind": ["lanes", "xy-tile"][tuning.get("f64_kind", 0)],
                                         "f64_rhs_per_block": (tuning["f64_nr"] if tuning.get("f64_kind", 0) == 1
-                                                              else 1 << tuning["f64_lgr"])}},
+                                                              else 1 << tuning["f64_lgr"]),
+                                        "f32_interleave": tuning.get("f32_interleave", 1),
+                                        "f64_interleave": tuning.get("f64_interleave", 1)}},
         "steps_requested": args.steps, "warmup_requested": args.warmup, "budget_s": args.budget_s,
         "speedup_vs_fp64": round(fp64["s_per_map"] / (ms_per_step / 1000.0), 3),
         "roofline": roofline, "dslash": dslash, "fp64": fp64, "accuracy": accuracy,

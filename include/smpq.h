@@ -233,6 +233,16 @@ smpq_status smpq_get_coloring(const smpq_ctx *ctx, int32_t *colour);
 smpq_status smpq_apply_dw(smpq_ctx *ctx, const double *in, double *out, int n_rhs, int dagger,
                           smpq_precision prec);
 
+/* smpq_apply_dw on caller-owned device buffers: in_dev and out_dev hold n_rhs spinors in the
+ * host layout above ([rhs][site][spin][colour] complex128, 24 V doubles each) on the context's
+ * device; the layout is converted on the device and the stream is synchronised before return.
+ * Same results and errors as smpq_apply_dw (the same kernels).  The buffers must be memory of the
+ * HIP runtime this library is linked to (hipMalloc in the same process): a framework that ships
+ * its own copy of the HIP runtime (as some PyTorch wheels do) holds addresses of another runtime
+ * instance, which this library cannot use. */
+smpq_status smpq_apply_dw_dev(smpq_ctx *ctx, const double *in_dev, double *out_dev, int n_rhs, int dagger,
+                              smpq_precision prec);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid allocation): smpq_apply_dw without any allocation.  Same
  * arguments, results and errors as smpq_apply_dw (the same stencil kernels); the host layout
@@ -258,6 +268,15 @@ smpq_status smpq_apply_dov(smpq_ctx *ctx, const double *in, double *out, int n_r
  * st (nullable) receives statistics. */
 smpq_status smpq_compute_qx(smpq_ctx *ctx, double *qx, double *qx_imag, double *Q,
                             smpq_stats *st);
+
+/* smpq_compute_qx with the map left on the device: qx_dev (and qx_imag_dev, nullable) are
+ * caller-owned device buffers of V doubles on the context's device, memory of the HIP runtime
+ * this library is linked to (as for smpq_apply_dw_dev), written with device-to-device copies on
+ * the context's stream, which is synchronised before return.  Q and st as in smpq_compute_qx
+ * (Q summed on the host in the same order).  The buffers must not overlap the library's memory;
+ * the call does not check that they are device memory. */
+smpq_status smpq_compute_qx_dev(smpq_ctx *ctx, double *qx_dev, double *qx_imag_dev, double *Q,
+                                smpq_stats *st);
 
 /* As smpq_compute_qx for the listed classes only (each 0 <= class < n_classes, no
  * duplicates); sites of other classes are set to 0 in qx and qx_imag. */
@@ -383,18 +402,23 @@ smpq_status smpq_bench_stream(smpq_ctx *ctx, size_t bytes, int launches, int non
  * each side staged in LDS, ty the largest divisor of ny with nx*ty <= 256 and a multiple of 64
  * (nx <= 64; f32_nr = 4, 8 or 16); 3 = kind 1 with the plane's x and y links in LDS instead
  * of registers, at 3 waves per SIMD; 4 = kind 2's tiles with the links read for every
- * right-hand side instead of held in registers (f32_nr = 2, 4 or 8; 3-4 waves per SIMD), the
+ * right-hand side instead of held in registers (f32_nr = 1, 2, 4 or 8; 3-4 waves per SIMD), the
  * tile without halo rows when it is the whole plane.  plane_band (kinds 1-4; 1, 2 or 4, dividing nz): the
  * blocks take the (z, t) planes in bands of that many z with t running inside a band, so the
  * +-t neighbours of a plane were read shortly before (1 = z fastest).  FP64 stencil:
  * f64_kind 0 interleaves 2^f64_lgr = 1, 2 or 4 right-hand sides over the lanes of a block;
  * f64_kind 1 stages xy-tiles in LDS as FP32 kind 2 does (one halo row on each side unless the
- * tile is the whole plane), f64_nr = 2, 4 or 8 right-hand sides per block, the links read as
+ * tile is the whole plane), f64_nr = 1, 2, 4 or 8 right-hand sides per block, the links read as
  * their first two rows with the third rebuilt (where a tile fits; plane_band applies too).
+ * f32_interleave (FP32 kind 4) and f64_interleave (FP64 kind 1): 1, 2, 4, 8 or 16 blocks in a
+ * row take successive groups of right-hand sides of the same tile before the blocks move on
+ * to the next tile, so that the links a tile reads for each right-hand side come from L2;
+ * 1 for every other kind.
  * Results do not depend on the variant beyond the rounding order of sums. */
 typedef struct {
     int f32_kind, f32_nr, f64_lgr, plane_band;
     int f64_kind, f64_nr;
+    int f32_interleave, f64_interleave;
 } smpq_tuning;
 
 /* Choose the variants for this lattice by timing each on n_rhs right-hand sides as the solver
@@ -405,7 +429,7 @@ typedef struct {
  * the variants' order can change with the number of right-hand sides through L2 reuse.  The choice is kept by the context and written to
  * *chosen (may be NULL); on an error the previous choice is kept.  Without this call a
  * context uses kind 1 / 8 where the plane fits, else kind 2 / 8 where a tile fits, else kind
- * 0 / 4, with plane_band 1, f64_kind 0 and f64_lgr 1. */
+ * 0 / 4, with plane_band 1, f64_kind 0, f64_lgr 1 and both interleaves 1. */
 smpq_status smpq_autotune(smpq_ctx *ctx, int n_rhs, smpq_tuning *chosen);
 
 /* Select the variants explicitly.  SMPQ_EINVAL (previous choice kept) if a variant is not

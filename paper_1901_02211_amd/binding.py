@@ -20,7 +20,8 @@ __all__ = [
     "smpq_create", "smpq_destroy", "smpq_strerror", "smpq_last_error", "smpq_load_gauge",
     "smpq_set_kappa", "smpq_lanczos", "smpq_estimate_bounds", "smpq_set_zolotarev",
     "smpq_get_zolotarev", "smpq_set_solver", "smpq_get_settings", "SmpqSettings", "smpq_set_shift_check", "smpq_set_batch", "smpq_set_scheme",
-    "smpq_set_point_scheme", "smpq_get_coloring", "smpq_get_scheme_rmin", "smpq_apply_dw", "smpq_apply_dw_noalloc", "smpq_apply_dov",
+    "smpq_set_point_scheme", "smpq_get_coloring", "smpq_get_scheme_rmin", "smpq_apply_dw", "smpq_apply_dw_noalloc", "smpq_apply_dw_dev", "smpq_apply_dov",
+    "smpq_compute_qx_dev",
     "smpq_compute_qx", "smpq_compute_qx_classes", "smpq_compute_trinv", "smpq_dov_locality", "smpq_deflate", "smpq_compute_qx_points", "smpq_prepare", "smpq_set_stream",
     "smpq_set_timing", "smpq_set_graphs", "smpq_bench_dslash", "smpq_bench_copy", "smpq_bench_stream", "smpq_autotune",
     "smpq_set_tuning", "smpq_get_tuning", "smpq_set_memory_limit", "smpq_compute_qx_multi",
@@ -38,7 +39,8 @@ _vp = ctypes.c_void_p
 
 
 class SmpqTuning(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_int) for n in ("f32_kind", "f32_nr", "f64_lgr", "plane_band", "f64_kind", "f64_nr")]
+    _fields_ = [(n, ctypes.c_int) for n in ("f32_kind", "f32_nr", "f64_lgr", "plane_band", "f64_kind", "f64_nr",
+                                            "f32_interleave", "f64_interleave")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -90,6 +92,8 @@ _SIG = {
     "smpq_apply_dw_noalloc": (ctypes.c_int, [_vp, _c_double_p, _c_double_p, ctypes.c_int, ctypes.c_int,
                                              ctypes.c_int]),
     "smpq_apply_dov": (ctypes.c_int, [_vp, _c_double_p, _c_double_p, ctypes.c_int]),
+    "smpq_apply_dw_dev": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "smpq_compute_qx_dev": (ctypes.c_int, [_vp, _vp, _vp, _c_double_p, ctypes.POINTER(SmpqStats)]),
     "smpq_compute_qx": (ctypes.c_int, [_vp, _c_double_p, _c_double_p, _c_double_p, ctypes.POINTER(SmpqStats)]),
     "smpq_compute_qx_classes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int, _c_double_p,
                                                _c_double_p, ctypes.POINTER(SmpqStats)]),
@@ -293,6 +297,31 @@ def smpq_apply_dw_noalloc(ctx, psi, dagger=False, precision=SMPQ_FP64, out=None)
     return out
 
 
+def _dev_ptr(buf):
+    """Device address of a caller-owned buffer: an int, or an object with data_ptr().  The memory
+    must come from the HIP runtime libsmpq.so is linked to (see include/smpq.h)."""
+    if buf is None:
+        return None
+    return ctypes.c_void_p(int(buf.data_ptr()) if hasattr(buf, "data_ptr") else int(buf))
+
+
+def smpq_apply_dw_dev(ctx, in_buf, out_buf, n_rhs, dagger=False, precision=SMPQ_FP64):
+    """D_W (or D_W^dag) of n_rhs spinors in device buffers of the host layout (24 V float64 each):
+    in_buf / out_buf are device addresses or objects with data_ptr()."""
+    _check(ctx, _lib.smpq_apply_dw_dev(ctx.ptr, _dev_ptr(in_buf), _dev_ptr(out_buf), int(n_rhs),
+                                       int(bool(dagger)), int(precision)))
+
+
+def smpq_compute_qx_dev(ctx, qx_buf, qxi_buf=None):
+    """q(x) into caller-owned device buffers of V float64 (addresses or objects with data_ptr());
+    returns (Q, stats)."""
+    st = SmpqStats()
+    Q = ctypes.c_double()
+    _check(ctx, _lib.smpq_compute_qx_dev(ctx.ptr, _dev_ptr(qx_buf), _dev_ptr(qxi_buf), ctypes.byref(Q),
+                                         ctypes.byref(st)))
+    return Q.value, st.as_dict()
+
+
 def smpq_apply_dov(ctx, psi):
     psi = _spinors(ctx, psi)
     out = np.empty_like(psi)
@@ -394,8 +423,10 @@ def smpq_autotune(ctx, n_rhs=48):
     return t.as_dict()
 
 
-def smpq_set_tuning(ctx, f32_kind, f32_nr, f64_lgr, plane_band=1, f64_kind=0, f64_nr=4):
-    t = SmpqTuning(int(f32_kind), int(f32_nr), int(f64_lgr), int(plane_band), int(f64_kind), int(f64_nr))
+def smpq_set_tuning(ctx, f32_kind, f32_nr, f64_lgr, plane_band=1, f64_kind=0, f64_nr=4, f32_interleave=1,
+                    f64_interleave=1):
+    t = SmpqTuning(int(f32_kind), int(f32_nr), int(f64_lgr), int(plane_band), int(f64_kind), int(f64_nr),
+                   int(f32_interleave), int(f64_interleave))
     _check(ctx, _lib.smpq_set_tuning(ctx.ptr, ctypes.byref(t)))
 
 

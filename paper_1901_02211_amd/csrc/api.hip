@@ -214,10 +214,10 @@ struct smpq_ctx {
     long long gen = 0;
     int *h_count = nullptr;     // pinned
     // stencil variant (see Geom); defaults: plane tile where the xy-plane has 256 sites
-    int f32_kind = 0, f32_nr = 4, f64_lgr = 1, band = 1, f64_kind = 0, f64_nr = 4;
+    int f32_kind = 0, f32_nr = 4, f64_lgr = 1, band = 1, f64_kind = 0, f64_nr = 4, f32_il = 1, f64_il = 1;
     Geom geom() const {
         return Geom{dims[0], dims[1], dims[2], dims[3], V, vs, f32_kind, f32_nr, f64_lgr, band,
-                    tile_rows(dims[0], dims[1]), f64_kind, f64_nr};
+                    tile_rows(dims[0], dims[1]), f64_kind, f64_nr, f32_il, f64_il};
     }
 };
 
@@ -1711,6 +1711,37 @@ smpq_status smpq_apply_dw_noalloc(smpq_ctx *c, const double *in, double *out, in
     });
 }
 
+smpq_status smpq_apply_dw_dev(smpq_ctx *c, const double *in_dev, double *out_dev, int n, int dagger,
+                              smpq_precision prec) {
+    return guarded(c, [&] {
+        if (!in_dev || !out_dev || n < 1) throw Fail{SMPQ_EINVAL, "need input, output and n_rhs >= 1"};
+        if (prec != SMPQ_FP64 && prec != SMPQ_MIXED_FP32) throw Fail{SMPQ_EINVAL, "unknown precision"};
+        need_device(c);
+        if (!c->have_gauge) throw Fail{SMPQ_ESTATE, "no gauge field loaded"};
+        const Geom g = c->geom();
+        const size_t v64 = 12 * 16 * c->vs, v32 = 6 * 16 * c->vs;
+        DevMem a, b, a32, b32;
+        a.ensure(v64 * n);
+        b.ensure(v64 * n);
+        launch_layout(true, g, reinterpret_cast<const double2 *>(in_dev), a.as<double2>(), n, c->stream);
+        Slots sl{nullptr, nullptr, n};
+        if (prec == SMPQ_FP64) {
+            launch_dslash(0, dagger != 0, 0, c->U64.p, a.p, 12 * c->vs, 0, b.p, 12 * c->vs, nullptr, 0, 0, g,
+                          c->kappa, 0.0, sl, n, nullptr, c->stream);
+        } else {
+            a32.ensure(v32 * n);
+            b32.ensure(v32 * n);
+            launch_convert(1, g, a.p, a32.p, n, c->stream);
+            launch_dslash(1, dagger != 0, 0, c->U32.p, a32.p, 6 * c->vs, 0, b32.p, 6 * c->vs, nullptr, 0, 0, g,
+                          c->kappa, 0.0, sl, n, nullptr, c->stream);
+            launch_convert(0, g, b32.p, b.p, n, c->stream);
+        }
+        launch_layout(false, g, b.as<double2>(), reinterpret_cast<double2 *>(out_dev), n, c->stream);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(c->stream));   // the staging vectors are freed on return
+    });
+}
+
 smpq_status smpq_apply_dov(smpq_ctx *c, const double *in, double *out, int n) {
     return guarded(c, [&] {
         if (!in || !out || n < 1) throw Fail{SMPQ_EINVAL, "need input, output and n_rhs >= 1"};
@@ -1790,6 +1821,31 @@ smpq_status smpq_compute_qx(smpq_ctx *c, double *qx, double *qxi, double *Q, smp
         if (Q) {
             double s = 0.0;
             for (int i = 0; i < c->V; ++i) s += qx[i];
+            *Q = s;
+        }
+    });
+}
+
+smpq_status smpq_compute_qx_dev(smpq_ctx *c, double *qx_dev, double *qxi_dev, double *Q, smpq_stats *st) {
+    return guarded(c, [&] {
+        if (!qx_dev) throw Fail{SMPQ_EINVAL, "null output"};
+        if (!c->have_scheme) throw Fail{SMPQ_ESTATE, "no scheme set"};
+        if (st) std::memset(st, 0, sizeof(*st));
+        prepare_q(c, st);
+        ensure_scheme_device(c);
+        std::vector<int> cls(c->n_classes);
+        for (int i = 0; i < c->n_classes; ++i) cls[i] = i;
+        qx_classes(c, cls, false, st);
+        // the map stays on the device: copies into the caller's buffers on the context's stream;
+        // Q and the statistics from a host copy, summed as smpq_compute_qx sums them
+        const size_t bytes = sizeof(double) * c->V;
+        HIPCHK(hipMemcpyAsync(qx_dev, c->qx.p, bytes, hipMemcpyDeviceToDevice, c->stream));
+        if (qxi_dev) HIPCHK(hipMemcpyAsync(qxi_dev, c->qxi.p, bytes, hipMemcpyDeviceToDevice, c->stream));
+        std::vector<double> h(c->V);
+        finish_q(c, h.data(), nullptr, st);
+        if (Q) {
+            double s = 0.0;
+            for (int i = 0; i < c->V; ++i) s += h[i];
             *Q = s;
         }
     });
@@ -2135,6 +2191,8 @@ smpq_status smpq_set_tuning(smpq_ctx *c, const smpq_tuning *t) {
         g.band = t->plane_band;
         g.f64_kind = t->f64_kind;
         g.f64_nr = t->f64_nr;
+        g.f32_il = t->f32_interleave;
+        g.f64_il = t->f64_interleave;
         if (!valid_tuning(0, g) || !valid_tuning(1, g))
             throw Fail{SMPQ_EINVAL, "unsupported stencil variant for this lattice"};
         c->f32_kind = t->f32_kind;
@@ -2143,6 +2201,8 @@ smpq_status smpq_set_tuning(smpq_ctx *c, const smpq_tuning *t) {
         c->band = t->plane_band;
         c->f64_kind = t->f64_kind;
         c->f64_nr = t->f64_nr;
+        c->f32_il = t->f32_interleave;
+        c->f64_il = t->f64_interleave;
         c->gen++;
     });
 }
@@ -2150,7 +2210,7 @@ smpq_status smpq_set_tuning(smpq_ctx *c, const smpq_tuning *t) {
 smpq_status smpq_get_tuning(smpq_ctx *c, smpq_tuning *t) {
     return guarded(c, [&] {
         if (!t) throw Fail{SMPQ_EINVAL, "null tuning"};
-        *t = smpq_tuning{c->f32_kind, c->f32_nr, c->f64_lgr, c->band, c->f64_kind, c->f64_nr};
+        *t = smpq_tuning{c->f32_kind, c->f32_nr, c->f64_lgr, c->band, c->f64_kind, c->f64_nr, c->f32_il, c->f64_il};
     });
 }
 
@@ -2166,31 +2226,34 @@ smpq_status smpq_autotune(smpq_ctx *c, int n_rhs, smpq_tuning *chosen) {
         }
         double by;
         struct Cand {
-            int kind, nr, band;
+            int kind, nr, band, il;
         };
-        std::vector<Cand> cand = {{0, 2, 1}, {0, 4, 1}, {0, 8, 1}};
+        std::vector<Cand> cand = {{0, 2, 1, 1}, {0, 4, 1, 1}, {0, 8, 1, 1}};
         const Geom g0 = c->geom();
         for (int kind = 1; kind <= 4; ++kind) {
             if (kind == 2 || kind == 4 ? g0.tile_y == 0 : !plane_tileable(g0)) continue;
-            for (int nr : kind == 4 ? std::vector<int>{2, 4, 8} : std::vector<int>{4, 8, 16})
+            for (int nr : kind == 4 ? std::vector<int>{1, 2, 4, 8} : std::vector<int>{4, 8, 16})
                 for (int band : {1, 2, 4})
-                    if (c->dims[2] % band == 0) cand.push_back({kind, nr, band});
+                    // interleaving pays with few right-hand sides per block (measured: 1 or 2)
+                    for (int il : kind == 4 ? std::vector<int>{1, 2, 4} : std::vector<int>{1})
+                        if (c->dims[2] % band == 0 && (il == 1 || nr * il <= 4)) cand.push_back({kind, nr, band, il});
         }
-        const smpq_tuning keep{c->f32_kind, c->f32_nr, c->f64_lgr, c->band, c->f64_kind, c->f64_nr};
+        const smpq_tuning keep{c->f32_kind, c->f32_nr, c->f64_lgr, c->band, c->f64_kind, c->f64_nr, c->f32_il, c->f64_il};
         double best = INFINITY;
-        Cand pick{keep.f32_kind, keep.f32_nr, keep.plane_band};
+        Cand pick{keep.f32_kind, keep.f32_nr, keep.plane_band, keep.f32_interleave};
         StencilBench tb;   // one set of timing buffers per precision for the whole sweep
         try {
             for (const Cand &k : cand) {
                 c->f32_kind = k.kind;
                 c->f32_nr = k.nr;
                 c->band = k.band;
+                c->f32_il = k.il;
                 const double t = std::min(time_dslash(c, tb, 1, n_rhs, 2, 10, &by, true),
                                           time_dslash(c, tb, 1, n_rhs, 2, 10, &by, true));
                 if (c->trace)
-                    std::fprintf(stderr, "smpq: autotune FP32 kind %d, %d per block/thread, band %d: %.3f ms per pair "
-                                 "(%.0f GB/s) on %d right-hand sides\n", k.kind, k.nr, k.band, t, by / t * 1e-6,
-                                 std::min(n_rhs, tb.n_rhs));
+                    std::fprintf(stderr, "smpq: autotune FP32 kind %d, %d per block/thread, band %d, interleave %d: "
+                                 "%.3f ms per pair (%.0f GB/s) on %d right-hand sides\n", k.kind, k.nr, k.band, k.il, t,
+                                 by / t * 1e-6, std::min(n_rhs, tb.n_rhs));
                 if (t < best) {
                     best = t;
                     pick = k;
@@ -2199,26 +2262,30 @@ smpq_status smpq_autotune(smpq_ctx *c, int n_rhs, smpq_tuning *chosen) {
             c->f32_kind = pick.kind;
             c->f32_nr = pick.nr;
             c->band = pick.band;
+            c->f32_il = pick.il;
             // FP64: lanes interleaving 1, 2 or 4 right-hand sides; xy-tiles with 2, 4 or 8 per
             // block (same plane order band as the FP32 choice) where a tile fits
             best = INFINITY;
             struct Cand64 {
-                int kind, lgr, nr;
+                int kind, lgr, nr, il;
             };
-            std::vector<Cand64> c64 = {{0, 0, 4}, {0, 1, 4}, {0, 2, 4}};
+            std::vector<Cand64> c64 = {{0, 0, 4, 1}, {0, 1, 4, 1}, {0, 2, 4, 1}};
             if (g0.tile_y > 0 && c->dims[2] % c->band == 0)
-                for (int nr : {2, 4, 8}) c64.push_back({1, keep.f64_lgr, nr});
-            Cand64 p64{keep.f64_kind, keep.f64_lgr, keep.f64_nr};
+                for (int nr : {1, 2, 4, 8})
+                    for (int il : {1, 2, 4})
+                        if (il == 1 || nr * il <= 8) c64.push_back({1, keep.f64_lgr, nr, il});
+            Cand64 p64{keep.f64_kind, keep.f64_lgr, keep.f64_nr, keep.f64_interleave};
             for (const Cand64 &k : c64) {
                 c->f64_kind = k.kind;
                 c->f64_lgr = k.lgr;
                 c->f64_nr = k.nr;
+                c->f64_il = k.il;
                 const double t = std::min(time_dslash(c, tb, 0, n_rhs, 2, 10, &by, true),
                                           time_dslash(c, tb, 0, n_rhs, 2, 10, &by, true));
                 if (c->trace)
-                    std::fprintf(stderr, "smpq: autotune FP64 kind %d, lanes 2^%d / %d per block: %.3f ms per pair "
-                                 "(%.0f GB/s) on %d right-hand sides\n", k.kind, k.lgr, k.nr, t, by / t * 1e-6,
-                                 std::min(n_rhs, tb.n_rhs));
+                    std::fprintf(stderr, "smpq: autotune FP64 kind %d, lanes 2^%d / %d per block, interleave %d: "
+                                 "%.3f ms per pair (%.0f GB/s) on %d right-hand sides\n", k.kind, k.lgr, k.nr, k.il, t,
+                                 by / t * 1e-6, std::min(n_rhs, tb.n_rhs));
                 if (t < best) {
                     best = t;
                     p64 = k;
@@ -2227,6 +2294,7 @@ smpq_status smpq_autotune(smpq_ctx *c, int n_rhs, smpq_tuning *chosen) {
             c->f64_kind = p64.kind;
             c->f64_lgr = p64.lgr;
             c->f64_nr = p64.nr;
+            c->f64_il = p64.il;
         } catch (...) {
             c->f32_kind = keep.f32_kind;
             c->f32_nr = keep.f32_nr;
@@ -2234,10 +2302,12 @@ smpq_status smpq_autotune(smpq_ctx *c, int n_rhs, smpq_tuning *chosen) {
             c->band = keep.plane_band;
             c->f64_kind = keep.f64_kind;
             c->f64_nr = keep.f64_nr;
+            c->f32_il = keep.f32_interleave;
+            c->f64_il = keep.f64_interleave;
             throw;
         }
         c->gen++;   // captured graphs used the previous variants
-        if (chosen) *chosen = smpq_tuning{c->f32_kind, c->f32_nr, c->f64_lgr, c->band, c->f64_kind, c->f64_nr};
+        if (chosen) *chosen = smpq_tuning{c->f32_kind, c->f32_nr, c->f64_lgr, c->band, c->f64_kind, c->f64_nr, c->f32_il, c->f64_il};
     });
 }
 

@@ -23,9 +23,12 @@ struct Geom {
     // lanes of an FP64 block, and the z-band of the plane order of kinds 1 and 2;
     // tile_y = tile_rows(nx, ny) (0 when no tile fits); FP64 kernel kind (0: right-hand sides
     // interleaved over the lanes, 2^f64_lgr per block; 1: xy-tiles in LDS like the FP32 kind 2,
-    // f64_nr right-hand sides per block, links read per right-hand side)
+    // f64_nr right-hand sides per block, links read per right-hand side); f32_il / f64_il: in
+    // the tile kernels (FP32 kind 4, FP64 kind 1) consecutive blocks take that many groups of
+    // right-hand sides of one tile before the next tile, so that the tile's links are still in L2
     int f32_kind, f32_nr, f64_lgr, band, tile_y;
     int f64_kind, f64_nr;
+    int f32_il, f64_il;
 };
 
 // Right-hand-side addressing: slot k of a launch uses offset (slot * slot_stride + extra)

@@ -125,9 +125,9 @@ __device__ __forceinline__ void unpack_rows(float4 a, float4 b, float4 c, cpx<fl
     u[3] = {b.z, b.w};
     u[4] = {c.x, c.y};
     u[5] = {c.z, c.w};
-    const cpx<float> r0 = cmul(u[1], u[5]) - cmul(u[2], u[4]);
-    const cpx<float> r1 = cmul(u[2], u[3]) - cmul(u[0], u[5]);
-    const cpx<float> r2 = cmul(u[0], u[4]) - cmul(u[1], u[3]);
+    const cpx<float> r0 = cfma(u[1], u[5], -1.0f * cmul(u[2], u[4]));
+    const cpx<float> r1 = cfma(u[2], u[3], -1.0f * cmul(u[0], u[5]));
+    const cpx<float> r2 = cfma(u[0], u[4], -1.0f * cmul(u[1], u[3]));
     u[6] = {r0.re, -r0.im};
     u[7] = {r1.re, -r1.im};
     u[8] = {r2.re, -r2.im};
@@ -164,6 +164,23 @@ __device__ __forceinline__ int plane_order(int p, const Geom &g) {
     if (g.band == 1) return p;
     const int per = g.band * g.nt, b = p / per, i = p % per;
     return b * g.band + i % g.band + g.nz * (i / g.band);
+}
+
+// Neighbours of site s = (x, y) of the (z, t) plane pl = z + nz t without per-thread integer
+// divisions (the plane is uniform over a block, so the z and t offsets are too).  The tile
+// kernels read the +x and +y neighbours from LDS: fwd[0] and fwd[1] are left at s.
+__device__ __forceinline__ Nbr plane_neighbours(int s, int x, int y, int pl, int nx, int ny, int nz, int nt) {
+    const int zc = pl % nz, tc = pl / nz;
+    const int sxy = nx * ny, sxyz = sxy * nz;
+    Nbr nb;
+    nb.fwd[0] = nb.fwd[1] = s;
+    nb.bwd[0] = x == 0 ? s + (nx - 1) : s - 1;
+    nb.bwd[1] = y == 0 ? s + (ny - 1) * nx : s - nx;
+    nb.fwd[2] = s + (zc == nz - 1 ? -(nz - 1) * sxy : sxy);
+    nb.bwd[2] = s + (zc == 0 ? (nz - 1) * sxy : -sxy);
+    nb.fwd[3] = s + (tc == nt - 1 ? -(nt - 1) * sxyz : sxyz);
+    nb.bwd[3] = s + (tc == 0 ? (nt - 1) * sxyz : -sxyz);
+    return nb;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -470,7 +487,7 @@ __global__ __launch_bounds__(kBlock) void k_dslash_f32_tile(const float4 *__rest
     const int x = threadIdx.x % nx, yl = threadIdx.x / nx;
     const int plane0 = pl * nx * ny;
     const int s = plane0 + (y0 + yl) * nx + x;   // every site is valid: V is a multiple of the tile
-    const Nbr nb = neighbours(s, nx, ny, g.nz, g.nt);
+    const Nbr nb = plane_neighbours(s, x, y0 + yl, pl, nx, ny, g.nz, g.nt);
     // halo loads: threads 0 .. 2nx-1 also fetch row y0 - 1 (first nx) or y0 + ty (next nx)
     const bool halo = (int)threadIdx.x < 2 * nx;
     const int hrow = threadIdx.x < (unsigned)nx ? 0 : ty + 1;
@@ -722,9 +739,9 @@ __device__ __forceinline__ void load_link64_rows(const double2 *U, int V, int mu
         const double2 t = U[(size_t)(mu * 9 + k) * V + s];
         u[k] = {t.x, t.y};
     }
-    const cpx<double> r0 = cmul(u[1], u[5]) - cmul(u[2], u[4]);
-    const cpx<double> r1 = cmul(u[2], u[3]) - cmul(u[0], u[5]);
-    const cpx<double> r2 = cmul(u[0], u[4]) - cmul(u[1], u[3]);
+    const cpx<double> r0 = cfma(u[1], u[5], -1.0 * cmul(u[2], u[4]));
+    const cpx<double> r1 = cfma(u[2], u[3], -1.0 * cmul(u[0], u[5]));
+    const cpx<double> r2 = cfma(u[0], u[4], -1.0 * cmul(u[1], u[3]));
     u[6] = {r0.re, -r0.im};
     u[7] = {r1.re, -r1.im};
     u[8] = {r2.re, -r2.im};
@@ -769,7 +786,11 @@ __global__ __launch_bounds__(kBlock) void k_dslash_tile_rl(const typename Store<
     extern __shared__ __align__(16) unsigned char tile_raw[];
     vec *tile = reinterpret_cast<vec *>(tile_raw);   // [UN][tsites]
     const int L = xcd_swizzle(blockIdx.x, gridDim.x);
-    const int sb = L % nsb, rg = L / nsb;
+    // block order: groups of IL right-hand-side groups, tiles, then the IL groups of one tile
+    // fastest (IL = 1: the tiles of one right-hand-side group in a row)
+    const int IL = std::is_same<T, double>::value ? g.f64_il : g.f32_il;
+    const int grp = L / (nsb * IL), rem = L - grp * nsb * IL;
+    const int sb = rem / IL, rg = grp * IL + (rem - sb * IL);
     const int cnt = slot_count(sl);
     const int k0 = rg * NR;
     if (k0 >= cnt) return;  // uniform over the block
@@ -782,7 +803,7 @@ __global__ __launch_bounds__(kBlock) void k_dslash_tile_rl(const typename Store<
     const int x = threadIdx.x % nx, yl = threadIdx.x / nx;
     const int plane0 = pl * nx * ny;
     const int s = plane0 + (y0 + yl) * nx + x;   // every site is valid: V is a multiple of the tile
-    const Nbr nb = neighbours(s, nx, ny, g.nz, g.nt);
+    const Nbr nb = plane_neighbours(s, x, y0 + yl, pl, nx, ny, g.nz, g.nt);
     // LDS row of tile row yl: shifted by the lower halo row when there is one
     const int off = whole ? 0 : 1;
     const int me = (yl + off) * nx + x;
@@ -886,19 +907,23 @@ int dslash_partials(int prec, const Geom &g) {
     return g.f32_kind == 2 || g.f32_kind == 4 ? tile_blocks(g) : site_blocks(g);
 }
 
+static bool il_ok(int il) { return il == 1 || il == 2 || il == 4 || il == 8 || il == 16; }
+
 bool valid_tuning(int prec, const Geom &g) {
     if (prec == 0) {
         if (g.f64_kind == 1)
             return g.tile_y > 0 && g.tile_y == tile_rows(g.nx, g.ny) && g.band >= 1 && g.nz % g.band == 0 &&
-                   (g.f64_nr == 2 || g.f64_nr == 4 || g.f64_nr == 8);
-        return g.f64_kind == 0 && g.f64_lgr >= 0 && g.f64_lgr <= 2;
+                   (g.f64_nr == 1 || g.f64_nr == 2 || g.f64_nr == 4 || g.f64_nr == 8) && il_ok(g.f64_il);
+        return g.f64_kind == 0 && g.f64_lgr >= 0 && g.f64_lgr <= 2 && g.f64_il == 1;
     }
+    if (g.f32_kind != 4 && g.f32_il != 1) return false;   // the interleave applies to kind 4 only
     const bool nr_tile = g.f32_nr == 4 || g.f32_nr == 8 || g.f32_nr == 16;
     if (g.f32_kind == 1 || g.f32_kind == 3) return plane_tileable(g) && nr_tile && g.band >= 1 && g.nz % g.band == 0;
     const bool tiled = g.tile_y > 0 && g.tile_y == tile_rows(g.nx, g.ny);
     const bool band_ok = g.band >= 1 && g.nz % g.band == 0;
     if (g.f32_kind == 2) return tiled && nr_tile && band_ok;
-    if (g.f32_kind == 4) return tiled && band_ok && (g.f32_nr == 2 || g.f32_nr == 4 || g.f32_nr == 8);
+    if (g.f32_kind == 4)
+        return tiled && band_ok && (g.f32_nr == 1 || g.f32_nr == 2 || g.f32_nr == 4 || g.f32_nr == 8) && il_ok(g.f32_il);
     return g.f32_kind == 0 && (g.f32_nr == 2 || g.f32_nr == 4 || g.f32_nr == 8);
 }
 
@@ -910,7 +935,9 @@ static void launch_tile_rl(const void *U, const void *in, size_t in_stride, size
     using vec = typename Store<T>::vec;
     using link = typename Store<T>::link;
     const int nsb = tile_blocks(g);
-    const int ngr = (max_slots + NR - 1) / NR;
+    const int il = std::is_same<T, double>::value ? g.f64_il : g.f32_il;
+    // right-hand-side groups, rounded up to whole interleave groups (the extra blocks exit)
+    const int ngr = ((max_slots + NR - 1) / NR + il - 1) / il * il;
     const int rows = g.tile_y == g.ny ? g.tile_y : g.tile_y + 2;
     const size_t lds = (size_t)rows * g.nx * Store<T>::units * sizeof(vec);
     hipLaunchKernelGGL((k_dslash_tile_rl<T, NR, DAG, EPI>), dim3(nsb * ngr), dim3(g.nx * g.tile_y), lds, st,
@@ -931,7 +958,8 @@ static void launch_dslash_t(const void *U, const void *in, size_t in_stride, siz
 #define SMPQ_F64T(NR)                                                                                             \
     launch_tile_rl<double, NR, DAG, EPI>(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra, g, \
                                          kappa, sigma, sl, max_slots, partial, alpha, status, st)
-            if (g.f64_nr == 2) SMPQ_F64T(2);
+            if (g.f64_nr == 1) SMPQ_F64T(1);
+            else if (g.f64_nr == 2) SMPQ_F64T(2);
             else if (g.f64_nr == 8) SMPQ_F64T(8);
             else SMPQ_F64T(4);
 #undef SMPQ_F64T
@@ -988,7 +1016,8 @@ static void launch_f32_tuned(const void *U, const void *in, size_t in_stride, si
 #define SMPQ_F32RL(NR)                                                                                            \
     launch_tile_rl<float, NR, DAG, EPI>(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra, g, \
                                         kappa, sigma, sl, max_slots, partial, alpha, status, st)
-        if (g.f32_nr == 2) SMPQ_F32RL(2);
+        if (g.f32_nr == 1) SMPQ_F32RL(1);
+        else if (g.f32_nr == 2) SMPQ_F32RL(2);
         else if (g.f32_nr == 8) SMPQ_F32RL(8);
         else SMPQ_F32RL(4);
 #undef SMPQ_F32RL

@@ -204,3 +204,24 @@ def test_binding_layouts_match_the_header():
         assert getattr(smpq, name) == value, name
     assert _enum_values(src, "smpq_status")["SMPQ_ESTATE"] == -6
     assert int(re.search(r"#define SMPQ_MAX_POLES (\d+)", src).group(1)) == 32
+
+
+def test_tuning_validation_on_host_context():
+    """smpq_set_tuning accepts the variants that fit the lattice and refuses the others (the
+    previous choice kept), the right-hand-side interleave only for the tile kernels."""
+    c = smpq.smpq_create((16, 16, 16, 32), -1)
+    smpq.smpq_set_tuning(c, 4, 1, 1, 1, 1, 2, f32_interleave=4, f64_interleave=8)
+    want = smpq.smpq_get_tuning(c)
+    assert want == {"f32_kind": 4, "f32_nr": 1, "f64_lgr": 1, "plane_band": 1, "f64_kind": 1, "f64_nr": 2,
+                    "f32_interleave": 4, "f64_interleave": 8}
+    for bad in (dict(f32_kind=4, f32_interleave=3), dict(f32_kind=4, f32_interleave=32),
+                dict(f32_kind=1, f32_nr=8, f32_interleave=2), dict(f64_kind=0, f64_interleave=2),
+                dict(f32_kind=4, f32_nr=16), dict(f64_kind=1, f64_nr=3)):
+        args = dict(f32_kind=4, f32_nr=1, f64_lgr=1, plane_band=1, f64_kind=1, f64_nr=2)
+        args.update(bad)
+        with pytest.raises(smpq.SmpqError):
+            smpq.smpq_set_tuning(c, **args)
+        assert smpq.smpq_get_tuning(c) == want, bad
+    smpq.smpq_set_tuning(c, 1, 8, 1)   # plane kernel, both interleaves back to 1
+    assert smpq.smpq_get_tuning(c)["f32_interleave"] == 1
+    smpq.smpq_destroy(c)

@@ -37,9 +37,11 @@ def _zolo_interval(U, lat):
 SITE_VARIANTS = [(0, nr, lgr) for nr, lgr in ((2, 0), (4, 1), (8, 2))]
 PLANE_VARIANTS = [(k, nr, lgr) for k in (1, 3) for nr, lgr in ((4, 0), (8, 1), (16, 2))]
 TILE_VARIANTS = [(2, nr, lgr) for nr, lgr in ((4, 0), (8, 1), (16, 2))]
-F64_TILE_NR = (2, 4, 8)       # FP64 xy-tile kernel (f64_kind 1): right-hand sides per block
-# FP32 xy-tiles with the links read per right-hand side (kind 4): 2, 4, 8 right-hand sides per block
-RL_VARIANTS = [(4, nr, lgr) for nr, lgr in ((2, 0), (4, 1), (8, 2))]
+F64_TILE_NR = (1, 2, 4, 8)    # FP64 xy-tile kernel (f64_kind 1): right-hand sides per block
+# FP32 xy-tiles with the links read per right-hand side (kind 4): 1, 2, 4, 8 right-hand sides per block
+RL_VARIANTS = [(4, nr, lgr) for nr, lgr in ((1, 0), (2, 0), (4, 1), (8, 2))]
+# the tile kernels' block order: that many right-hand-side groups of one tile in a row
+INTERLEAVES = (2, 8)
 
 
 @pytest.mark.parametrize("dims", [(6, 4, 4, 6), (5, 3, 4, 7), (4, 4, 4, 4)])
@@ -88,14 +90,19 @@ def test_dslash_parity_plane_tiled(dims, nrhs):
                 assert np.abs(out32 - ref).max() <= 2e-6 * np.abs(ref).max(), (tune, band)
             out64 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_FP64)
             assert np.abs(out64 - ref).max() <= 1e-13 * np.abs(ref).max(), tune
+        for tune in RL_VARIANTS:
+            for il in INTERLEAVES:
+                smpq.smpq_set_tuning(c, *tune, 1, 0, 4, il)
+                out32 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_MIXED_FP32)
+                assert np.abs(out32 - ref).max() <= 2e-6 * np.abs(ref).max(), (tune, il)
         # the FP64 xy-tile kernel: here the tile is the whole 16x16 plane (no halo rows)
         for nr in F64_TILE_NR:
-            for band in (1, 2):
+            for band, il in ((1, 1), (2, 1), (1, 2), (1, 8)):
                 if dims[2] % band:
                     continue
-                smpq.smpq_set_tuning(c, 1, 8, 1, band, 1, nr)
+                smpq.smpq_set_tuning(c, 1, 8, 1, band, 1, nr, 1, il)
                 out64 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_FP64)
-                assert np.abs(out64 - ref).max() <= 1e-13 * np.abs(ref).max(), (nr, band)
+                assert np.abs(out64 - ref).max() <= 1e-13 * np.abs(ref).max(), (nr, band, il)
 
 
 def test_autotune_picks_a_valid_variant_and_keeps_parity():
@@ -111,6 +118,8 @@ def test_autotune_picks_a_valid_variant_and_keeps_parity():
                                             + RL_VARIANTS]
     assert t["f64_lgr"] in (0, 1, 2) and t["plane_band"] in (1, 2)
     assert (t["f64_kind"], t["f64_nr"]) in [(0, t["f64_nr"])] + [(1, n) for n in F64_TILE_NR]
+    assert t["f32_interleave"] in ((1, 2, 4, 8) if t["f32_kind"] == 4 else (1,))
+    assert t["f64_interleave"] in ((1, 2, 4, 8) if t["f64_kind"] == 1 else (1,))
     ref = np.stack([apply_dw(U, lat, KAPPA, p) for p in psi])
     out32 = smpq.smpq_apply_dw(c, psi, precision=smpq.SMPQ_MIXED_FP32)
     assert np.abs(out32 - ref).max() <= 2e-6 * np.abs(ref).max()
@@ -151,20 +160,28 @@ def test_dslash_parity_xy_tiles(dims, nrhs):
                 smpq.smpq_set_tuning(c, *tune, band)
                 out32 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_MIXED_FP32)
                 assert np.abs(out32 - ref).max() <= 2e-6 * np.abs(ref).max(), (tune, band)
+        for tune in RL_VARIANTS:
+            for il in INTERLEAVES:
+                smpq.smpq_set_tuning(c, *tune, 1, 0, 4, il)
+                out32 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_MIXED_FP32)
+                assert np.abs(out32 - ref).max() <= 2e-6 * np.abs(ref).max(), (tune, il)
         # the FP64 xy-tile kernel with its halo rows
         for nr in F64_TILE_NR:
-            smpq.smpq_set_tuning(c, 2, 8, 1, 1, 1, nr)
-            out64 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_FP64)
-            assert np.abs(out64 - ref).max() <= 1e-13 * np.abs(ref).max(), nr
+            for il in (1,) + INTERLEAVES:
+                smpq.smpq_set_tuning(c, 2, 8, 1, 1, 1, nr, 1, il)
+                out64 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_FP64)
+                assert np.abs(out64 - ref).max() <= 1e-13 * np.abs(ref).max(), (nr, il)
     with pytest.raises(smpq.SmpqError):           # FP64 tile: 2, 4 or 8 right-hand sides per block
         smpq.smpq_set_tuning(c, 2, 8, 1, 1, 1, 16)
     with pytest.raises(smpq.SmpqError):           # the band must divide nz
         smpq.smpq_set_tuning(c, 2, 8, 1, 3)
 
 
-@pytest.mark.parametrize("dims,kind,band", [((16, 16, 2, 2), 1, 1), ((16, 16, 2, 2), 2, 2), ((24, 16, 2, 2), 2, 2),
-                                             ((16, 16, 2, 2), 3, 2), ((16, 16, 2, 2), 4, 1), ((24, 16, 2, 2), 4, 2)])
-def test_qx_plane_tiled_mixed(dims, kind, band):
+@pytest.mark.parametrize("dims,kind,band,il", [((16, 16, 2, 2), 1, 1, 1), ((16, 16, 2, 2), 2, 2, 1),
+                                                ((24, 16, 2, 2), 2, 2, 1), ((16, 16, 2, 2), 3, 2, 1),
+                                                ((16, 16, 2, 2), 4, 1, 1), ((24, 16, 2, 2), 4, 2, 1),
+                                                ((16, 16, 2, 2), 4, 1, 4), ((24, 16, 2, 2), 4, 2, 2)])
+def test_qx_plane_tiled_mixed(dims, kind, band, il):
     lat = Lattice(dims)
     U = si.near_identity_su3(dims, 0.3, 13)
     lo, hi = _zolo_interval(U, lat)
@@ -172,14 +189,14 @@ def test_qx_plane_tiled_mixed(dims, kind, band):
     col, ncls = colouring(lat, (2, 2, 2, 2), 0)
     ref = qx_probing(U, lat, KAPPA, zo, col, [5], TOL, 5000)
     c = _ctx(dims, U)
-    smpq.smpq_set_tuning(c, kind, 8, 1, band)
+    smpq.smpq_set_tuning(c, kind, 8, 1, band, 0, 4, il if kind == 4 else 1)
     smpq.smpq_set_scheme(c, (2, 2, 2, 2), 0)
     smpq.smpq_set_zolotarev(c, 14, lo, hi)
     smpq.smpq_set_solver(c, smpq.SMPQ_MIXED_FP32, TOL, 5000, 50)
     q32 = smpq.smpq_compute_qx_classes(c, [5])[0]
     assert np.abs(q32 - ref.real).max() < 1e-5
     # the FP64 path with the FP64 xy-tile stencil (in the solver: both fused epilogues)
-    smpq.smpq_set_tuning(c, kind, 8, 1, band, 1, 4)
+    smpq.smpq_set_tuning(c, kind, 8, 1, band, 1, 4, il if kind == 4 else 1, il)
     smpq.smpq_set_solver(c, smpq.SMPQ_FP64, TOL, 5000, 0)
     q64 = smpq.smpq_compute_qx_classes(c, [5])[0]
     assert np.abs(q64 - ref.real).max() < 1e-10 * np.abs(ref.real).max()
