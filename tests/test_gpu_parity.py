@@ -5,6 +5,8 @@ Tolerances: FP64 stencil 1e-13 and FP32 stencil 2e-6, relative to the largest ou
 entry; FP64 q(x) within 1e-10 relative to the largest |q| of the oracle; mixed precision
 within 1e-5.
 """
+import functools
+
 import numpy as np
 import pytest
 
@@ -177,17 +179,24 @@ def test_dslash_parity_xy_tiles(dims, nrhs):
         smpq.smpq_set_tuning(c, 2, 8, 1, 3)
 
 
+@functools.lru_cache(maxsize=None)
+def _tiled_qx_reference(dims):
+    """The oracle's q(x) of class 5 (r = 2) on a near-identity field: one solve per lattice,
+    shared by every stencil variant below."""
+    lat = Lattice(dims)
+    U = si.near_identity_su3(dims, 0.3, 13)
+    lo, hi = _zolo_interval(U, lat)
+    col, _ = colouring(lat, (2, 2, 2, 2), 0)
+    return U, lo, hi, qx_probing(U, lat, KAPPA, zolotarev(14, lo, hi), col, [5], TOL, 5000)
+
+
 @pytest.mark.parametrize("dims,kind,band,il", [((16, 16, 2, 2), 1, 1, 1), ((16, 16, 2, 2), 2, 2, 1),
                                                 ((24, 16, 2, 2), 2, 2, 1), ((16, 16, 2, 2), 3, 2, 1),
                                                 ((16, 16, 2, 2), 4, 1, 1), ((24, 16, 2, 2), 4, 2, 1),
                                                 ((16, 16, 2, 2), 4, 1, 4), ((24, 16, 2, 2), 4, 2, 2)])
 def test_qx_plane_tiled_mixed(dims, kind, band, il):
-    lat = Lattice(dims)
-    U = si.near_identity_su3(dims, 0.3, 13)
-    lo, hi = _zolo_interval(U, lat)
-    zo = zolotarev(14, lo, hi)
-    col, ncls = colouring(lat, (2, 2, 2, 2), 0)
-    ref = qx_probing(U, lat, KAPPA, zo, col, [5], TOL, 5000)
+    print(f"q(x) of class 5 on {dims}, kind {kind}, band {band}, interleave {il}", flush=True)
+    U, lo, hi, ref = _tiled_qx_reference(dims)
     c = _ctx(dims, U)
     smpq.smpq_set_tuning(c, kind, 8, 1, band, 0, 4, il if kind == 4 else 1)
     smpq.smpq_set_scheme(c, (2, 2, 2, 2), 0)
