@@ -471,7 +471,11 @@ def main():
                                         "f64_rhs_per_block": (tuning["f64_nr"] if tuning.get("f64_kind", 0) == 1
                                                               else 1 << tuning["f64_lgr"]),
                                         "f32_interleave": tuning.get("f32_interleave", 1),
-                                        "f64_interleave": tuning.get("f64_interleave", 1)}},
+                                        "f64_interleave": tuning.get("f64_interleave", 1),
+                                        "f32_dag_kind": F32_KINDS[tuning.get("f32_dag_kind", tuning["f32_kind"])],
+                                        "f32_dag_rhs_per_thread": tuning.get("f32_dag_nr", tuning["f32_nr"]),
+                                        "f32_dag_interleave": tuning.get("f32_dag_interleave",
+                                                                         tuning.get("f32_interleave", 1))}},
         "steps_requested": args.steps, "warmup_requested": args.warmup, "budget_s": args.budget_s,
         "speedup_vs_fp64": round(fp64["s_per_map"] / (ms_per_step / 1000.0), 3),
         "roofline": roofline, "dslash": dslash, "fp64": fp64, "accuracy": accuracy,

@@ -414,22 +414,29 @@ smpq_status smpq_bench_stream(smpq_ctx *ctx, size_t bytes, int launches, int non
  * row take successive groups of right-hand sides of the same tile before the blocks move on
  * to the next tile, so that the links a tile reads for each right-hand side come from L2;
  * 1 for every other kind.
+ * f32_kind, f32_nr and f32_interleave apply to the D_W launches (the first stencil of each CG
+ * iteration, D_W p with the partial sums of <p, (H^2 + s) p>); f32_dag_kind, f32_dag_nr and
+ * f32_dag_interleave, with the same meanings and limits, to the D_W^dag launches (the second,
+ * which also updates the residual), so that each can use the variant that suits its epilogue.
  * Results do not depend on the variant beyond the rounding order of sums. */
 typedef struct {
     int f32_kind, f32_nr, f64_lgr, plane_band;
     int f64_kind, f64_nr;
     int f32_interleave, f64_interleave;
+    int f32_dag_kind, f32_dag_nr, f32_dag_interleave;
 } smpq_tuning;
 
 /* Choose the variants for this lattice by timing each on n_rhs right-hand sides as the solver
- * uses it: D_W followed by D_W^dag with the +sigma term and its partial sums (two rotating
- * buffer sets, 10 pairs, best of two runs; fewer right-hand sides where they would take more
- * than half of the free device memory).  n_rhs = 0 times the batch size that a whole q(x)
+ * uses it: FP32 D_W with its partial sums and D_W^dag with the +sigma term and the residual
+ * update, each alone and chosen separately (the plane band shared: the band with the smallest
+ * sum of the two); FP64 the pair (two rotating buffer sets, 10 launches, best of two runs; fewer
+ * right-hand sides where they would take more than half of the free device memory).  n_rhs = 0 times the batch size that a whole q(x)
  * map of the current scheme, coefficients and precision would use (ESTATE without them):
  * the variants' order can change with the number of right-hand sides through L2 reuse.  The choice is kept by the context and written to
  * *chosen (may be NULL); on an error the previous choice is kept.  Without this call a
  * context uses kind 1 / 8 where the plane fits, else kind 2 / 8 where a tile fits, else kind
- * 0 / 4, with plane_band 1, f64_kind 0, f64_lgr 1 and both interleaves 1. */
+ * 0 / 4 (the same for D_W and D_W^dag), with plane_band 1, f64_kind 0, f64_lgr 1 and the
+ * interleaves 1. */
 smpq_status smpq_autotune(smpq_ctx *ctx, int n_rhs, smpq_tuning *chosen);
 
 /* Select the variants explicitly.  SMPQ_EINVAL (previous choice kept) if a variant is not

@@ -40,7 +40,8 @@ _vp = ctypes.c_void_p
 
 class SmpqTuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int) for n in ("f32_kind", "f32_nr", "f64_lgr", "plane_band", "f64_kind", "f64_nr",
-                                            "f32_interleave", "f64_interleave")]
+                                            "f32_interleave", "f64_interleave", "f32_dag_kind", "f32_dag_nr",
+                                            "f32_dag_interleave")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -424,9 +425,13 @@ def smpq_autotune(ctx, n_rhs=48):
 
 
 def smpq_set_tuning(ctx, f32_kind, f32_nr, f64_lgr, plane_band=1, f64_kind=0, f64_nr=4, f32_interleave=1,
-                    f64_interleave=1):
+                    f64_interleave=1, f32_dag_kind=None, f32_dag_nr=None, f32_dag_interleave=None):
+    """The D_W^dag variant defaults to the D_W one (f32_kind, f32_nr, f32_interleave)."""
+    dk = f32_kind if f32_dag_kind is None else f32_dag_kind
+    dn = f32_nr if f32_dag_nr is None else f32_dag_nr
+    di = f32_interleave if f32_dag_interleave is None else f32_dag_interleave
     t = SmpqTuning(int(f32_kind), int(f32_nr), int(f64_lgr), int(plane_band), int(f64_kind), int(f64_nr),
-                   int(f32_interleave), int(f64_interleave))
+                   int(f32_interleave), int(f64_interleave), int(dk), int(dn), int(di))
     _check(ctx, _lib.smpq_set_tuning(ctx.ptr, ctypes.byref(t)))
 
 

@@ -215,9 +215,28 @@ struct smpq_ctx {
     int *h_count = nullptr;     // pinned
     // stencil variant (see Geom); defaults: plane tile where the xy-plane has 256 sites
     int f32_kind = 0, f32_nr = 4, f64_lgr = 1, band = 1, f64_kind = 0, f64_nr = 4, f32_il = 1, f64_il = 1;
+    int f32_dag_kind = 0, f32_dag_nr = 4, f32_dag_il = 1;   // the D_W^dag launches
     Geom geom() const {
         return Geom{dims[0], dims[1], dims[2], dims[3], V, vs, f32_kind, f32_nr, f64_lgr, band,
-                    tile_rows(dims[0], dims[1]), f64_kind, f64_nr, f32_il, f64_il};
+                    tile_rows(dims[0], dims[1]), f64_kind, f64_nr, f32_il, f64_il, f32_dag_kind, f32_dag_nr,
+                    f32_dag_il};
+    }
+    smpq_tuning tuning() const {
+        return smpq_tuning{f32_kind, f32_nr, f64_lgr, band, f64_kind, f64_nr, f32_il, f64_il,
+                           f32_dag_kind, f32_dag_nr, f32_dag_il};
+    }
+    void set_tuning(const smpq_tuning &t) {
+        f32_kind = t.f32_kind;
+        f32_nr = t.f32_nr;
+        f64_lgr = t.f64_lgr;
+        band = t.plane_band;
+        f64_kind = t.f64_kind;
+        f64_nr = t.f64_nr;
+        f32_il = t.f32_interleave;
+        f64_il = t.f64_interleave;
+        f32_dag_kind = t.f32_dag_kind;
+        f32_dag_nr = t.f32_dag_nr;
+        f32_dag_il = t.f32_dag_interleave;
     }
 };
 
@@ -482,7 +501,8 @@ void enqueue_iteration(smpq_ctx *c, int prec, const MSState &S, bool y64, bool x
     // the base direction: one of NS per slot, or (16-bit shifted directions) the only one
     const size_t pst = dir == kDirF32 ? NS * rs : rs, pofs = dir == kDirF32 ? S.i0 * rs : 0;
     const void *U = vp == 0 ? c->U64.p : c->U32.p;
-    const int np_ds = dslash_partials(vp, g);
+    // partials per slot of the first (D_W p) and the second (D_W^dag) stencil
+    const int np_ds = dslash_partials(vp, g, false), np_dag = dslash_partials(vp, g, true);
     const bool mixed = prec >= 1;
     const Slots act{S.list, S.count, 0};
     const double s0 = c->coef->s0;
@@ -496,7 +516,7 @@ void enqueue_iteration(smpq_ctx *c, int prec, const MSState &S, bool y64, bool x
     launch_dslash(vp, true, 2, U, w.tmp.p, rs, 0, w.r.p, rs, w.p.p, pst, pofs, g, c->kappa, s0, act, B, S.partial, s,
                   S.alpha, S.status);
     if (tm) tm->dslash.record(s, captured);
-    launch_scalars_beta(S, np_ds, s);
+    launch_scalars_beta(S, np_dag, s);
     if (tm) tm->update.record(s, captured);
     launch_shift_update(vp, g, S, w.r.p, w.p.p, y64 ? w.y.p : w.yacc.p, y64,
                         mixed ? (x64 ? w.x0.p : w.x0acc.p) : nullptr, x64, dir, w.ph.p, c->cur_xs, s);
@@ -855,7 +875,7 @@ void lanczos(smpq_ctx *c, int steps, uint64_t seed, double *tmin, double *tmax) 
     const size_t v64 = 12 * 16 * c->vs;
     c->lz.ensure(4 * v64);
     double2 *v = c->lz.as<double2>(), *vp = v + 12 * c->vs, *w = vp + 12 * c->vs, *t = w + 12 * c->vs;
-    const int np_ds = dslash_partials(0, g), np_unit = unit_parts(0, g);
+    const int np_ds = dslash_partials(0, g, true), np_unit = unit_parts(0, g);
     DevMem part;
     part.ensure(sizeof(double) * partial_stride(g));
     std::vector<double> h((size_t)24 * c->V), stage;
@@ -1228,8 +1248,12 @@ struct StencilBench {
 // D_W^dag + sigma with the in-place residual update (epilogue 2, alpha = 0 so r keeps its
 // values but is read and written), and *bytes covers both launches.  n_rhs is lowered where the
 // buffers would take more than half of the free device memory.
+// mode 0: D_W alone (no epilogue); 1: the solver's pair, D_W p with the partials of
+// <p, (H^2 + s) p> (epilogue 3) then D_W^dag with r -= alpha (H^2 + s) p (epilogue 2); 2 and 3:
+// the first or the second of the pair alone.  Returns ms per launch (per pair in mode 1).
 double time_dslash(smpq_ctx *c, StencilBench &tb, int p, int n_rhs, int n_sets, int launches, double *bytes,
-                   bool pair = false) {
+                   int mode = 0) {
+    const bool pair = mode != 0;   // buffers of the pair
     const Geom g = c->geom();
     const size_t units = p == 0 ? 12 : 6;
     const size_t vbytes = units * 16 * c->vs;
@@ -1282,10 +1306,13 @@ double time_dslash(smpq_ctx *c, StencilBench &tb, int p, int n_rhs, int n_sets, 
                           nullptr, c->stream);
             return;
         }
-        launch_dslash(p, false, 3, tb.links[k].p, a, st, 0, b, st, nullptr, 0, 0, g, c->kappa, 0.1, sl, n_rhs,
-                      tb.part.as<double>(), c->stream);
-        launch_dslash(p, true, 2, tb.links[k].p, b, st, 0, tb.vecs[(size_t)k * nvec + 2].p, st, a, st, 0, g, c->kappa,
-                      0.1, sl, n_rhs, tb.part.as<double>(), c->stream, tb.alpha.as<double>(), tb.status.as<int>());
+        if (mode != 3)
+            launch_dslash(p, false, 3, tb.links[k].p, a, st, 0, b, st, nullptr, 0, 0, g, c->kappa, 0.1, sl, n_rhs,
+                          tb.part.as<double>(), c->stream);
+        if (mode != 2)
+            launch_dslash(p, true, 2, tb.links[k].p, b, st, 0, tb.vecs[(size_t)k * nvec + 2].p, st, a, st, 0, g,
+                          c->kappa, 0.1, sl, n_rhs, tb.part.as<double>(), c->stream, tb.alpha.as<double>(),
+                          tb.status.as<int>());
     };
     for (int i = 0; i < n_sets; ++i) one(i);   // warm-up
     hipEvent_t e0, e1;
@@ -1302,7 +1329,9 @@ double time_dslash(smpq_ctx *c, StencilBench &tb, int p, int n_rhs, int n_sets, 
     HIPCHK(hipGetLastError());
     const double u = p == 0 ? 16.0 : 8.0;
     *bytes = (double)c->V * ((double)lbytes / c->V + (double)n_rhs * 24.0 * u);
-    if (pair) *bytes = 2.0 * *bytes + (double)c->V * n_rhs * 24.0 * u;   // + aux and the r read
+    // the pair: + the aux read (p) and the r read; the second stencil alone: D_W plus those
+    if (mode == 1) *bytes = 2.0 * *bytes + (double)c->V * n_rhs * 24.0 * u;
+    if (mode == 3) *bytes = *bytes + (double)c->V * n_rhs * 24.0 * u;
     return t / launches;
 }
 
@@ -1342,11 +1371,11 @@ smpq_status smpq_create(const int dims[4], int device, smpq_ctx **out) {
     c->vs = (size_t)((V + 255) / 256) * 256;
     c->device = device;
     if (dims[0] * dims[1] == 256) {
-        c->f32_kind = 1;
-        c->f32_nr = 8;
+        c->f32_kind = c->f32_dag_kind = 1;
+        c->f32_nr = c->f32_dag_nr = 8;
     } else if (tile_rows(dims[0], dims[1]) > 0) {
-        c->f32_kind = 2;
-        c->f32_nr = 8;
+        c->f32_kind = c->f32_dag_kind = 2;
+        c->f32_nr = c->f32_dag_nr = 8;
     }
     if (device >= 0) {
         int n = 0;
@@ -2184,25 +2213,13 @@ smpq_status smpq_bench_stream(smpq_ctx *c, size_t bytes, int launches, int nonte
 smpq_status smpq_set_tuning(smpq_ctx *c, const smpq_tuning *t) {
     return guarded(c, [&] {
         if (!t) throw Fail{SMPQ_EINVAL, "null tuning"};
-        Geom g = c->geom();
-        g.f32_kind = t->f32_kind;
-        g.f32_nr = t->f32_nr;
-        g.f64_lgr = t->f64_lgr;
-        g.band = t->plane_band;
-        g.f64_kind = t->f64_kind;
-        g.f64_nr = t->f64_nr;
-        g.f32_il = t->f32_interleave;
-        g.f64_il = t->f64_interleave;
-        if (!valid_tuning(0, g) || !valid_tuning(1, g))
+        const smpq_tuning keep = c->tuning();
+        c->set_tuning(*t);
+        const Geom g = c->geom();
+        if (!valid_tuning(0, g) || !valid_tuning(1, g)) {
+            c->set_tuning(keep);
             throw Fail{SMPQ_EINVAL, "unsupported stencil variant for this lattice"};
-        c->f32_kind = t->f32_kind;
-        c->f32_nr = t->f32_nr;
-        c->f64_lgr = t->f64_lgr;
-        c->band = t->plane_band;
-        c->f64_kind = t->f64_kind;
-        c->f64_nr = t->f64_nr;
-        c->f32_il = t->f32_interleave;
-        c->f64_il = t->f64_interleave;
+        }
         c->gen++;
     });
 }
@@ -2210,7 +2227,7 @@ smpq_status smpq_set_tuning(smpq_ctx *c, const smpq_tuning *t) {
 smpq_status smpq_get_tuning(smpq_ctx *c, smpq_tuning *t) {
     return guarded(c, [&] {
         if (!t) throw Fail{SMPQ_EINVAL, "null tuning"};
-        *t = smpq_tuning{c->f32_kind, c->f32_nr, c->f64_lgr, c->band, c->f64_kind, c->f64_nr, c->f32_il, c->f64_il};
+        *t = c->tuning();
     });
 }
 
@@ -2238,34 +2255,56 @@ smpq_status smpq_autotune(smpq_ctx *c, int n_rhs, smpq_tuning *chosen) {
                     for (int il : kind == 4 ? std::vector<int>{1, 2, 4} : std::vector<int>{1})
                         if (c->dims[2] % band == 0 && (il == 1 || nr * il <= 4)) cand.push_back({kind, nr, band, il});
         }
-        const smpq_tuning keep{c->f32_kind, c->f32_nr, c->f64_lgr, c->band, c->f64_kind, c->f64_nr, c->f32_il, c->f64_il};
-        double best = INFINITY;
-        Cand pick{keep.f32_kind, keep.f32_nr, keep.plane_band, keep.f32_interleave};
+        const smpq_tuning keep = c->tuning();
         StencilBench tb;   // one set of timing buffers per precision for the whole sweep
         try {
+            // FP32: the two stencils of an iteration (D_W p with its partials, D_W^dag with the
+            // residual update) are timed alone and chosen separately; the plane band is shared,
+            // so the band with the smallest sum of the two best times wins
+            struct Best {
+                double t3 = INFINITY, t2 = INFINITY;
+                Cand k3{}, k2{};
+            };
+            Best per_band[5];
+            double by3 = 0.0, by2 = 0.0;
             for (const Cand &k : cand) {
-                c->f32_kind = k.kind;
-                c->f32_nr = k.nr;
+                c->f32_kind = c->f32_dag_kind = k.kind;
+                c->f32_nr = c->f32_dag_nr = k.nr;
                 c->band = k.band;
-                c->f32_il = k.il;
-                const double t = std::min(time_dslash(c, tb, 1, n_rhs, 2, 10, &by, true),
-                                          time_dslash(c, tb, 1, n_rhs, 2, 10, &by, true));
+                c->f32_il = c->f32_dag_il = k.il;
+                const double t3 = std::min(time_dslash(c, tb, 1, n_rhs, 2, 10, &by3, 2),
+                                           time_dslash(c, tb, 1, n_rhs, 2, 10, &by3, 2));
+                const double t2 = std::min(time_dslash(c, tb, 1, n_rhs, 2, 10, &by2, 3),
+                                           time_dslash(c, tb, 1, n_rhs, 2, 10, &by2, 3));
                 if (c->trace)
                     std::fprintf(stderr, "smpq: autotune FP32 kind %d, %d per block/thread, band %d, interleave %d: "
-                                 "%.3f ms per pair (%.0f GB/s) on %d right-hand sides\n", k.kind, k.nr, k.band, k.il, t,
-                                 by / t * 1e-6, std::min(n_rhs, tb.n_rhs));
-                if (t < best) {
-                    best = t;
-                    pick = k;
+                                 "D_W %.3f ms (%.0f GB/s), D_W^dag %.3f ms (%.0f GB/s) on %d right-hand sides\n",
+                                 k.kind, k.nr, k.band, k.il, t3, by3 / t3 * 1e-6, t2, by2 / t2 * 1e-6,
+                                 std::min(n_rhs, tb.n_rhs));
+                Best &b = per_band[k.band];
+                if (t3 < b.t3) {
+                    b.t3 = t3;
+                    b.k3 = k;
+                }
+                if (t2 < b.t2) {
+                    b.t2 = t2;
+                    b.k2 = k;
                 }
             }
-            c->f32_kind = pick.kind;
-            c->f32_nr = pick.nr;
-            c->band = pick.band;
-            c->f32_il = pick.il;
+            int band = 1;
+            for (int bb : {2, 4})
+                if (per_band[bb].t3 + per_band[bb].t2 < per_band[band].t3 + per_band[band].t2) band = bb;
+            const Best &b = per_band[band];
+            c->band = band;
+            c->f32_kind = b.k3.kind;
+            c->f32_nr = b.k3.nr;
+            c->f32_il = b.k3.il;
+            c->f32_dag_kind = b.k2.kind;
+            c->f32_dag_nr = b.k2.nr;
+            c->f32_dag_il = b.k2.il;
             // FP64: lanes interleaving 1, 2 or 4 right-hand sides; xy-tiles with 2, 4 or 8 per
             // block (same plane order band as the FP32 choice) where a tile fits
-            best = INFINITY;
+            double best = INFINITY;
             struct Cand64 {
                 int kind, lgr, nr, il;
             };
@@ -2280,8 +2319,8 @@ smpq_status smpq_autotune(smpq_ctx *c, int n_rhs, smpq_tuning *chosen) {
                 c->f64_lgr = k.lgr;
                 c->f64_nr = k.nr;
                 c->f64_il = k.il;
-                const double t = std::min(time_dslash(c, tb, 0, n_rhs, 2, 10, &by, true),
-                                          time_dslash(c, tb, 0, n_rhs, 2, 10, &by, true));
+                const double t = std::min(time_dslash(c, tb, 0, n_rhs, 2, 10, &by, 1),
+                                          time_dslash(c, tb, 0, n_rhs, 2, 10, &by, 1));
                 if (c->trace)
                     std::fprintf(stderr, "smpq: autotune FP64 kind %d, lanes 2^%d / %d per block, interleave %d: "
                                  "%.3f ms per pair (%.0f GB/s) on %d right-hand sides\n", k.kind, k.lgr, k.nr, k.il, t,
@@ -2296,18 +2335,11 @@ smpq_status smpq_autotune(smpq_ctx *c, int n_rhs, smpq_tuning *chosen) {
             c->f64_nr = p64.nr;
             c->f64_il = p64.il;
         } catch (...) {
-            c->f32_kind = keep.f32_kind;
-            c->f32_nr = keep.f32_nr;
-            c->f64_lgr = keep.f64_lgr;
-            c->band = keep.plane_band;
-            c->f64_kind = keep.f64_kind;
-            c->f64_nr = keep.f64_nr;
-            c->f32_il = keep.f32_interleave;
-            c->f64_il = keep.f64_interleave;
+            c->set_tuning(keep);
             throw;
         }
         c->gen++;   // captured graphs used the previous variants
-        if (chosen) *chosen = smpq_tuning{c->f32_kind, c->f32_nr, c->f64_lgr, c->band, c->f64_kind, c->f64_nr, c->f32_il, c->f64_il};
+        if (chosen) *chosen = c->tuning();
     });
 }
 

@@ -29,6 +29,9 @@ struct Geom {
     int f32_kind, f32_nr, f64_lgr, band, tile_y;
     int f64_kind, f64_nr;
     int f32_il, f64_il;
+    // the FP32 variant of the D_W^dag launches (f32_kind, f32_nr and f32_il above apply to D_W):
+    // the two stencils of a CG iteration have different epilogues and favour different variants
+    int f32_dag_kind, f32_dag_nr, f32_dag_il;
 };
 
 // Right-hand-side addressing: slot k of a launch uses offset (slot * slot_stride + extra)
@@ -90,7 +93,7 @@ void launch_dslash(int prec, bool dag, int epi, const void *U, const void *in, s
                    size_t aux_extra, const Geom &g, double kappa, double sigma, Slots sl, int max_slots,
                    double *partial, hipStream_t st, const double *alpha = nullptr, const int *status = nullptr);
 __host__ __device__ int site_blocks(const Geom &g);   // blocks of 256 sites
-int dslash_partials(int prec, const Geom &g);         // partials per slot of the stencil epilogue
+int dslash_partials(int prec, const Geom &g, bool dag);   // partials per slot of the stencil epilogue
 bool plane_tileable(const Geom &g);
 // Rows per xy-tile: the largest divisor ty >= 2 of ny with nx * ty <= 256 and a multiple of 64
 // (nx <= 64); 0 when there is none.

@@ -902,20 +902,36 @@ int tile_rows(int nx, int ny) {
 
 static int tile_blocks(const Geom &g) { return g.V / (g.nx * g.tile_y); }
 
-int dslash_partials(int prec, const Geom &g) {
+// g with the FP32 variant of one direction in f32_kind, f32_nr and f32_il
+static Geom for_direction(const Geom &g, int prec, bool dag) {
+    Geom d = g;
+    if (prec != 0 && dag) {
+        d.f32_kind = g.f32_dag_kind;
+        d.f32_nr = g.f32_dag_nr;
+        d.f32_il = g.f32_dag_il;
+    }
+    return d;
+}
+
+int dslash_partials(int prec, const Geom &g, bool dag) {
     if (prec == 0) return g.f64_kind == 1 ? tile_blocks(g) : fp64_parts(g);
-    return g.f32_kind == 2 || g.f32_kind == 4 ? tile_blocks(g) : site_blocks(g);
+    const Geom d = for_direction(g, prec, dag);
+    return d.f32_kind == 2 || d.f32_kind == 4 ? tile_blocks(d) : site_blocks(d);
 }
 
 static bool il_ok(int il) { return il == 1 || il == 2 || il == 4 || il == 8 || il == 16; }
 
+static bool valid_f32(const Geom &g);
+
 bool valid_tuning(int prec, const Geom &g) {
-    if (prec == 0) {
-        if (g.f64_kind == 1)
-            return g.tile_y > 0 && g.tile_y == tile_rows(g.nx, g.ny) && g.band >= 1 && g.nz % g.band == 0 &&
-                   (g.f64_nr == 1 || g.f64_nr == 2 || g.f64_nr == 4 || g.f64_nr == 8) && il_ok(g.f64_il);
-        return g.f64_kind == 0 && g.f64_lgr >= 0 && g.f64_lgr <= 2 && g.f64_il == 1;
-    }
+    if (prec != 0) return valid_f32(g) && valid_f32(for_direction(g, prec, true));
+    if (g.f64_kind == 1)
+        return g.tile_y > 0 && g.tile_y == tile_rows(g.nx, g.ny) && g.band >= 1 && g.nz % g.band == 0 &&
+               (g.f64_nr == 1 || g.f64_nr == 2 || g.f64_nr == 4 || g.f64_nr == 8) && il_ok(g.f64_il);
+    return g.f64_kind == 0 && g.f64_lgr >= 0 && g.f64_lgr <= 2 && g.f64_il == 1;
+}
+
+static bool valid_f32(const Geom &g) {
     if (g.f32_kind != 4 && g.f32_il != 1) return false;   // the interleave applies to kind 4 only
     const bool nr_tile = g.f32_nr == 4 || g.f32_nr == 8 || g.f32_nr == 16;
     if (g.f32_kind == 1 || g.f32_kind == 3) return plane_tileable(g) && nr_tile && g.band >= 1 && g.nz % g.band == 0;
@@ -1061,8 +1077,8 @@ void launch_dslash(int prec, bool dag, int epi, const void *U, const void *in, s
          {launch_f32_tuned<true, 0>, launch_f32_tuned<true, 1>, launch_f32_tuned<true, 2>, nullptr}}};
     const Fn f = table[prec == 0 ? 0 : 1][dag ? 1 : 0][epi];
     if (!f) throw std::invalid_argument("stencil epilogue not built for this precision and direction");
-    f(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra, g, kappa, sigma, sl, max_slots, partial,
-      alpha, status, st);
+    f(U, in, in_stride, in_extra, out, out_stride, aux, aux_stride, aux_extra, for_direction(g, prec, dag), kappa,
+      sigma, sl, max_slots, partial, alpha, status, st);
 }
 
 // ------------------------------------------------------------------ element-wise kernels

@@ -211,17 +211,25 @@ def test_tuning_validation_on_host_context():
     previous choice kept), the right-hand-side interleave only for the tile kernels."""
     c = smpq.smpq_create((16, 16, 16, 32), -1)
     smpq.smpq_set_tuning(c, 4, 1, 1, 1, 1, 2, f32_interleave=4, f64_interleave=8)
+    assert smpq.smpq_get_tuning(c) == {"f32_kind": 4, "f32_nr": 1, "f64_lgr": 1, "plane_band": 1, "f64_kind": 1,
+                                       "f64_nr": 2, "f32_interleave": 4, "f64_interleave": 8, "f32_dag_kind": 4,
+                                       "f32_dag_nr": 1, "f32_dag_interleave": 4}
+    # D_W and D_W^dag with different variants
+    smpq.smpq_set_tuning(c, 1, 8, 1, 1, 1, 2, 1, 8, f32_dag_kind=4, f32_dag_nr=1, f32_dag_interleave=2)
     want = smpq.smpq_get_tuning(c)
-    assert want == {"f32_kind": 4, "f32_nr": 1, "f64_lgr": 1, "plane_band": 1, "f64_kind": 1, "f64_nr": 2,
-                    "f32_interleave": 4, "f64_interleave": 8}
+    assert (want["f32_kind"], want["f32_nr"], want["f32_interleave"]) == (1, 8, 1)
+    assert (want["f32_dag_kind"], want["f32_dag_nr"], want["f32_dag_interleave"]) == (4, 1, 2)
     for bad in (dict(f32_kind=4, f32_interleave=3), dict(f32_kind=4, f32_interleave=32),
                 dict(f32_kind=1, f32_nr=8, f32_interleave=2), dict(f64_kind=0, f64_interleave=2),
-                dict(f32_kind=4, f32_nr=16), dict(f64_kind=1, f64_nr=3)):
+                dict(f32_kind=4, f32_nr=16), dict(f64_kind=1, f64_nr=3),
+                dict(f32_dag_kind=4, f32_dag_nr=1, f32_dag_interleave=3),
+                dict(f32_dag_kind=1, f32_dag_nr=8, f32_dag_interleave=2), dict(f32_dag_kind=5, f32_dag_nr=1)):
         args = dict(f32_kind=4, f32_nr=1, f64_lgr=1, plane_band=1, f64_kind=1, f64_nr=2)
         args.update(bad)
         with pytest.raises(smpq.SmpqError):
             smpq.smpq_set_tuning(c, **args)
         assert smpq.smpq_get_tuning(c) == want, bad
-    smpq.smpq_set_tuning(c, 1, 8, 1)   # plane kernel, both interleaves back to 1
-    assert smpq.smpq_get_tuning(c)["f32_interleave"] == 1
+    smpq.smpq_set_tuning(c, 1, 8, 1)   # plane kernel for both directions, interleaves back to 1
+    t = smpq.smpq_get_tuning(c)
+    assert t["f32_interleave"] == t["f32_dag_interleave"] == 1 and t["f32_dag_kind"] == 1
     smpq.smpq_destroy(c)

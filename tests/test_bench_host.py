@@ -121,8 +121,8 @@ class StubBinding:
 
     def smpq_autotune(self, c, n):
         self._tick(20.0)
-        return {"f32_kind": 4, "f32_nr": 1, "f64_lgr": 0, "plane_band": 1, "f64_kind": 1, "f64_nr": 2,
-                "f32_interleave": 2, "f64_interleave": 2}
+        return {"f32_kind": 1, "f32_nr": 8, "f64_lgr": 0, "plane_band": 1, "f64_kind": 1, "f64_nr": 2,
+                "f32_interleave": 1, "f64_interleave": 2, "f32_dag_kind": 4, "f32_dag_nr": 1, "f32_dag_interleave": 2}
 
     def smpq_prepare(self, c):
         self._tick(2.0)
@@ -186,8 +186,9 @@ def test_driver_command_fits_its_time_limit(monkeypatch, capsys):
     assert line["accuracy"]["dQ_over"] == "whole map"
     assert line["value"] == 37.5 and line["roofline"]["bound"] == "hbm"
     sv = line["config"]["stencil_variants"]
-    assert sv["f32_kind"] == bench.F32_KINDS[4] and sv["f64_kind"] == "xy-tile" and sv["f64_rhs_per_block"] == 2
-    assert sv["f32_interleave"] == sv["f64_interleave"] == 2
+    assert sv["f32_kind"] == bench.F32_KINDS[1] and sv["f64_kind"] == "xy-tile" and sv["f64_rhs_per_block"] == 2
+    assert sv["f32_dag_kind"] == bench.F32_KINDS[4] and sv["f32_dag_rhs_per_thread"] == 1
+    assert sv["f32_dag_interleave"] == sv["f64_interleave"] == 2 and sv["f32_interleave"] == 1
     mixed_maps = [c for c in stub.calls if c[1] == 1 and c[2] == 256]
     assert len(mixed_maps) == line["steps"] + line["warmup"]
 

@@ -97,6 +97,11 @@ def test_dslash_parity_plane_tiled(dims, nrhs):
                 smpq.smpq_set_tuning(c, *tune, 1, 0, 4, il)
                 out32 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_MIXED_FP32)
                 assert np.abs(out32 - ref).max() <= 2e-6 * np.abs(ref).max(), (tune, il)
+        # D_W and D_W^dag on different variants: each direction runs its own
+        for d_w, d_dag in (((1, 8, 1), (4, 1, 2)), ((4, 1, 2), (3, 16, 1))):
+            smpq.smpq_set_tuning(c, d_w[0], d_w[1], 1, 1, 0, 4, d_w[2], 1, *d_dag)
+            out32 = smpq.smpq_apply_dw(c, psi, dagger=dag, precision=smpq.SMPQ_MIXED_FP32)
+            assert np.abs(out32 - ref).max() <= 2e-6 * np.abs(ref).max(), (d_w, d_dag)
         # the FP64 xy-tile kernel: here the tile is the whole 16x16 plane (no halo rows)
         for nr in F64_TILE_NR:
             for band, il in ((1, 1), (2, 1), (1, 2), (1, 8)):
@@ -121,6 +126,9 @@ def test_autotune_picks_a_valid_variant_and_keeps_parity():
     assert t["f64_lgr"] in (0, 1, 2) and t["plane_band"] in (1, 2)
     assert (t["f64_kind"], t["f64_nr"]) in [(0, t["f64_nr"])] + [(1, n) for n in F64_TILE_NR]
     assert t["f32_interleave"] in ((1, 2, 4, 8) if t["f32_kind"] == 4 else (1,))
+    assert (t["f32_dag_kind"], t["f32_dag_nr"]) in [(k, n) for k, n, _ in SITE_VARIANTS + PLANE_VARIANTS
+                                                    + TILE_VARIANTS + RL_VARIANTS]
+    assert t["f32_dag_interleave"] in ((1, 2, 4, 8) if t["f32_dag_kind"] == 4 else (1,))
     assert t["f64_interleave"] in ((1, 2, 4, 8) if t["f64_kind"] == 1 else (1,))
     ref = np.stack([apply_dw(U, lat, KAPPA, p) for p in psi])
     out32 = smpq.smpq_apply_dw(c, psi, precision=smpq.SMPQ_MIXED_FP32)
@@ -209,6 +217,23 @@ def test_qx_plane_tiled_mixed(dims, kind, band, il):
     smpq.smpq_set_solver(c, smpq.SMPQ_FP64, TOL, 5000, 0)
     q64 = smpq.smpq_compute_qx_classes(c, [5])[0]
     assert np.abs(q64 - ref.real).max() < 1e-10 * np.abs(ref.real).max()
+
+
+@pytest.mark.parametrize("d_w,d_dag", [((1, 8, 1), (4, 1, 2)), ((4, 1, 2), (3, 16, 1))])
+def test_qx_split_stencil_variants(d_w, d_dag):
+    """The first stencil of each CG iteration (D_W p with its partial sums) and the second (D_W^dag
+    with the residual update) on different variants, each with its own partial count: the mixed
+    q(x) of class 5 against the oracle."""
+    dims = (16, 16, 2, 2)
+    print(f"q(x) with D_W on {d_w} and D_W^dag on {d_dag}", flush=True)
+    U, lo, hi, ref = _tiled_qx_reference(dims)
+    c = _ctx(dims, U)
+    smpq.smpq_set_tuning(c, d_w[0], d_w[1], 1, 1, 0, 4, d_w[2], 1, *d_dag)
+    smpq.smpq_set_scheme(c, (2, 2, 2, 2), 0)
+    smpq.smpq_set_zolotarev(c, 14, lo, hi)
+    smpq.smpq_set_solver(c, smpq.SMPQ_MIXED_FP32, TOL, 5000, 50)
+    q32 = smpq.smpq_compute_qx_classes(c, [5])[0]
+    assert np.abs(q32 - ref.real).max() < 1e-5
 
 
 def test_dslash_gamma5_hermiticity_and_adjoint():
