@@ -638,7 +638,9 @@ BatchResult run_batch(smpq_ctx *c, int prec, int nslots, const Source &src, smpq
         iter += kGroup;
         if (mixed && c->reliable > 0 && iter % c->reliable == 0) {
             // residual replacement: fold the running base solution, r = b - (H^2 + s0) x0 in FP64
-            launch_fold(g, act, S.B, w.y.as<double2>(), w.yacc.p, w.x0.as<double2>(), w.x0acc.p, s);
+            // the running sum of y was folded at the end of the group (or is still zero before
+            // the first FP32-summed group), so only x0's is folded here
+            launch_fold(g, act, S.B, nullptr, nullptr, w.x0.as<double2>(), w.x0acc.p, s);
             launch_dslash(0, false, 0, c->U64.p, w.x0.p, rs64, 0, w.tmp64.p, rs64, nullptr, 0, 0, g,
                           c->kappa, 0.0, act, S.B, nullptr, s);
             launch_dslash(0, true, 1, c->U64.p, w.tmp64.p, rs64, 0, w.ap64.p, rs64, w.x0.p, rs64, 0, g,

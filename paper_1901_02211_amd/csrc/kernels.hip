@@ -769,8 +769,18 @@ __device__ __forceinline__ void tile_read(const float4 *tile, int tsites, int l,
     }
 }
 
+// Waves per SIMD the tile kernel is compiled for: the FP64 kernel with one right-hand side per
+// block needs 164-171 VGPRs, just above the 168 that three waves allow.  The solver's two
+// epilogues (3 and 2) fit 168 with at most two registers spilled and run the pair 9 % faster than
+// at two waves; the plain D_W and the +sigma epilogue would spill 5-10 and keep two waves, as do
+// all other instances.
+template <class T, int NR, int EPI>
+struct TileWaves {
+    static constexpr int min = std::is_same<T, double>::value && NR == 1 && (EPI == 2 || EPI == 3) ? 3 : 1;
+};
+
 template <class T, int NR, bool DAG, int EPI>
-__global__ __launch_bounds__(kBlock) void k_dslash_tile_rl(const typename Store<T>::link *__restrict__ U,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TileWaves<T, NR, EPI>::min, 8))) void k_dslash_tile_rl(const typename Store<T>::link *__restrict__ U,
                                                            const typename Store<T>::vec *__restrict__ in,
                                                            size_t in_stride, size_t in_extra,
                                                            typename Store<T>::vec *__restrict__ out, size_t out_stride,
@@ -1593,8 +1603,8 @@ void launch_shift_update(int prec, const Geom &g, const MSState &s, const void *
 #undef SMPQ_SU
 }
 
-// FP32 path: y += yacc, yacc = 0 (and x0 += x0acc, x0acc = 0 when x0acc is given), for the
-// listed slots, in FP64.
+// FP32 path: y += yacc, yacc = 0 when y is given, and x0 += x0acc, x0acc = 0 when x0acc is
+// given, for the listed slots, in FP64.
 __global__ __launch_bounds__(kBlock) void k_fold(Geom g, Slots sl, double2 *y, float4 *yacc, double2 *x0,
                                                  float4 *x0acc) {
     if ((int)blockIdx.y >= slot_count(sl)) return;
@@ -1606,12 +1616,15 @@ __global__ __launch_bounds__(kBlock) void k_fold(Geom g, Slots sl, double2 *y, f
     const size_t rs = 6 * g.vs, ys = 12 * g.vs;
     const cpx<float> z[2] = {{0.f, 0.f}, {0.f, 0.f}};
     cpx<float> a[2];
-    Unit<float>::load_stream(yacc + slot * rs, g.vs, u, s, a);
-    double2 *yp = y + slot * ys;
+    if (y) {
+        Unit<float>::load_stream(yacc + slot * rs, g.vs, u, s, a);
+        double2 *yp = y + slot * ys;
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-        st64_stream(yp, g.vs, 2 * u + j, s, ld64_stream(yp, g.vs, 2 * u + j, s) + cpx<double>{(double)a[j].re, (double)a[j].im});
-    Unit<float>::store_stream(yacc + slot * rs, g.vs, u, s, z);
+        for (int j = 0; j < 2; ++j)
+            st64_stream(yp, g.vs, 2 * u + j, s,
+                        ld64_stream(yp, g.vs, 2 * u + j, s) + cpx<double>{(double)a[j].re, (double)a[j].im});
+        Unit<float>::store_stream(yacc + slot * rs, g.vs, u, s, z);
+    }
     if (x0acc) {
         Unit<float>::load_stream(x0acc + slot * rs, g.vs, u, s, a);
         double2 *xp = x0 + slot * ys;

@@ -206,14 +206,18 @@ def test_qx_plane_tiled_mixed(dims, kind, band, il):
     print(f"q(x) of class 5 on {dims}, kind {kind}, band {band}, interleave {il}", flush=True)
     U, lo, hi, ref = _tiled_qx_reference(dims)
     c = _ctx(dims, U)
-    smpq.smpq_set_tuning(c, kind, 8, 1, band, 0, 4, il if kind == 4 else 1)
+    # with kind 4 the reliable updates' FP64 stencils run on the FP64 tile kernel with one
+    # right-hand side per block (the solver's pick at 16^3x32), else on the lane kernel
+    tile64 = kind == 4
+    smpq.smpq_set_tuning(c, kind, 8, 1, band, 1 if tile64 else 0, 1 if tile64 else 4, il if tile64 else 1,
+                         il if tile64 else 1)
     smpq.smpq_set_scheme(c, (2, 2, 2, 2), 0)
     smpq.smpq_set_zolotarev(c, 14, lo, hi)
     smpq.smpq_set_solver(c, smpq.SMPQ_MIXED_FP32, TOL, 5000, 50)
     q32 = smpq.smpq_compute_qx_classes(c, [5])[0]
     assert np.abs(q32 - ref.real).max() < 1e-5
     # the FP64 path with the FP64 xy-tile stencil (in the solver: both fused epilogues)
-    smpq.smpq_set_tuning(c, kind, 8, 1, band, 1, 4, il if kind == 4 else 1, il)
+    smpq.smpq_set_tuning(c, kind, 8, 1, band, 1, 1 if tile64 else 4, il if tile64 else 1, il)
     smpq.smpq_set_solver(c, smpq.SMPQ_FP64, TOL, 5000, 0)
     q64 = smpq.smpq_compute_qx_classes(c, [5])[0]
     assert np.abs(q64 - ref.real).max() < 1e-10 * np.abs(ref.real).max()
