@@ -2297,6 +2297,7 @@ smpq_status smpq_autotune(smpq_ctx *c, int n_rhs, smpq_tuning *chosen) {
             for (int bb : {2, 4})
                 if (per_band[bb].t3 + per_band[bb].t2 < per_band[band].t3 + per_band[band].t2) band = bb;
             const Best &b = per_band[band];
+            if (!std::isfinite(b.t3 + b.t2)) throw Fail{SMPQ_EDEVICE, "no FP32 stencil variant could be timed"};
             c->band = band;
             c->f32_kind = b.k3.kind;
             c->f32_nr = b.k3.nr;
