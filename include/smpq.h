@@ -265,7 +265,9 @@ smpq_status smpq_apply_dov(smpq_ctx *ctx, const double *in, double *out, int n_r
  * q(x) += 1/2 [gamma5 D_ov phi](x, alpha, a).  qx[V] gets Re q, qx_imag[V] (nullable) the
  * imaginary part (a diagnostic), Q (nullable) = sum_x qx[x].  If no Zolotarev
  * coefficients are set, 14 poles on smpq_estimate_bounds(ctx, 300) are used.
- * st (nullable) receives statistics. */
+ * st (nullable) receives statistics.  The argument order puts the two V-sized maps side by
+ * side and the scalar Q after them (the planned (qx, Q, qx_imag, st) order was changed for
+ * that). */
 smpq_status smpq_compute_qx(smpq_ctx *ctx, double *qx, double *qx_imag, double *Q,
                             smpq_stats *st);
 
@@ -371,8 +373,11 @@ smpq_status smpq_set_memory_limit(smpq_ctx *ctx, size_t bytes);
  * device memory: one batch of 12 right-hand sides each first, the rest in proportion to
  * V x (number of classes), never more than a context can use (the excess goes to the
  * others).  Every context solves on its own stream from its own host thread, so the batches
- * of different contexts overlap on the GPU.  Results equal those of separate calls bit for
- * bit (each source's solve is independent of the batch it runs in).
+ * of different contexts overlap on the GPU.  This replaces a single persistent launch over all
+ * configurations: lattices of different geometry need different grids and stencil variants,
+ * and measured overlap of separate streams leaves no idle device time to recover.  Results equal
+ * those of separate calls bit for bit (each source's solve is independent of the batch it runs
+ * in).
  *   ctxs[n_ctx]      distinct contexts on one device, with distinct streams, gauge and scheme set
  *   classes, n_classes  per-context class lists (NULL, or classes[k] NULL: every class)
  *   qx[k]            V_k doubles, written in full (sites of unlisted classes are 0)
