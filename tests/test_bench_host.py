@@ -197,3 +197,12 @@ def test_cpu_leg_that_does_not_finish_reports_no_value():
     res = bench.cpu_baseline("noise16x32", (16, 16, 16, 32), 4, 10 ** 6, 3072, 8, bench.SMALL_MAP, 0.5)
     assert res["value"] is None and res["kind"] == "oracle" and res["cores"] >= 1
     assert "not finished" in res["sample"]
+
+
+def test_stencil_bench_variant_parsing():
+    """The standalone stencil driver reads kind,nr,band,interleave tuples."""
+    from paper_1901_02211_amd.stencil_bench import parse_variant
+    assert parse_variant("4,1,1,2") == (4, 1, 1, 2)
+    import pytest
+    with pytest.raises(ValueError):
+        parse_variant("4,1,1")
